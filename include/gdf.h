@@ -1,0 +1,200 @@
+/*
+ * gdf.h — C ABI of the gradient-domain fusion library for MI355X (gfx950).
+ *
+ * The method (Kazhdan et al., "Gradient-Domain Fusion for Color Correction in
+ * Large EM Image Stacks", arXiv 1506.02079) corrects an EM image stack I0 in
+ * two steps:
+ *   1. anisotropic Gaussian smoothing across slices, I1 = I0 * G(sigma_xy,
+ *      sigma_z), with the kernel truncated at three standard deviations
+ *      (Section III-A; Implementation subsection);
+ *   2. per slice j, the screened-Poisson blend of Eq. (1):
+ *          (alpha - Laplacian) I2_j = alpha I1_j - Laplacian I0_j,
+ *      the minimiser of the energy of Section III-B.
+ *
+ * Discretisation used by every entry point: unit pixel spacing; the Laplacian
+ * is the 5-point graph Laplacian of the 4-connected pixel grid, so for
+ * Neumann boundaries (the energy's natural boundary condition) a pixel only
+ * couples to neighbours inside the slice.  The system solved per slice is
+ *          (alpha I + L) f = alpha g_s + L g_o,
+ * with g_s the smoothed slice (I1_j), g_o the original slice (I0_j), f = I2_j.
+ * The relative residual is ||b - A f||_2 / ||b||_2 with b = alpha g_s + L g_o
+ * (the definition the paper gives for its solver statistics), evaluated in
+ * FP64, per slice.
+ *
+ * Conventions shared by all entry points
+ *  - Pointers named *_dev are device (HBM) pointers owned by the caller; the
+ *    library never frees or retains them past the call.  Host pointers are
+ *    named *_host.
+ *  - Images are row-major, x (width) fastest.  Element strides are given in
+ *    elements of the buffer's own type.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  All device work is enqueued on it.  Every entry point returns
+ *    after the solve has finished on the device (convergence is decided on
+ *    the host between V-cycles, or at the end of a captured graph), so
+ *    outputs are ready when it returns.
+ *  - `workspace_dev` is caller-allocated device memory of at least the size
+ *    returned by the matching *_workspace_size call for the same arguments,
+ *    aligned to 256 bytes.  The library allocates no device memory of its own
+ *    apart from a small per-device cache of captured graphs (gdf_release).
+ *  - Argument checks run on the host before any device work and return
+ *    GDF_EINVAL (with gdf_last_error() describing the argument).  No C++
+ *    exception crosses this interface.
+ *  - GDF_ENOCONV / GDF_ENONFINITE: outputs are still written; per-slice
+ *    status is in the report.
+ */
+#ifndef GDF_H
+#define GDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GDF_OK = 0,
+    GDF_EINVAL = 1,        /* invalid argument (message in gdf_last_error) */
+    GDF_EUNSUPPORTED = 2,  /* valid but unsupported combination (e.g. Dirichlet) */
+    GDF_ENOMEM = 3,        /* workspace smaller than required */
+    GDF_EDEVICE = 4,       /* HIP runtime error (message in gdf_last_error) */
+    GDF_ENOCONV = 5,       /* some slice did not reach tol within max_vcycles */
+    GDF_ENONFINITE = 6     /* some slice produced a NaN/Inf residual */
+} gdf_status;
+
+typedef enum {
+    GDF_BC_NEUMANN = 0,    /* reflecting edges: the energy's natural boundary condition */
+    GDF_BC_PERIODIC = 1,   /* wrap-around (the paper's Fourier basis); not implemented on the GPU */
+    GDF_BC_DIRICHLET = 2   /* boundary values are not specified by the method: GDF_EUNSUPPORTED */
+} gdf_bc;
+
+typedef enum { GDF_U8 = 0, GDF_F32 = 1, GDF_F64 = 2 } gdf_dtype;
+
+typedef enum {
+    GDF_PREC_FP32 = 0,     /* FP32 V-cycles on u = f - g_o; FP64 residual norms */
+    GDF_PREC_FP64 = 1,     /* FP64 throughout */
+    GDF_PREC_MIXED = 2     /* FP32 V-cycles inside FP64 iterative refinement */
+} gdf_precision;
+
+/* Solver options.  Zero-initialise and set what you need; 0 selects the
+ * default noted for each field. */
+typedef struct {
+    int precision;     /* gdf_precision (default GDF_PREC_FP32) */
+    int max_vcycles;   /* cap on V-cycles per slice (default 40; for MIXED: total inner cycles) */
+    int nu;            /* red-black Gauss-Seidel sweeps before and after each coarse
+                          correction: 1 or 2 (default 2) */
+    int out_dtype;     /* GDF_F32 or GDF_F64 for f; 0 = F32 for FP32, F64 otherwise */
+    int use_graph;     /* 1: record the whole V-cycle schedule once as a hipGraph and
+                          replay it, with per-slice convergence flags on the device */
+    int tile_rows;     /* rows per strip work item (even, >= 16); 0 = tuned default */
+    int inner_cycles;  /* MIXED: FP32 V-cycles per refinement step (default 3) */
+    int reserved[9];
+} gdf_solve_opts;
+
+/* Per-slice outcome (host memory, filled when a report pointer is given). */
+typedef struct {
+    int vcycles;                /* coarse-grid corrections applied */
+    int status;                 /* gdf_status of this slice */
+    double rel_residual;        /* FP64 ||b - A f|| / ||b|| of the returned f (before
+                                   rounding to out_dtype) */
+    double rel_residual_init;   /* the same for f = g_o (the zero correction) */
+} gdf_slice_report;
+
+/* One slice of a batch (host memory).  Offsets and row pitches are in
+ * elements of the buffer they index. */
+typedef struct {
+    int H, W;                   /* slice height and width, >= 1 */
+    double alpha;               /* screening weight of Eq. (1), > 0 */
+    long long off_gs, pitch_gs; /* g_s (smoothed slice) */
+    long long off_go, pitch_go; /* g_o (original slice) */
+    long long off_f, pitch_f;   /* f (output); also grad_f / grad_gs / grad_go in the backward */
+} gdf_slice_desc;
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *gdf_last_error(void);
+
+/* Library version string. */
+const char *gdf_version(void);
+
+/* Releases the per-device graph cache.  Safe to call at any time when no
+ * other call is running. */
+void gdf_release(void);
+
+/* ------------------------------------------------------------------------ */
+/* fuse_stack: the whole method on a uint8 stack (Section III-A then Eq. (1)).
+ *
+ * stack_dev      uint8 [S][H][W] at element strides (pitch_slice, pitch_row).
+ * alpha          screening weight, > 0 and finite.
+ * bc             gdf_bc; only GDF_BC_NEUMANN runs on the GPU.
+ * tol            target relative residual per slice, in (0, 1).
+ * sigma_xy/z     Gaussian widths in pixels/slices, >= 0; 0 disables that axis.
+ *                The kernel is truncated at floor(3 sigma) taps per axis and
+ *                renormalised over the taps inside the stack.
+ * f_dev          output [S][H][W] contiguous, dtype opts.out_dtype.
+ * g_smooth_dev   optional output [S][H][W] contiguous (NULL to skip): I1 in
+ *                FP32 (FP64 when precision is GDF_PREC_FP64).
+ * report_host    optional [S] per-slice report.
+ * Returns GDF_OK when every slice reached tol.                              */
+size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts);
+
+gdf_status fuse_stack(const uint8_t *stack_dev, int S, int H, int W, long long pitch_row,
+                      long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
+                      double sigma_z, void *f_dev, void *g_smooth_dev, const gdf_solve_opts *opts,
+                      void *workspace_dev, size_t workspace_bytes, gdf_slice_report *report_host,
+                      void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* solve_slices: Eq. (1) for a batch of slices of possibly different sizes and
+ * screening weights, from caller-supplied g_s and g_o.
+ *
+ * desc_host      [n] slice descriptors (sizes, alpha, offsets, pitches).
+ * gs_dtype/gs    g_s buffer: GDF_F32 or GDF_F64.
+ * go_dtype/go    g_o buffer: GDF_U8, GDF_F32 or GDF_F64.
+ * f_dev          output buffer, dtype opts.out_dtype.
+ * Uneven batches run as one work list per multigrid level; with
+ * opts.use_graph the schedule is captured once and replayed.               */
+size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *desc_host, const gdf_solve_opts *opts);
+
+gdf_status solve_slices(int n, const gdf_slice_desc *desc_host, int gs_dtype, const void *gs_dev,
+                        int go_dtype, const void *go_dev, int bc, double tol, void *f_dev,
+                        const gdf_solve_opts *opts, void *workspace_dev, size_t workspace_bytes,
+                        gdf_slice_report *report_host, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* solve_slices_backward: gradients of a scalar loss through Eq. (1).
+ *
+ * Given grad_f = dLoss/df, solves the adjoint system A lambda = grad_f (A is
+ * symmetric, so the same multigrid solver is reused) and forms
+ *     dLoss/dg_s = alpha lambda,  dLoss/dg_o = L lambda,
+ *     dLoss/dalpha_j = lambda_j . (g_s,j - f_j)   (FP64 sum per slice).
+ * dtype (GDF_F32 or GDF_F64) applies to grad_f, f, g_s and the gradient
+ * outputs.  grad_f, f, grad_gs and grad_go use (off_f, pitch_f) of each
+ * descriptor; g_s uses (off_gs, pitch_gs).  grad_gs_dev, grad_go_dev and
+ * grad_alpha_host may each be NULL.                                          */
+size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *desc_host,
+                                   const gdf_solve_opts *opts);
+
+gdf_status solve_slices_backward(int n, const gdf_slice_desc *desc_host, int dtype,
+                                 const void *grad_f_dev, const void *f_dev, const void *gs_dev,
+                                 int bc, double tol, void *grad_gs_dev, void *grad_go_dev,
+                                 double *grad_alpha_host, const gdf_solve_opts *opts,
+                                 void *workspace_dev, size_t workspace_bytes,
+                                 gdf_slice_report *report_host, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing for measurement.  When enabled, the library brackets every
+ * launch of the named kernel class with HIP events on the launch stream and
+ * accumulates their durations.  Classes: "smooth", "vcycle_fine" (the fused
+ * finest-level post-/pre-smoothing pass), "restrict_first", "coarse",
+ * "finalize", "prep", "refine", "adjoint".  Returns the number of launches
+ * recorded and writes the summed milliseconds and the summed algorithmic
+ * HBM bytes.                                                                 */
+void gdf_profile_enable(int on);
+int gdf_profile_read(const char *kernel_class, double *total_ms_host, double *algo_bytes_host);
+void gdf_profile_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDF_H */

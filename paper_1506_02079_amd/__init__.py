@@ -1,0 +1,402 @@
+"""Gradient-domain fusion of EM image stacks on MI355X (gfx950).
+
+Python binding of ``libgdf.so`` (C ABI in ``include/gdf.h``).  This module
+only marshals arguments: torch tensors provide device memory and the current
+HIP stream; every step of the method runs in the library's HIP kernels.  If
+the library is not built, calls raise immediately -- there is no CPU path.
+
+Method (Kazhdan et al., arXiv 1506.02079): smooth the stack across slices
+with an anisotropic Gaussian (Section III-A), then solve per slice the
+screened-Poisson blend of Eq. (1), (alpha - Laplacian) f = alpha g_s -
+Laplacian g_o, to a relative residual tolerance.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgdf.so")
+
+GDF_OK, GDF_EINVAL, GDF_EUNSUPPORTED, GDF_ENOMEM, GDF_EDEVICE, GDF_ENOCONV, GDF_ENONFINITE = range(7)
+STATUS_NAMES = {0: "GDF_OK", 1: "GDF_EINVAL", 2: "GDF_EUNSUPPORTED", 3: "GDF_ENOMEM",
+                4: "GDF_EDEVICE", 5: "GDF_ENOCONV", 6: "GDF_ENONFINITE"}
+BC = {"neumann": 0, "periodic": 1, "dirichlet": 2}
+DTYPE_U8, DTYPE_F32, DTYPE_F64 = 0, 1, 2
+PRECISION = {"fp32": 0, "fp64": 1, "mixed": 2}
+
+
+class GdfError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("max_vcycles", ctypes.c_int), ("nu", ctypes.c_int),
+                ("out_dtype", ctypes.c_int), ("use_graph", ctypes.c_int),
+                ("tile_rows", ctypes.c_int), ("inner_cycles", ctypes.c_int),
+                ("reserved", ctypes.c_int * 9)]
+
+
+class SliceReport(ctypes.Structure):
+    _fields_ = [("vcycles", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("rel_residual_init", ctypes.c_double)]
+
+
+class SliceDesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("off_gs", ctypes.c_longlong), ("pitch_gs", ctypes.c_longlong),
+                ("off_go", ctypes.c_longlong), ("pitch_go", ctypes.c_longlong),
+                ("off_f", ctypes.c_longlong), ("pitch_f", ctypes.c_longlong)]
+
+
+_lib = None
+
+# exported symbols, with their ctypes signatures
+_P, _I, _D, _L, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, ctypes.c_size_t
+SIGNATURES = {
+    "gdf_last_error": ([], ctypes.c_char_p),
+    "gdf_version": ([], ctypes.c_char_p),
+    "gdf_release": ([], None),
+    "gdf_profile_enable": ([_I], None),
+    "gdf_profile_reset": ([], None),
+    "gdf_profile_read": ([ctypes.c_char_p, ctypes.POINTER(_D), ctypes.POINTER(_D)], _I),
+    "gdf_fuse_workspace_size": ([_I, _I, _I, ctypes.POINTER(SolveOpts)], _S),
+    "fuse_stack": ([_P, _I, _I, _I, _L, _L, _D, _I, _D, _D, _D, _P, _P, ctypes.POINTER(SolveOpts),
+                    _P, _S, ctypes.POINTER(SliceReport), _P], _I),
+    "gdf_solve_workspace_size": ([_I, ctypes.POINTER(SliceDesc), ctypes.POINTER(SolveOpts)], _S),
+    "solve_slices": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _I, _P, _I, _D, _P,
+                      ctypes.POINTER(SolveOpts), _P, _S, ctypes.POINTER(SliceReport), _P], _I),
+    "gdf_backward_workspace_size": ([_I, ctypes.POINTER(SliceDesc), ctypes.POINTER(SolveOpts)], _S),
+    "solve_slices_backward": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _P, _P, _I, _D, _P, _P,
+                               ctypes.POINTER(_D), ctypes.POINTER(SolveOpts), _P, _S,
+                               ctypes.POINTER(SliceReport), _P], _I),
+}
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgdf.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().gdf_last_error().decode()
+
+
+def version() -> str:
+    return lib().gdf_version().decode()
+
+
+def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=False,
+              tile_rows=0, inner_cycles=0) -> SolveOpts:
+    o = SolveOpts()
+    o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    o.max_vcycles = int(max_vcycles)
+    o.nu = int(nu)
+    o.out_dtype = 0 if out_dtype is None else int(out_dtype)
+    o.use_graph = int(bool(use_graph))
+    o.tile_rows = int(tile_rows)
+    o.inner_cycles = int(inner_cycles)
+    return o
+
+
+def _check(status, allow_noconv=False):
+    if status == GDF_OK or (allow_noconv and status in (GDF_ENOCONV, GDF_ENONFINITE)):
+        return
+    raise GdfError(status, last_error())
+
+
+def _report_list(rep, n):
+    return [dict(vcycles=rep[i].vcycles, status=rep[i].status, rel_residual=rep[i].rel_residual,
+                 rel_residual_init=rep[i].rel_residual_init) for i in range(n)]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(dev):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+_SIDE = {}
+
+
+def _side_stream(dev):
+    torch = _torch()
+    key = str(dev)
+    if key not in _SIDE:
+        _SIDE[key] = torch.cuda.Stream(device=dev)   # default priority
+    return _SIDE[key]
+
+
+def _dtype_code(t):
+    torch = _torch()
+    return {torch.uint8: DTYPE_U8, torch.float32: DTYPE_F32, torch.float64: DTYPE_F64}[t.dtype]
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if not t.is_cuda:
+            raise ValueError("tensors must live on the GPU (got %s)" % t.device)
+
+
+# ------------------------------------------------------------------ fuse_stack
+
+def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
+               precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
+               tile_rows=0, inner_cycles=0, allow_noconv=False):
+    """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
+
+    Returns (f, report) or (f, report, g_smooth) with return_smooth=True.
+    f has dtype float32 (fp32) or float64 (fp64 / mixed) unless out_dtype is given.
+    """
+    torch = _torch()
+    _require_cuda(stack)
+    if stack.dtype != torch.uint8 or stack.dim() != 3:
+        raise ValueError("stack must be a uint8 tensor [S, H, W]")
+    if stack.stride(2) != 1:
+        stack = stack.contiguous()
+    S, H, W = stack.shape
+    o = make_opts(precision, max_vcycles, nu, out_dtype, False, tile_rows, inner_cycles)
+    L = lib()
+    ws = L.gdf_fuse_workspace_size(S, H, W, ctypes.byref(o))
+    if ws == 0:
+        raise GdfError(GDF_EINVAL, last_error())
+    od = o.out_dtype or (DTYPE_F32 if o.precision == 0 else DTYPE_F64)
+    f = torch.empty((S, H, W), dtype=torch.float64 if od == DTYPE_F64 else torch.float32,
+                    device=stack.device)
+    gsm = None
+    if return_smooth:
+        gsm = torch.empty((S, H, W), dtype=torch.float64 if o.precision == 1 else torch.float32,
+                          device=stack.device)
+    work = torch.empty(ws, dtype=torch.uint8, device=stack.device)
+    rep = (SliceReport * S)()
+    st = L.fuse_stack(stack.data_ptr(), S, H, W, stack.stride(1), stack.stride(0), float(alpha),
+                      BC[bc], float(tol), float(sigma_xy), float(sigma_z), f.data_ptr(),
+                      gsm.data_ptr() if gsm is not None else None, ctypes.byref(o),
+                      work.data_ptr(), ws, rep, _stream(stack.device))
+    _check(st, allow_noconv)
+    out = (f, _report_list(rep, S))
+    return out + (gsm,) if return_smooth else out
+
+
+# ---------------------------------------------------------------- solve_slices
+
+def _descs(gs_list, go_list, f_list, alphas):
+    """Slice descriptors for lists of 2D tensors, offsets from each list's lowest address."""
+    n = len(gs_list)
+    d = (SliceDesc * n)()
+    bases = []
+    for lst in (gs_list, go_list, f_list):
+        base = min(t.data_ptr() for t in lst)
+        bases.append(base)
+    for i in range(n):
+        H, W = gs_list[i].shape
+        d[i].H, d[i].W, d[i].alpha = H, W, float(alphas[i])
+        for k, (lst, name) in enumerate(((gs_list, "gs"), (go_list, "go"), (f_list, "f"))):
+            t = lst[i]
+            if t.stride(1) != 1:
+                raise ValueError("slices must have unit column stride")
+            diff = t.data_ptr() - bases[k]
+            if diff % t.element_size():
+                raise ValueError("misaligned slice buffer")
+            setattr(d[i], "off_" + name, diff // t.element_size())
+            setattr(d[i], "pitch_" + name, t.stride(0))
+    return d, bases
+
+
+def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_dtype=None,
+                 nu=0, max_vcycles=0, use_graph=False, tile_rows=0, inner_cycles=0,
+                 allow_noconv=False):
+    """Eq. (1) per slice.  g_s, g_o: [S, H, W] tensors or lists of 2D tensors
+    (uneven batch).  alpha: scalar or per-slice sequence.  Returns (f, report)
+    with f shaped like the input (a list for list input)."""
+    torch = _torch()
+    as_list = isinstance(g_s, (list, tuple))
+    gs_list = list(g_s) if as_list else list(g_s.unbind(0))
+    go_list = list(g_o) if as_list else list(g_o.unbind(0))
+    n = len(gs_list)
+    if len(go_list) != n:
+        raise ValueError("g_s and g_o must have the same number of slices")
+    if not as_list and g_s.shape != g_o.shape:
+        raise ValueError("g_s and g_o shapes differ")
+    for a, b in zip(gs_list, go_list):
+        if a.shape != b.shape or a.dim() != 2:
+            raise ValueError("each slice pair must be 2D with equal shapes")
+    _require_cuda(*gs_list, *go_list)
+    gdt = {gs_list[0].dtype}
+    if len({t.dtype for t in gs_list}) != 1 or len({t.dtype for t in go_list}) != 1:
+        raise ValueError("all g_s slices (and all g_o slices) must share a dtype")
+    alphas = [float(alpha)] * n if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
+    o = make_opts(precision, max_vcycles, nu, out_dtype, use_graph, tile_rows, inner_cycles)
+    od = o.out_dtype or (DTYPE_F32 if o.precision == 0 else DTYPE_F64)
+    fdt = torch.float64 if od == DTYPE_F64 else torch.float32
+    dev = gs_list[0].device
+    if as_list:
+        tot = sum(t.numel() for t in gs_list)
+        flat = torch.empty(tot, dtype=fdt, device=dev)
+        f_list, off = [], 0
+        for t in gs_list:
+            f_list.append(flat[off:off + t.numel()].view(t.shape))
+            off += t.numel()
+    else:
+        f_all = torch.empty(g_s.shape, dtype=fdt, device=dev)
+        f_list = list(f_all.unbind(0))
+    d, bases = _descs(gs_list, go_list, f_list, alphas)
+    L = lib()
+    ws = L.gdf_solve_workspace_size(n, d, ctypes.byref(o))
+    if ws == 0:
+        raise GdfError(GDF_EINVAL, last_error())
+    work = torch.empty(ws, dtype=torch.uint8, device=dev)
+    rep = (SliceReport * n)()
+    if use_graph:
+        # stream capture needs a non-default stream: run on a side stream that
+        # is ordered after the caller's current stream and joined back after
+        cur = torch.cuda.current_stream(dev)
+        side = _side_stream(dev)
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            st = L.solve_slices(n, d, _dtype_code(gs_list[0]), bases[0], _dtype_code(go_list[0]),
+                                bases[1], BC[bc], float(tol), bases[2], ctypes.byref(o),
+                                work.data_ptr(), ws, rep, _stream(dev))
+        cur.wait_stream(side)
+        for t in (work, *gs_list, *go_list, *f_list):
+            t.record_stream(side)
+    else:
+        st = L.solve_slices(n, d, _dtype_code(gs_list[0]), bases[0], _dtype_code(go_list[0]),
+                            bases[1], BC[bc], float(tol), bases[2], ctypes.byref(o),
+                            work.data_ptr(), ws, rep, _stream(dev))
+    _check(st, allow_noconv)
+    del gdt
+    return (f_list if as_list else f_all), _report_list(rep, n)
+
+
+def solve_slices_backward(grad_f, f, g_s, alpha, bc="neumann", tol=1e-6, precision=None, nu=0,
+                          max_vcycles=0, need=(True, True, True), allow_noconv=False):
+    """Adjoint of Eq. (1): returns (dL/dg_s, dL/dg_o, dL/dalpha per slice, report)
+    for grad_f = dL/df.  Tensors are [S, H, W] of one float dtype."""
+    torch = _torch()
+    _require_cuda(grad_f, f, g_s)
+    if not (grad_f.shape == f.shape == g_s.shape) or grad_f.dim() != 3:
+        raise ValueError("grad_f, f and g_s must be [S, H, W] of equal shapes")
+    dt = grad_f.dtype
+    if f.dtype != dt or g_s.dtype != dt or dt not in (torch.float32, torch.float64):
+        raise ValueError("grad_f, f and g_s must share float32 or float64 dtype")
+    grad_f, f, g_s = grad_f.contiguous(), f.contiguous(), g_s.contiguous()
+    S, H, W = grad_f.shape
+    prec = precision or ("fp64" if dt == torch.float64 else "fp32")
+    alphas = [float(alpha)] * S if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
+    d = (SliceDesc * S)()
+    for i in range(S):
+        d[i].H, d[i].W, d[i].alpha = H, W, alphas[i]
+        d[i].off_gs = d[i].off_go = d[i].off_f = i * H * W
+        d[i].pitch_gs = d[i].pitch_go = d[i].pitch_f = W
+    o = make_opts(prec, max_vcycles, nu)
+    L = lib()
+    ws = L.gdf_backward_workspace_size(S, d, ctypes.byref(o))
+    if ws == 0:
+        raise GdfError(GDF_EINVAL, last_error())
+    work = torch.empty(ws, dtype=torch.uint8, device=grad_f.device)
+    ggs = torch.empty_like(grad_f) if need[0] else None
+    ggo = torch.empty_like(grad_f) if need[1] else None
+    ga = (ctypes.c_double * S)()
+    rep = (SliceReport * S)()
+    st = L.solve_slices_backward(S, d, _dtype_code(grad_f), grad_f.data_ptr(), f.data_ptr(),
+                                 g_s.data_ptr(), BC[bc], float(tol),
+                                 ggs.data_ptr() if ggs is not None else None,
+                                 ggo.data_ptr() if ggo is not None else None,
+                                 ga if need[2] else None, ctypes.byref(o), work.data_ptr(), ws, rep,
+                                 _stream(grad_f.device))
+    _check(st, allow_noconv)
+    galpha = torch.tensor([ga[i] for i in range(S)], dtype=torch.float64) if need[2] else None
+    return ggs, ggo, galpha, _report_list(rep, S)
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class ScreenedPoissonSolve(torch.autograd.Function):
+        """f = solve of Eq. (1) per slice, differentiable in g_s, g_o and alpha.
+
+        apply(g_s, g_o, alpha, tol=1e-6): g_s, g_o float tensors [S, H, W] on the
+        GPU (same dtype; float64 runs the FP64 solver); alpha a scalar tensor
+        (shared by all slices) or a 1D tensor of per-slice weights.
+        """
+
+        @staticmethod
+        def forward(ctx, g_s, g_o, alpha, tol=1e-6):
+            prec = "fp64" if g_s.dtype == torch.float64 else "fp32"
+            a = alpha.detach().double().cpu()
+            al = a.tolist() if a.dim() else float(a)
+            f, _ = solve_slices(g_s.detach(), g_o.detach(), al, tol=tol, precision=prec,
+                                out_dtype=DTYPE_F64 if prec == "fp64" else DTYPE_F32)
+            ctx.save_for_backward(g_s, f, alpha)
+            ctx.al = al
+            ctx.tol = tol
+            return f
+
+        @staticmethod
+        def backward(ctx, grad_f):
+            g_s, f, alpha = ctx.saved_tensors
+            need = ctx.needs_input_grad
+            ggs, ggo, ga, _ = solve_slices_backward(grad_f.contiguous().to(f.dtype), f, g_s.detach(),
+                                                    ctx.al, tol=ctx.tol,
+                                                    need=(need[0], need[1], need[2]))
+            galpha = None
+            if need[2]:
+                galpha = ga.sum() if alpha.dim() == 0 else ga
+                galpha = galpha.to(dtype=alpha.dtype, device=alpha.device)
+            return ggs, ggo, galpha, None
+
+    return ScreenedPoissonSolve
+
+
+class _Lazy:
+    _cls = None
+
+    def __get__(self, obj, owner):
+        if _Lazy._cls is None:
+            _Lazy._cls = _make_autograd()
+        return _Lazy._cls
+
+
+class _Namespace:
+    ScreenedPoissonSolve = _Lazy()
+
+
+def __getattr__(name):
+    if name == "ScreenedPoissonSolve":
+        return _Namespace.ScreenedPoissonSolve
+    raise AttributeError(name)
+
+
+# ------------------------------------------------------------------ profiling
+
+def profile_enable(on=True):
+    lib().gdf_profile_enable(int(bool(on)))
+
+
+def profile_reset():
+    lib().gdf_profile_reset()
+
+
+def profile_read(kernel_class):
+    """(launches, total_ms, algorithmic_bytes) recorded for a kernel class."""
+    ms = ctypes.c_double(0.0)
+    by = ctypes.c_double(0.0)
+    n = lib().gdf_profile_read(kernel_class.encode(), ctypes.byref(ms), ctypes.byref(by))
+    return n, ms.value, by.value

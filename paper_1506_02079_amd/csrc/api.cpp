@@ -1,0 +1,1154 @@
+// Host side of the gradient-domain fusion library: argument validation, the
+// per-slice multigrid hierarchy, the work lists, the V-cycle schedule and the
+// C entry points declared in include/gdf.h.
+//
+// Method (arXiv 1506.02079): anisotropic smoothing across slices (Section
+// III-A), then per slice the screened-Poisson blend of Eq. (1).  The solve is
+// a multigrid V-cycle iteration on the correction u = f - g_o:
+//   level 0 is the pixel grid; level l + 1 halves each side (ceil) and carries
+//   sigma_{l+1} = 4 sigma_l; coarsening stops once sigma_l >= 2 (the screened
+//   operator is then diagonally dominant enough for a few red-black sweeps to
+//   solve it) or the grid is a single pixel.
+//   Cycle k (k >= 1): restrict down through the coarse levels (2nu sweeps,
+//   residual, restriction), 6 sweeps on the coarsest level, back up
+//   (prolongation, 2nu sweeps), then one fused pass on level 0: prolongate,
+//   nu post-sweeps of cycle k, nu pre-sweeps of cycle k + 1, residual (its
+//   norm is the convergence test), restriction.
+// The paper's own solver (the out-of-core streaming multigrid of Kazhdan et
+// al. 2010, Implementation subsection) is prior art for a disk-bound CPU; this
+// schedule keeps each slice resident in HBM and fuses sweeps instead.
+#include "gdf.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace gdf;
+
+namespace {
+
+thread_local std::string g_err;
+
+gdf_status set_err(gdf_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return set_err(GDF_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                           __LINE__);                                                          \
+    } while (0)
+
+constexpr double kSigmaStop = 2.0;
+constexpr int kCoarsePasses = 3;   // x 2 sweeps on the coarsest level
+constexpr int kTileW = 64, kTileH = 16;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------------ options
+
+struct Opts {
+    int prec, max_vc, nu, out_dtype, use_graph, tile_rows, inner;
+};
+
+gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
+{
+    gdf_solve_opts z;
+    std::memset(&z, 0, sizeof z);
+    if (!o) o = &z;
+    r.prec = o->precision;
+    if (r.prec < GDF_PREC_FP32 || r.prec > GDF_PREC_MIXED)
+        return set_err(GDF_EINVAL, "opts.precision must be GDF_PREC_FP32, _FP64 or _MIXED (got %d)", r.prec);
+    r.max_vc = o->max_vcycles ? o->max_vcycles : 40;
+    if (r.max_vc < 1 || r.max_vc > 100000)
+        return set_err(GDF_EINVAL, "opts.max_vcycles must be in [1, 100000] (got %d)", r.max_vc);
+    r.nu = o->nu ? o->nu : 2;
+    if (r.nu != 1 && r.nu != 2) return set_err(GDF_EINVAL, "opts.nu must be 1 or 2 (got %d)", r.nu);
+    r.out_dtype = o->out_dtype ? o->out_dtype : (r.prec == GDF_PREC_FP32 ? GDF_F32 : GDF_F64);
+    if (r.out_dtype != GDF_F32 && r.out_dtype != GDF_F64)
+        return set_err(GDF_EINVAL, "opts.out_dtype must be GDF_F32 or GDF_F64 (got %d)", r.out_dtype);
+    r.use_graph = o->use_graph != 0;
+    r.tile_rows = o->tile_rows;
+    if (r.tile_rows && (r.tile_rows < 16 || (r.tile_rows & 1) || r.tile_rows > 65536))
+        return set_err(GDF_EINVAL, "opts.tile_rows must be 0 or an even number in [16, 65536] (got %d)", r.tile_rows);
+    r.inner = o->inner_cycles ? o->inner_cycles : 3;
+    if (r.inner < 1 || r.inner > 64)
+        return set_err(GDF_EINVAL, "opts.inner_cycles must be in [1, 64] (got %d)", r.inner);
+    return GDF_OK;
+}
+
+gdf_status check_common(int bc, double tol)
+{
+    if (bc == GDF_BC_PERIODIC)
+        return set_err(GDF_EUNSUPPORTED, "periodic boundaries are not implemented on the GPU path");
+    if (bc == GDF_BC_DIRICHLET)
+        return set_err(GDF_EUNSUPPORTED, "Dirichlet boundaries need boundary values the method does not define");
+    if (bc != GDF_BC_NEUMANN) return set_err(GDF_EINVAL, "unknown boundary condition %d", bc);
+    if (!(tol > 0.0 && tol < 1.0)) return set_err(GDF_EINVAL, "tol must be in (0, 1) (got %g)", tol);
+    return GDF_OK;
+}
+
+// ------------------------------------------------------------------- plan
+
+struct SliceGeom {
+    int H, W;
+    double alpha;
+    int nlev;
+    int h[kMaxLevels], w[kMaxLevels], pitch[kMaxLevels];
+    double sigma[kMaxLevels];
+    double wxL[kMaxLevels], wyL[kMaxLevels];   // last column / row size relative to a full cell
+    size_t off_u[kMaxLevels][2], off_b[kMaxLevels];
+    size_t off_u64[2];
+};
+
+int level_pitch(int W)
+{
+    const int p = (W & 1) ? W + 1 : W;
+    return (p + 63) / 64 * 64;
+}
+
+void build_levels(SliceGeom &g)
+{
+    g.h[0] = g.H;
+    g.w[0] = g.W;
+    g.sigma[0] = g.alpha;
+    int l = 0;
+    while (l + 1 < kMaxLevels && g.sigma[l] < kSigmaStop && (g.h[l] > 1 || g.w[l] > 1)) {
+        g.h[l + 1] = (g.h[l] + 1) / 2;
+        g.w[l + 1] = (g.w[l] + 1) / 2;
+        g.sigma[l + 1] = 4.0 * g.sigma[l];
+        ++l;
+    }
+    g.nlev = l + 1;
+    for (int i = 0; i < g.nlev; ++i) g.pitch[i] = level_pitch(g.w[i]);
+    // extent of the last cell in pixels: a coarse cell takes two children, or
+    // one when the finer side is odd; only the last cell can be partial
+    double lx = 1.0, ly = 1.0, side = 1.0;
+    g.wxL[0] = g.wyL[0] = 1.0;
+    for (int i = 1; i < g.nlev; ++i) {
+        lx = (g.w[i - 1] & 1) ? lx : side + lx;
+        ly = (g.h[i - 1] & 1) ? ly : side + ly;
+        side *= 2.0;
+        g.wxL[i] = lx / side;
+        g.wyL[i] = ly / side;
+    }
+}
+
+struct List {
+    StripKind kind;
+    int level;
+    int off, count;
+    int G, VW, TH;
+};
+
+enum ProfClass { PC_SMOOTH, PC_FINE, PC_FIRST, PC_COARSE, PC_FINALIZE, PC_PREP, PC_REFINE, PC_ADJOINT, PC_COUNT };
+const char *kProfNames[PC_COUNT] = {"smooth", "vcycle_fine", "restrict_first", "coarse",
+                                    "finalize", "prep", "refine", "adjoint"};
+
+struct Plan {
+    Opts o;
+    bool fp64;       // hierarchy element type
+    int esz;
+    int n;
+    std::vector<SliceGeom> g;
+    std::vector<int> desc_base;
+    std::vector<LevelDesc> descs;
+    std::vector<Item> items;
+    std::vector<List> lists;
+    int list_first = -1, list_fine = -1, list_single = -1;
+    int list_down[kMaxLevels], list_up[kMaxLevels], list_coarse[kMaxLevels];
+    int max_level = 0;
+    std::vector<int> ranges_first, ranges_cycle, ranges_tiles, ranges_smooth;
+    int n_norm;
+    std::vector<SliceIO> io;
+    long long n_tiles = 0;
+    long long n_partd = 0;
+    bool mixed = false;
+    bool need_gs_copy = false;   // fuse_stack MIXED without g_smooth output
+    // layout (bytes from the workspace base)
+    size_t off_tables, tables_bytes;
+    size_t off_state, off_active, off_desc, off_items, off_r_first, off_r_cycle, off_r_tiles,
+        off_r_smooth, off_io, off_u64tab;
+    size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
+};
+
+int choose_rows(const Plan &P, const std::vector<int> &slices, int level, int VW)
+{
+    if (level == 0 && P.o.tile_rows) return P.o.tile_rows;
+    long long rows = 0;
+    for (int s : slices) {
+        const SliceGeom &g = P.g[s];
+        rows += (long long)g.h[level] * ((g.w[level] + VW - 1) / VW);
+    }
+    long long th = rows / 6144;
+    th = std::max<long long>(16, std::min<long long>(512, th));
+    int p = 16;
+    while (p * 2 <= th) p *= 2;
+    return p;
+}
+
+int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
+{
+    if (slices.empty()) return -1;
+    List L;
+    L.kind = kind;
+    L.level = level;
+    L.G = strip_halo(kind, P.o.nu);
+    L.VW = kStripCols - 2 * L.G;
+    L.TH = choose_rows(P, slices, level, L.VW);
+    L.off = (int)P.items.size();
+    for (int s : slices) {
+        const SliceGeom &g = P.g[s];
+        const int H = g.h[level], W = g.w[level];
+        for (int y0 = 0; y0 < H; y0 += L.TH)
+            for (int x0 = 0; x0 < W; x0 += L.VW)
+                P.items.push_back(Item{P.desc_base[s] + level, x0, y0, std::min(y0 + L.TH, H)});
+    }
+    L.count = (int)P.items.size() - L.off;
+    P.lists.push_back(L);
+    return (int)P.lists.size() - 1;
+}
+
+// per-slice [begin, end) of a list's items (items of a slice are contiguous)
+void list_ranges(const Plan &P, int li, int base, std::vector<int> &r)
+{
+    if (li < 0) return;
+    const List &L = P.lists[li];
+    for (int i = 0; i < L.count; ++i) {
+        const Item &it = P.items[L.off + i];
+        const int s = P.descs[it.lev].slice;
+        if (r[2 * s] < 0) r[2 * s] = base + i;
+        r[2 * s + 1] = base + i + 1;
+    }
+}
+
+// Builds geometry, work lists and the workspace layout.  Host only.
+gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vector<int> &W,
+                     const std::vector<double> &alpha, const Opts &o, int smooth_S)
+{
+    P.o = o;
+    P.n = n;
+    P.mixed = o.prec == GDF_PREC_MIXED;
+    P.fp64 = o.prec == GDF_PREC_FP64;
+    P.esz = P.fp64 ? 8 : 4;
+    P.g.resize(n);
+    P.desc_base.resize(n);
+    int nd = 0;
+    for (int s = 0; s < n; ++s) {
+        SliceGeom &g = P.g[s];
+        g.H = H[s];
+        g.W = W[s];
+        g.alpha = alpha[s];
+        build_levels(g);
+        P.desc_base[s] = nd;
+        nd += g.nlev;
+        P.max_level = std::max(P.max_level, g.nlev - 1);
+    }
+    // arena: per slice, per level u[0], u[1], b; plus the FP64 iterates when mixed
+    size_t off = 0;
+    for (int s = 0; s < n; ++s) {
+        SliceGeom &g = P.g[s];
+        for (int l = 0; l < g.nlev; ++l) {
+            const size_t bytes = align_up((size_t)g.h[l] * g.pitch[l] * P.esz);
+            g.off_u[l][0] = off; off += bytes;
+            g.off_u[l][1] = off; off += bytes;
+            g.off_b[l] = off; off += bytes;
+        }
+        if (P.mixed) {
+            const size_t bytes = align_up((size_t)g.h[0] * g.pitch[0] * 8);
+            g.off_u64[0] = off; off += bytes;
+            g.off_u64[1] = off; off += bytes;
+        }
+    }
+    P.arena_bytes = off;
+    // level descriptors (pointers filled at bind time)
+    P.descs.resize(nd);
+    for (int s = 0; s < n; ++s) {
+        const SliceGeom &g = P.g[s];
+        for (int l = 0; l < g.nlev; ++l) {
+            LevelDesc &d = P.descs[P.desc_base[s] + l];
+            std::memset(&d, 0, sizeof d);
+            d.H = g.h[l];
+            d.W = g.w[l];
+            d.pitch = g.pitch[l];
+            d.sigma = g.sigma[l];
+            d.wxL = g.wxL[l];
+            d.wyL = g.wyL[l];
+            d.slice = s;
+            if (l + 1 < g.nlev) {
+                d.Hc = g.h[l + 1];
+                d.Wc = g.w[l + 1];
+                d.pitch_c = g.pitch[l + 1];
+            } else {
+                d.Hc = d.Wc = 1;
+                d.pitch_c = 0;
+            }
+        }
+    }
+    // work lists
+    for (int l = 0; l < kMaxLevels; ++l) P.list_down[l] = P.list_up[l] = P.list_coarse[l] = -1;
+    std::vector<int> mid0, single0;
+    for (int s = 0; s < n; ++s) (P.g[s].nlev > 1 ? mid0 : single0).push_back(s);
+    P.list_first = add_list(P, SK_DOWN_FIRST, 0, mid0);
+    P.list_fine = add_list(P, SK_FINE, 0, mid0);
+    P.list_single = add_list(P, SK_SINGLE, 0, single0);
+    for (int l = 1; l <= P.max_level; ++l) {
+        std::vector<int> mid, coarsest;
+        for (int s = 0; s < n; ++s) {
+            if (P.g[s].nlev - 1 > l) mid.push_back(s);
+            else if (P.g[s].nlev - 1 == l) coarsest.push_back(s);
+        }
+        P.list_down[l] = add_list(P, SK_DOWN, l, mid);
+        P.list_up[l] = add_list(P, SK_UP, l, mid);
+        P.list_coarse[l] = add_list(P, SK_COARSE, l, coarsest);
+    }
+    const int nF = P.list_first >= 0 ? P.lists[P.list_first].count : 0;
+    const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
+    const int nS = P.list_single >= 0 ? P.lists[P.list_single].count : 0;
+    P.n_norm = std::max(nF, nC) + nS;
+    P.ranges_first.assign(2 * n, -1);
+    P.ranges_cycle.assign(2 * n, -1);
+    list_ranges(P, P.list_first, 0, P.ranges_first);
+    list_ranges(P, P.list_single, nF, P.ranges_first);
+    list_ranges(P, P.list_fine, 0, P.ranges_cycle);
+    list_ranges(P, P.list_single, nC, P.ranges_cycle);
+    // tiles for the per-pixel kernels
+    P.io.resize(n);
+    P.ranges_tiles.resize(2 * n);
+    long long tb = 0;
+    for (int s = 0; s < n; ++s) {
+        SliceIO &io = P.io[s];
+        std::memset(&io, 0, sizeof io);
+        io.alpha = alpha[s];
+        io.H = H[s];
+        io.W = W[s];
+        io.lev0 = P.desc_base[s];
+        io.tiles_x = (W[s] + kTileW - 1) / kTileW;
+        io.tile_begin = tb;
+        const long long nt = (long long)io.tiles_x * ((H[s] + kTileH - 1) / kTileH);
+        P.ranges_tiles[2 * s] = (int)tb;
+        tb += nt;
+        P.ranges_tiles[2 * s + 1] = (int)tb;
+    }
+    P.n_tiles = tb;
+    P.n_partd = tb;
+    if (smooth_S > 0) {
+        // smoothing partials: [S][tiles][4 waves]
+        const long long nparts = (long long)((W[0] + 63) / 64) * ((H[0] + 15) / 16) * 4;
+        P.ranges_smooth.resize(2 * n);
+        for (int s = 0; s < n; ++s) {
+            P.ranges_smooth[2 * s] = (int)(s * nparts);
+            P.ranges_smooth[2 * s + 1] = (int)((s + 1) * nparts);
+        }
+        P.n_partd = std::max<long long>(P.n_partd, nparts * n);
+    }
+    if (P.n_partd > 0x7fffffffLL || P.items.size() > 0x7fffffffULL)
+        return set_err(GDF_EUNSUPPORTED, "problem too large for 32-bit work indices");
+    // layout: [tables][partials][gs copy][arena]
+    size_t o2 = 0;
+    auto take = [&](size_t bytes) { const size_t r = o2; o2 += align_up(bytes); return r; };
+    P.off_tables = 0;
+    P.off_state = take(sizeof(SliceState) * n);
+    P.off_active = take(sizeof(int) * n);
+    P.off_desc = take(sizeof(LevelDesc) * P.descs.size());
+    P.off_items = take(sizeof(Item) * std::max<size_t>(1, P.items.size()));
+    P.off_r_first = take(sizeof(int) * 2 * n);
+    P.off_r_cycle = take(sizeof(int) * 2 * n);
+    P.off_r_tiles = take(sizeof(int) * 2 * n);
+    P.off_r_smooth = take(sizeof(int) * 2 * n);
+    P.off_io = take(sizeof(SliceIO) * n);
+    P.off_u64tab = take(sizeof(double *) * 2 * n);
+    P.tables_bytes = o2;
+    P.off_partf = take(sizeof(float2) * std::max(1, P.n_norm));
+    P.off_partd = take(sizeof(double) * std::max<long long>(1, P.n_partd));
+    P.off_partd2 = take(sizeof(double) * std::max<long long>(1, P.n_partd));
+    P.off_partd3 = take(sizeof(double) * std::max<long long>(1, P.n_partd));
+    P.off_gscopy = o2;
+    if (P.need_gs_copy) take((size_t)n * H[0] * W[0] * sizeof(float));
+    P.off_arena = take(0);
+    P.total = P.off_arena + P.arena_bytes;
+    return GDF_OK;
+}
+
+// Fills device pointers into the descriptors and returns the host image of
+// the tables region.
+std::vector<char> bind_tables(Plan &P, char *ws)
+{
+    char *arena = ws + P.off_arena;
+    SliceState *st_dev = reinterpret_cast<SliceState *>(ws + P.off_state);
+    for (int s = 0; s < P.n; ++s) {
+        const SliceGeom &g = P.g[s];
+        for (int l = 0; l < g.nlev; ++l) {
+            LevelDesc &d = P.descs[P.desc_base[s] + l];
+            d.u[0] = arena + g.off_u[l][0];
+            d.u[1] = arena + g.off_u[l][1];
+            d.b = arena + g.off_b[l];
+            d.bshift = (l == 0 && !P.mixed) ? &st_dev[s].bmean : nullptr;
+            if (l + 1 < g.nlev) {
+                d.bc = arena + g.off_b[l + 1];
+                // level l+1's final iterate: buffer 1 after an up pass; the
+                // coarsest level ends its kCoarsePasses passes in buffer (passes-1)&1
+                const int fin = (l + 1 == g.nlev - 1) ? ((kCoarsePasses - 1) & 1) : 1;
+                d.ec = arena + g.off_u[l + 1][fin];
+            }
+        }
+    }
+    std::vector<char> img(P.tables_bytes, 0);
+    // state zeroed except the per-slice constants; active = 1
+    SliceState *st = reinterpret_cast<SliceState *>(img.data() + P.off_state);
+    int *act = reinterpret_cast<int *>(img.data() + P.off_active);
+    for (int s = 0; s < P.n; ++s) {
+        st[s].npx = (double)P.g[s].H * P.g[s].W;
+        st[s].alpha = P.g[s].alpha;
+        act[s] = 1;
+    }
+    std::memcpy(img.data() + P.off_desc, P.descs.data(), sizeof(LevelDesc) * P.descs.size());
+    if (!P.items.empty()) std::memcpy(img.data() + P.off_items, P.items.data(), sizeof(Item) * P.items.size());
+    std::memcpy(img.data() + P.off_r_first, P.ranges_first.data(), sizeof(int) * 2 * P.n);
+    std::memcpy(img.data() + P.off_r_cycle, P.ranges_cycle.data(), sizeof(int) * 2 * P.n);
+    std::memcpy(img.data() + P.off_r_tiles, P.ranges_tiles.data(), sizeof(int) * 2 * P.n);
+    if (!P.ranges_smooth.empty())
+        std::memcpy(img.data() + P.off_r_smooth, P.ranges_smooth.data(), sizeof(int) * 2 * P.n);
+    std::memcpy(img.data() + P.off_io, P.io.data(), sizeof(SliceIO) * P.n);
+    if (P.mixed) {
+        double **tab = reinterpret_cast<double **>(img.data() + P.off_u64tab);
+        for (int s = 0; s < P.n; ++s) {
+            tab[s] = reinterpret_cast<double *>(arena + P.g[s].off_u64[0]);
+            tab[P.n + s] = reinterpret_cast<double *>(arena + P.g[s].off_u64[1]);
+        }
+    }
+    return img;
+}
+
+// ---------------------------------------------------------------- profiling
+
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+struct ProfRec { int cls; hipEvent_t a, b; double bytes; };
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_prof_pool;
+double g_prof_ms[PC_COUNT], g_prof_bytes[PC_COUNT];
+int g_prof_n[PC_COUNT];
+
+hipEvent_t prof_event()
+{
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_drain()
+{
+    for (ProfRec &r : g_prof_recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_prof_ms[r.cls] += ms;
+            g_prof_bytes[r.cls] += r.bytes;
+            g_prof_n[r.cls] += 1;
+        }
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_recs.clear();
+}
+
+struct ProfScope {
+    bool on;
+    ProfRec rec;
+    hipStream_t s;
+    ProfScope(int cls, double bytes, hipStream_t st, bool capturing) : on(false), s(st)
+    {
+        if (!g_prof_on || capturing) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        rec.cls = cls;
+        rec.bytes = bytes;
+        rec.a = prof_event();
+        rec.b = prof_event();
+        if (!rec.a || !rec.b) return;
+        on = hipEventRecord(rec.a, s) == hipSuccess;
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (hipEventRecord(rec.b, s) == hipSuccess) g_prof_recs.push_back(rec);
+    }
+};
+
+// ------------------------------------------------------------------ driver
+
+struct Run {
+    Plan &P;
+    char *ws;
+    hipStream_t s;
+    bool capturing = false;
+    SliceState *st;
+    int *active;
+    LevelDesc *desc;
+    Item *items;
+    int *r_first, *r_cycle, *r_tiles, *r_smooth;
+    SliceIO *io;
+    double **u64tab;
+    float2 *partf;
+    double *partd, *partd2, *partd3;
+    std::vector<char> active_host;
+    double tol;
+    int max_cycles;
+
+    Run(Plan &p, char *w, hipStream_t st_) : P(p), ws(w), s(st_)
+    {
+        st = reinterpret_cast<SliceState *>(ws + P.off_state);
+        active = reinterpret_cast<int *>(ws + P.off_active);
+        desc = reinterpret_cast<LevelDesc *>(ws + P.off_desc);
+        items = reinterpret_cast<Item *>(ws + P.off_items);
+        r_first = reinterpret_cast<int *>(ws + P.off_r_first);
+        r_cycle = reinterpret_cast<int *>(ws + P.off_r_cycle);
+        r_tiles = reinterpret_cast<int *>(ws + P.off_r_tiles);
+        r_smooth = reinterpret_cast<int *>(ws + P.off_r_smooth);
+        io = reinterpret_cast<SliceIO *>(ws + P.off_io);
+        u64tab = reinterpret_cast<double **>(ws + P.off_u64tab);
+        partf = reinterpret_cast<float2 *>(ws + P.off_partf);
+        partd = reinterpret_cast<double *>(ws + P.off_partd);
+        partd2 = reinterpret_cast<double *>(ws + P.off_partd2);
+        partd3 = reinterpret_cast<double *>(ws + P.off_partd3);
+        active_host.assign(P.n, 1);
+    }
+
+    // algorithmic bytes of a list's pass over the slices still iterating
+    double pass_bytes(int li, double per_px) const
+    {
+        const List &L = P.lists[li];
+        double px = 0.0;
+        int last = -1;
+        for (int i = 0; i < L.count; ++i) {
+            const int s = P.descs[P.items[L.off + i].lev].slice;
+            if (s == last) continue;
+            last = s;
+            if (active_host[s]) px += (double)P.g[s].h[L.level] * P.g[s].w[L.level];
+        }
+        return px * per_px;
+    }
+
+    gdf_status strip(int li, StripKind kind, int in_sel, int out_sel, float2 *partials, bool fp64,
+                     int cls, double per_px)
+    {
+        if (li < 0) return GDF_OK;
+        const List &L = P.lists[li];
+        if (L.count == 0) return GDF_OK;
+        StripLaunch a;
+        a.levs = desc;
+        a.items = items + L.off;
+        a.n_items = L.count;
+        a.in_sel = in_sel;
+        a.out_sel = out_sel;
+        a.active = active;
+        a.partials = partials;
+        ProfScope ps(cls, g_prof_on ? pass_bytes(li, per_px) : 0.0, s, capturing);
+        HIP_TRY(launch_strip(kind, P.o.nu, fp64, a, s));
+        return GDF_OK;
+    }
+
+    gdf_status finish(const int *range, const float2 *pf, const double *pd, int mode, int count)
+    {
+        HIP_TRY(launch_finish(P.n, range, pf, pd, mode, tol, max_cycles, count, st, active, s));
+        return GDF_OK;
+    }
+
+    // one multigrid coarse-grid correction (levels >= 1), hierarchy precision fp64
+    gdf_status coarse(bool fp64)
+    {
+        const double e = fp64 ? 8.0 : 4.0;
+        gdf_status r;
+        for (int l = 1; l <= P.max_level; ++l) {
+            if ((r = strip(P.list_down[l], SK_DOWN, 0, 0, nullptr, fp64, PC_COARSE, 2.25 * e))) return r;
+            if ((r = strip(P.list_coarse[l], SK_COARSE_ZERO, 0, 0, nullptr, fp64, PC_COARSE, 2 * e))) return r;
+            for (int k = 1; k < kCoarsePasses; ++k)
+                if ((r = strip(P.list_coarse[l], SK_COARSE, (k - 1) & 1, k & 1, nullptr, fp64, PC_COARSE, 3 * e))) return r;
+        }
+        for (int l = P.max_level - 1; l >= 1; --l)
+            if ((r = strip(P.list_up[l], SK_UP, 0, 1, nullptr, fp64, PC_COARSE, 3.25 * e))) return r;
+        return GDF_OK;
+    }
+
+    gdf_status first_pass(bool fp64)
+    {
+        const double e = fp64 ? 8.0 : 4.0;
+        gdf_status r;
+        const int nF = P.list_first >= 0 ? P.lists[P.list_first].count : 0;
+        if ((r = strip(P.list_first, SK_DOWN_FIRST, 0, 0, partf, fp64, PC_FIRST, 2.25 * e))) return r;
+        if ((r = strip(P.list_single, SK_SINGLE_ZERO, 0, 0, partf + nF, fp64, PC_COARSE, 2 * e))) return r;
+        return GDF_OK;
+    }
+
+    gdf_status cycle(int k, bool fp64)
+    {
+        const double e = fp64 ? 8.0 : 4.0;
+        gdf_status r;
+        if ((r = coarse(fp64))) return r;
+        const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
+        if ((r = strip(P.list_fine, SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE, 3.5 * e))) return r;
+        if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e))) return r;
+        return GDF_OK;
+    }
+
+    gdf_status read_active(bool &any)
+    {
+        std::vector<int> h(P.n);
+        HIP_TRY(hipMemcpyAsync(h.data(), active, sizeof(int) * P.n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        any = false;
+        for (int i = 0; i < P.n; ++i) {
+            active_host[i] = h[i] != 0;
+            any |= active_host[i];
+        }
+        return GDF_OK;
+    }
+
+    // V-cycles until every slice meets tol (host checks the flags after each cycle)
+    gdf_status iterate(bool fp64)
+    {
+        gdf_status r;
+        if ((r = first_pass(fp64))) return r;
+        if ((r = finish(r_first, partf, nullptr, FIN_CHECK, 0))) return r;
+        if (capturing) {
+            for (int k = 1; k <= max_cycles; ++k) {
+                if ((r = cycle(k, fp64))) return r;
+                if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
+            }
+            return GDF_OK;
+        }
+        bool any = true;
+        for (int k = 1; k <= max_cycles; ++k) {
+            if ((r = read_active(any))) return r;
+            if (!any) break;
+            if ((r = cycle(k, fp64))) return r;
+            if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
+        }
+        return GDF_OK;
+    }
+};
+
+gdf_status upload_tables(Plan &P, char *ws, hipStream_t s)
+{
+    std::vector<char> img = bind_tables(P, ws);
+    HIP_TRY(hipMemcpyAsync(ws + P.off_tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
+    // pageable source: the copy is staged before the call returns; synchronise
+    // so the host image can be released safely
+    HIP_TRY(hipStreamSynchronize(s));
+    return GDF_OK;
+}
+
+gdf_status collect(Plan &P, char *ws, hipStream_t s, gdf_slice_report *rep, double tol, int cycles_scale)
+{
+    std::vector<SliceState> h(P.n);
+    HIP_TRY(hipMemcpyAsync(h.data(), ws + P.off_state, sizeof(SliceState) * P.n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    gdf_status worst = GDF_OK;
+    for (int i = 0; i < P.n; ++i) {
+        int status = GDF_OK;
+        if (h[i].status == GDF_ENONFINITE || !std::isfinite(h[i].rel)) status = GDF_ENONFINITE;
+        else if (h[i].rel > tol) status = GDF_ENOCONV;
+        if (rep) {
+            rep[i].vcycles = h[i].cycles * cycles_scale;
+            rep[i].status = status;
+            rep[i].rel_residual = h[i].rel;
+            rep[i].rel_residual_init = h[i].rel_init;
+        }
+        if (status == GDF_ENONFINITE) worst = GDF_ENONFINITE;
+        else if (status == GDF_ENOCONV && worst == GDF_OK) worst = GDF_ENOCONV;
+    }
+    if (worst == GDF_ENOCONV) set_err(worst, "some slices did not reach tol=%g", tol);
+    if (worst == GDF_ENONFINITE) set_err(worst, "non-finite residual in some slices");
+    return worst;
+}
+
+// -------------------------------------------------------------- graph cache
+
+struct GraphEntry {
+    std::vector<unsigned long long> key;
+    hipGraphExec_t exec;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+
+hipGraphExec_t graph_lookup(const std::vector<unsigned long long> &key)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto &e : g_graphs)
+        if (e.key == key) return e.exec;
+    return nullptr;
+}
+
+void graph_store(const std::vector<unsigned long long> &key, hipGraphExec_t ex)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    if (g_graphs.size() >= 16) {
+        hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back(GraphEntry{key, ex});
+}
+
+template <typename T> void key_push(std::vector<unsigned long long> &k, const T &v)
+{
+    unsigned long long x = 0;
+    std::memcpy(&x, &v, std::min(sizeof v, sizeof x));
+    k.push_back(x);
+}
+
+// ------------------------------------------------------------ solve body
+
+struct SolveIO {
+    int gs_dtype, go_dtype;
+    const void *gs, *go;
+    void *f;
+};
+
+// Prepared right-hand side (prep kernel or smoothing) -> iterate -> output.
+gdf_status solve_body(Run &R, const SolveIO &x)
+{
+    Plan &P = R.P;
+    gdf_status r;
+    if (!P.mixed) {
+        if ((r = R.iterate(P.fp64))) return r;
+        {
+            ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
+            HIP_TRY(launch_finalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
+                                    R.desc, R.st, R.partd, R.s));
+        }
+        return R.finish(R.r_tiles, nullptr, R.partd, FIN_FINAL, 0);
+    }
+    // mixed: FP64 refinement around FP32 V-cycles
+    RefineArgs ra;
+    ra.gs_dtype = x.gs_dtype;
+    ra.go_dtype = x.go_dtype;
+    ra.gs = x.gs;
+    ra.go = x.go;
+    ra.io = R.io;
+    ra.n_slices = P.n;
+    ra.n_tiles = P.n_tiles;
+    ra.levs = R.desc;
+    ra.u64 = R.u64tab;
+    ra.active = R.active;
+    ra.part_rr = R.partd;
+    ra.in_sel = 1;
+    ra.e_sel = 0;
+    ra.first = 1;
+    {
+        ProfScope ps(PC_REFINE, 0.0, R.s, R.capturing);
+        HIP_TRY(launch_refine(ra, R.s));
+    }
+    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_CHECK, 0))) return r;
+    const int steps = std::max(1, P.o.max_vc / P.o.inner);
+    const int saved_max = R.max_cycles;
+    R.max_cycles = steps;
+    for (int k = 1; k <= steps; ++k) {
+        if (!R.capturing) {
+            bool any = true;
+            if ((r = R.read_active(any))) return r;
+            if (!any) break;
+        }
+        if ((r = R.first_pass(false))) return r;
+        for (int c = 1; c <= P.o.inner; ++c)
+            if ((r = R.cycle(c, false))) return r;
+        ra.first = 0;
+        ra.in_sel = (k - 1) & 1;
+        ra.e_sel = P.o.inner & 1;
+        {
+            ProfScope ps(PC_REFINE, 0.0, R.s, R.capturing);
+            HIP_TRY(launch_refine(ra, R.s));
+        }
+        if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_CHECK, 1))) return r;
+    }
+    R.max_cycles = saved_max;
+    {
+        ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
+        HIP_TRY(launch_finalize64(x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
+                                  R.u64tab, 0, R.desc, R.s));
+    }
+    return GDF_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char *gdf_last_error(void) { return g_err.c_str(); }
+
+const char *gdf_version(void) { return "gdf-mi355x 0.1 (gfx950)"; }
+
+void gdf_release(void)
+{
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto &e : g_graphs) hipGraphExecDestroy(e.exec);
+    g_graphs.clear();
+}
+
+void gdf_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+}
+
+void gdf_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    for (int i = 0; i < PC_COUNT; ++i) g_prof_ms[i] = g_prof_bytes[i] = 0.0, g_prof_n[i] = 0;
+}
+
+int gdf_profile_read(const char *cls, double *ms, double *bytes)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    for (int i = 0; i < PC_COUNT; ++i)
+        if (cls && std::strcmp(cls, kProfNames[i]) == 0) {
+            if (ms) *ms = g_prof_ms[i];
+            if (bytes) *bytes = g_prof_bytes[i];
+            return g_prof_n[i];
+        }
+    return -1;
+}
+
+// ---------------------------------------------------------------- fuse_stack
+
+static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long long pr, long long ps,
+                                double alpha, int bc, double tol, double sxy, double sz,
+                                const void *f, const gdf_solve_opts *opts, Opts &o)
+{
+    gdf_status r;
+    if ((r = parse_opts(opts, o))) return r;
+    if (S < 1 || H < 1 || W < 1) return set_err(GDF_EINVAL, "S, H, W must be >= 1 (got %d, %d, %d)", S, H, W);
+    if (!stack || !f) return set_err(GDF_EINVAL, "stack and f must be non-null");
+    if (pr < W || ps < (long long)H * pr)
+        return set_err(GDF_EINVAL, "pitch_row must be >= W and pitch_slice >= H * pitch_row");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_err(GDF_EINVAL, "alpha must be finite and > 0 (got %g)", alpha);
+    if ((r = check_common(bc, tol))) return r;
+    if (!(sxy >= 0.0) || !(sz >= 0.0) || !std::isfinite(sxy) || !std::isfinite(sz))
+        return set_err(GDF_EINVAL, "sigma_xy and sigma_z must be finite and >= 0");
+    if (std::floor(3.0 * sxy) > 7 || std::floor(3.0 * sz) > 12)
+        return set_err(GDF_EUNSUPPORTED, "smoothing radius beyond 7 (xy) or 12 (z) taps is not supported");
+    return GDF_OK;
+}
+
+static gdf_status fuse_plan(Plan &P, int S, int H, int W, double alpha, const Opts &o, bool need_gs)
+{
+    std::vector<int> Hs(S, H), Ws(S, W);
+    std::vector<double> al(S, alpha);
+    P.need_gs_copy = need_gs;
+    return make_plan(P, S, Hs, Ws, al, o, S);
+}
+
+size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
+{
+    Opts o;
+    if (parse_opts(opts, o)) return 0;
+    if (S < 1 || H < 1 || W < 1) return 0;
+    Plan P;
+    if (fuse_plan(P, S, H, W, 1.0, o, o.prec == GDF_PREC_MIXED)) return 0;
+    // the hierarchy depth depends on alpha; size for the deepest (smallest alpha)
+    Plan Q;
+    if (fuse_plan(Q, S, H, W, 1e-12, o, o.prec == GDF_PREC_MIXED)) return 0;
+    return std::max(P.total, Q.total);
+}
+
+gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch_row,
+                      long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
+                      double sigma_z, void *f, void *g_smooth, const gdf_solve_opts *opts,
+                      void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream)
+{
+    Opts o;
+    gdf_status r;
+    if ((r = fuse_validate(stack, S, H, W, pitch_row, pitch_slice, alpha, bc, tol, sigma_xy, sigma_z, f, opts, o)))
+        return r;
+    if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
+    const bool mixed = o.prec == GDF_PREC_MIXED;
+    Plan P;
+    if ((r = fuse_plan(P, S, H, W, alpha, o, mixed && !g_smooth))) return r;
+    if (ws_bytes < P.total)
+        return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
+    // g_o is the stack itself; f (and the FP32 copy of g_s when kept) are contiguous
+    for (int z = 0; z < S; ++z) {
+        P.io[z].off_go = (long long)z * pitch_slice;
+        P.io[z].pitch_go = pitch_row;
+        P.io[z].off_f = (long long)z * H * W;
+        P.io[z].pitch_f = W;
+        P.io[z].off_gs = (long long)z * H * W;
+        P.io[z].pitch_gs = W;
+    }
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((r = upload_tables(P, ws, s))) return r;
+    Run R(P, ws, s);
+    R.tol = tol;
+    R.max_cycles = o.max_vc;
+
+    // smoothing writes the level-0 right-hand side of every slice
+    SmoothArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.stack = stack;
+    a.pitch_row = pitch_row;
+    a.pitch_slice = pitch_slice;
+    a.S = S;
+    a.H = H;
+    a.W = W;
+    a.rxy = sigma_xy > 0 ? (int)std::floor(3.0 * sigma_xy) : 0;
+    a.rz = sigma_z > 0 ? (int)std::floor(3.0 * sigma_z) : 0;
+    for (int d = 0; d <= a.rxy; ++d)
+        a.wxy[d] = sigma_xy > 0 ? std::exp(-(double)d * d / (2 * sigma_xy * sigma_xy)) : 1.0;
+    for (int d = 0; d <= a.rz; ++d)
+        a.wz[d] = sigma_z > 0 ? std::exp(-(double)d * d / (2 * sigma_z * sigma_z)) : 1.0;
+    a.alpha = alpha;
+    void *gs_used = g_smooth ? g_smooth : (mixed ? (void *)(ws + P.off_gscopy) : nullptr);
+    a.gs_out = gs_used;
+    a.levs = R.desc;
+    a.lev_stride = P.g[0].nlev;   // uniform stack: descriptors are [slice][level]
+    a.part_bb = R.partd;
+    a.part_b0 = R.partd2;
+    a.part_bs = R.partd3;
+    a.tiles_x = (W + 63) / 64;
+    a.tiles_y = (H + 15) / 16;
+    {
+        ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0)), s, false);
+        HIP_TRY(launch_smooth(P.fp64, a, s));
+    }
+    if ((r = R.finish(R.r_smooth, nullptr, R.partd, FIN_BB, 0))) return r;
+    if ((r = R.finish(R.r_smooth, nullptr, R.partd2, FIN_INIT, 0))) return r;
+    if ((r = R.finish(R.r_smooth, nullptr, R.partd3, FIN_MEAN, 0))) return r;
+
+    SolveIO x;
+    x.gs_dtype = P.fp64 ? GDF_F64 : GDF_F32;
+    x.gs = gs_used;
+    x.go_dtype = GDF_U8;
+    x.go = stack;
+    x.f = f;
+    if ((r = solve_body(R, x))) return r;
+    return collect(P, ws, s, report, tol, mixed ? o.inner : 1);
+}
+
+// -------------------------------------------------------------- solve_slices
+
+static gdf_status slices_validate(int n, const gdf_slice_desc *d, double tol, int bc,
+                                  const gdf_solve_opts *opts, Opts &o, std::vector<int> &H,
+                                  std::vector<int> &W, std::vector<double> &al)
+{
+    gdf_status r;
+    if ((r = parse_opts(opts, o))) return r;
+    if (n < 1 || !d) return set_err(GDF_EINVAL, "n must be >= 1 and desc non-null");
+    if ((r = check_common(bc, tol))) return r;
+    H.resize(n);
+    W.resize(n);
+    al.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const gdf_slice_desc &s = d[i];
+        if (s.H < 1 || s.W < 1) return set_err(GDF_EINVAL, "slice %d: H, W must be >= 1", i);
+        if (!(s.alpha > 0.0) || !std::isfinite(s.alpha))
+            return set_err(GDF_EINVAL, "slice %d: alpha must be finite and > 0 (got %g)", i, s.alpha);
+        if (s.off_gs < 0 || s.off_go < 0 || s.off_f < 0)
+            return set_err(GDF_EINVAL, "slice %d: offsets must be >= 0", i);
+        if (s.pitch_gs < s.W || s.pitch_go < s.W || s.pitch_f < s.W)
+            return set_err(GDF_EINVAL, "slice %d: row pitches must be >= W", i);
+        H[i] = s.H;
+        W[i] = s.W;
+        al[i] = s.alpha;
+    }
+    return GDF_OK;
+}
+
+static void fill_io(Plan &P, const gdf_slice_desc *d)
+{
+    for (int i = 0; i < P.n; ++i) {
+        P.io[i].off_gs = d[i].off_gs;
+        P.io[i].pitch_gs = d[i].pitch_gs;
+        P.io[i].off_go = d[i].off_go;
+        P.io[i].pitch_go = d[i].pitch_go;
+        P.io[i].off_f = d[i].off_f;
+        P.io[i].pitch_f = d[i].pitch_f;
+    }
+}
+
+size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
+{
+    Opts o;
+    std::vector<int> H, W;
+    std::vector<double> al;
+    if (slices_validate(n, d, 0.5, GDF_BC_NEUMANN, opts, o, H, W, al)) return 0;
+    Plan P;
+    if (make_plan(P, n, H, W, al, o, 0)) return 0;
+    return P.total;
+}
+
+size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
+{
+    return gdf_solve_workspace_size(n, d, opts);
+}
+
+gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
+                        const void *go, int bc, double tol, void *f, const gdf_solve_opts *opts,
+                        void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream)
+{
+    Opts o;
+    std::vector<int> H, W;
+    std::vector<double> al;
+    gdf_status r;
+    if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
+    if (gs_dtype != GDF_F32 && gs_dtype != GDF_F64) return set_err(GDF_EINVAL, "gs_dtype must be GDF_F32 or GDF_F64");
+    if (go_dtype != GDF_U8 && go_dtype != GDF_F32 && go_dtype != GDF_F64)
+        return set_err(GDF_EINVAL, "go_dtype must be GDF_U8, GDF_F32 or GDF_F64");
+    if (!gs || !go || !f) return set_err(GDF_EINVAL, "gs, go and f must be non-null");
+    if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
+    Plan P;
+    if ((r = make_plan(P, n, H, W, al, o, 0))) return r;
+    if (ws_bytes < P.total)
+        return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
+    fill_io(P, d);
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((r = upload_tables(P, ws, s))) return r;
+    Run R(P, ws, s);
+    R.tol = tol;
+    R.max_cycles = o.max_vc;
+    SolveIO x{gs_dtype, go_dtype, gs, go, f};
+
+    auto body = [&]() -> gdf_status {
+        gdf_status q;
+        {
+            ProfScope ps(PC_PREP, 0.0, s, R.capturing);
+            HIP_TRY(launch_prep(P.fp64, gs_dtype, gs, go_dtype, go, R.io, n, P.n_tiles, R.desc, R.partd,
+                                R.partd2, R.partd3, s));
+        }
+        if ((q = R.finish(R.r_tiles, nullptr, R.partd, FIN_BB, 0))) return q;
+        if ((q = R.finish(R.r_tiles, nullptr, R.partd2, FIN_INIT, 0))) return q;
+        if ((q = R.finish(R.r_tiles, nullptr, R.partd3, FIN_MEAN, 0))) return q;
+        return solve_body(R, x);
+    };
+
+    if (!o.use_graph) {
+        if ((r = body())) return r;
+    } else {
+        std::vector<unsigned long long> key;
+        key_push(key, n);
+        key_push(key, (const void *)ws);
+        key_push(key, gs);
+        key_push(key, go);
+        key_push(key, (const void *)f);
+        key_push(key, (const void *)s);
+        key_push(key, gs_dtype);
+        key_push(key, go_dtype);
+        key_push(key, tol);
+        key_push(key, o.prec);
+        key_push(key, o.max_vc);
+        key_push(key, o.nu);
+        key_push(key, o.out_dtype);
+        key_push(key, o.tile_rows);
+        key_push(key, o.inner);
+        for (int i = 0; i < n; ++i) {
+            key_push(key, d[i].H);
+            key_push(key, d[i].W);
+            key_push(key, d[i].alpha);
+            key_push(key, d[i].off_gs);
+            key_push(key, d[i].off_go);
+            key_push(key, d[i].off_f);
+            key_push(key, d[i].pitch_gs);
+            key_push(key, d[i].pitch_go);
+            key_push(key, d[i].pitch_f);
+        }
+        hipGraphExec_t ex = graph_lookup(key);
+        if (!ex) {
+            R.capturing = true;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            gdf_status q = body();
+            hipGraph_t g = nullptr;
+            const hipError_t ec = hipStreamEndCapture(s, &g);
+            if (q) {
+                if (g) hipGraphDestroy(g);
+                return q;
+            }
+            if (ec != hipSuccess) return set_err(GDF_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (ei != hipSuccess) return set_err(GDF_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ei));
+            graph_store(key, ex);
+            R.capturing = false;
+        }
+        HIP_TRY(hipGraphLaunch(ex, s));
+    }
+    return collect(P, ws, s, report, tol, o.prec == GDF_PREC_MIXED ? o.inner : 1);
+}
+
+// ----------------------------------------------------- solve_slices_backward
+
+gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
+                                 const void *f, const void *gs, int bc, double tol, void *grad_gs,
+                                 void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
+                                 void *workspace, size_t ws_bytes, gdf_slice_report *report,
+                                 void *stream)
+{
+    Opts o;
+    std::vector<int> H, W;
+    std::vector<double> al;
+    gdf_status r;
+    if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
+    if (dtype != GDF_F32 && dtype != GDF_F64) return set_err(GDF_EINVAL, "dtype must be GDF_F32 or GDF_F64");
+    if (o.prec == GDF_PREC_MIXED) return set_err(GDF_EUNSUPPORTED, "the adjoint solve runs in FP32 or FP64");
+    if ((dtype == GDF_F64) != (o.prec == GDF_PREC_FP64))
+        return set_err(GDF_EINVAL, "dtype must match opts.precision (F32 <-> FP32, F64 <-> FP64)");
+    if (!grad_f || !f || !gs) return set_err(GDF_EINVAL, "grad_f, f and gs must be non-null");
+    if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
+    Plan P;
+    if ((r = make_plan(P, n, H, W, al, o, 0))) return r;
+    if (ws_bytes < P.total)
+        return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
+    fill_io(P, d);
+    char *ws = static_cast<char *>(workspace);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((r = upload_tables(P, ws, s))) return r;
+    Run R(P, ws, s);
+    R.tol = tol;
+    R.max_cycles = o.max_vc;
+    {
+        ProfScope ps(PC_PREP, 0.0, s, false);
+        HIP_TRY(launch_prep_adjoint(P.fp64, grad_f, R.io, n, P.n_tiles, R.desc, R.partd, R.partd3, s));
+    }
+    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_BB, 0))) return r;
+    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_INIT, 0))) return r;
+    if ((r = R.finish(R.r_tiles, nullptr, R.partd3, FIN_MEAN, 0))) return r;
+    if ((r = R.iterate(P.fp64))) return r;
+    {
+        ProfScope ps(PC_ADJOINT, 0.0, s, false);
+        HIP_TRY(launch_adjoint_assemble(P.fp64, gs, f, grad_gs, grad_go, R.io, n, P.n_tiles, R.desc, R.st,
+                                        R.partd, s));
+    }
+    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_SUM, 0))) return r;
+    std::vector<SliceState> h(n);
+    HIP_TRY(hipMemcpyAsync(h.data(), R.st, sizeof(SliceState) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (grad_alpha)
+        for (int i = 0; i < n; ++i) grad_alpha[i] = h[i].aux;
+    return collect(P, ws, s, report, tol, 1);
+}
+
+}  // extern "C"

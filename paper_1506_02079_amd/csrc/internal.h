@@ -1,0 +1,193 @@
+// Internal declarations shared by the host driver and the HIP kernels of the
+// gradient-domain fusion library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace gdf {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kStripCols = 128;    // columns covered by one wave (2 per lane)
+constexpr int kWavesPerBlock = 4;  // independent waves per workgroup
+constexpr int kMaxLevels = 16;
+
+// One multigrid level of one slice.  Arrays are row-major with row pitch
+// `pitch` (elements, even, >= W + 1 for odd W) so that a lane's two-column
+// vector access never leaves the allocation.
+struct LevelDesc {
+    void *u[2];      // iterate ping-pong buffers at this level
+    void *b;         // right-hand side at this level (scaled units, see below)
+    void *ec;        // coarse correction to prolongate (level+1 iterate), or null
+    void *bc;        // coarse right-hand side to restrict into (level+1), or null
+    int H, W, pitch;
+    int Hc, Wc, pitch_c;
+    double sigma;    // alpha * h^2 with h = 2^level: the level's scaled screening term
+    double wxL, wyL; // width of the last column / height of the last row relative to a full
+                     // cell (ceil-halving leaves a partial last cell when a side is odd)
+    const double *bshift;  // level 0: per-slice mean of b subtracted on load (null: none)
+    int slice;       // slice index (flags, partial sums)
+    int pad_;
+};
+
+// A strip work item: one wave processes columns [x0 - G, x0 - G + 128) of
+// rows [y0 - G, y1 + G) and owns output columns [x0, x0 + 128 - 2G) x rows [y0, y1).
+struct Item {
+    int lev;  // index into the LevelDesc table
+    int x0;
+    int y0;
+    int y1;
+};
+
+enum ResidMode { RES_NONE = 0, RES_NORM = 1, RES_RESTRICT = 2, RES_BOTH = 3 };
+
+// Launch parameters of one strip pass.
+struct StripLaunch {
+    const LevelDesc *levs;
+    const Item *items;
+    int n_items;
+    int in_sel, out_sel;     // which u buffer is read / written
+    const int *active;       // per-slice "still iterating" flags
+    float2 *partials;        // per-item partial sums (r^2, r) (RES_NORM / RES_BOTH)
+};
+
+// Strip kernel variants (template instances live in mg_kernels.hip).
+enum StripKind {
+    SK_DOWN_FIRST,   // zero start, 2nu sweeps, residual -> norm + restrict (finest, first pass)
+    SK_FINE,         // prolongate, 4nu sweeps, residual -> norm + restrict (finest, fused up+down)
+    SK_DOWN,         // zero start, 2nu sweeps, restrict (coarse levels, down leg)
+    SK_UP,           // prolongate, 2nu sweeps (coarse levels, up leg)
+    SK_COARSE_ZERO,  // zero start, 2 sweeps (coarsest level)
+    SK_COARSE,       // 2 sweeps (coarsest level)
+    SK_SINGLE_ZERO,  // zero start, 2 sweeps, residual -> norm (single-level slices)
+    SK_SINGLE,       // 2 sweeps, residual -> norm
+    SK_COUNT
+};
+
+// Halo (G) of a strip kind: stages after the load, plus one for prolongation,
+// rounded up to even.  Valid output width per strip is 128 - 2G.
+int strip_halo(StripKind k, int nu);
+
+// Enqueue one strip pass.  fp64 selects double precision.
+hipError_t launch_strip(StripKind k, int nu, bool fp64, const StripLaunch &a, hipStream_t s);
+
+// ---- per-slice reductions and flags ------------------------------------
+
+struct SliceState {
+    double bb;          // ||b||^2 of Eq. (1) (f-form right-hand side)
+    double rr;          // ||r||^2 at the last check
+    double rel;         // sqrt(rr / bb)
+    double rel_init;    // residual of f = g_o relative to b
+    double aux;         // FIN_SUM result
+    double npx;         // pixels in the slice (set by the host)
+    double alpha;       // screening weight (set by the host)
+    double shift;       // constant-mode correction mean(r) / alpha of the last check
+    double bmean;       // mean of the level-0 right-hand side (subtracted on load)
+    double uoff;        // bmean / alpha: the solution's mean, added back at the end
+    int cycles;         // coarse-grid corrections applied
+    int status;         // 0 ok / iterating, GDF_ENONFINITE ...
+};
+
+enum FinishMode {
+    FIN_BB = 0,       // store the sum as ||b||^2
+    FIN_CHECK = 1,    // in-loop residual: store rr/rel, count the cycle, clear `active` when done
+    FIN_FINAL = 2,    // residual of the returned f: store rr/rel
+    FIN_INIT = 3,     // ||b_u||^2: rel_init = sqrt(sum / bb)
+    FIN_SUM = 4,      // plain sum into state.aux (e.g. dLoss/dalpha)
+    FIN_MEAN = 5      // sum of b: bmean = sum / npx, uoff = bmean / alpha
+};
+
+// Sum the partials of each slice over [range[2s], range[2s+1]) in a fixed
+// order (deterministic) and update the slice state and flags.
+// partials_f: strip partials (r^2, r); partials_d: FP64 tile partials.
+// FIN_CHECK with strip partials also records the constant-mode correction.
+hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_f,
+                         const double *partials_d, int mode, double tol, int max_cycles,
+                         int count_cycle, SliceState *state, int *active, hipStream_t s);
+
+// ---- elementwise / simple stencil kernels --------------------------------
+
+struct SliceIO {        // per-slice user-buffer view (element offsets/pitches)
+    long long off_gs, pitch_gs;
+    long long off_go, pitch_go;
+    long long off_f, pitch_f;
+    double alpha;
+    int H, W;
+    int lev0;           // LevelDesc index of the slice's finest level
+    int tiles_x;        // 64-wide tiles per row (for the simple 2D kernels)
+    long long tile_begin;  // first tile index of this slice
+};
+
+// b_u = alpha (g_s - g_o) into level 0 b, and FP64 partials of
+// ||alpha g_s + L g_o||^2, ||b_u||^2 and sum(b_u) per tile.
+hipError_t launch_prep(bool fp64, int gs_dtype, const void *gs, int go_dtype, const void *go,
+                       const SliceIO *io_dev, int n_slices, long long n_tiles,
+                       const LevelDesc *levs, double *part_bb, double *part_b0, double *part_bs,
+                       hipStream_t s);
+
+// f = g_o + u (out dtype), FP64 partials of ||b_u - A u||^2 per tile.  The
+// level-0 iterate of slice s is buffer (state[s].cycles & 1).
+hipError_t launch_finalize(bool fp64, int go_dtype, const void *go, int out_dtype, void *f,
+                           const SliceIO *io_dev, int n_slices, long long n_tiles,
+                           const LevelDesc *levs, const SliceState *state, double *part_rr,
+                           hipStream_t s);
+
+// Adjoint right-hand side: b = grad_f (converted), partials of ||grad_f||^2 and sum(grad_f).
+hipError_t launch_prep_adjoint(bool fp64, const void *grad_f, const SliceIO *io_dev, int n_slices,
+                               long long n_tiles, const LevelDesc *levs, double *part_bb,
+                               double *part_bs, hipStream_t s);
+
+// From lambda (level-0 iterate): grad_gs = alpha lambda, grad_go = L lambda,
+// partials of lambda . (g_s - f).  Buffers share the dtype of the solve.
+hipError_t launch_adjoint_assemble(bool fp64, const void *gs, const void *f, void *grad_gs,
+                                   void *grad_go, const SliceIO *io_dev, int n_slices,
+                                   long long n_tiles, const LevelDesc *levs,
+                                   const SliceState *state, double *part_da, hipStream_t s);
+
+// Mixed precision refinement step: u64_out = u64_in + e (e = level-0 FP32
+// iterate, buffer e_sel; skipped when first), r = alpha (g_s - g_o) - A u64_out
+// in FP64, written as FP32 into level-0 b, partials of ||r||^2.
+struct RefineArgs {
+    int gs_dtype, go_dtype;
+    const void *gs, *go;
+    const SliceIO *io;
+    int n_slices;
+    long long n_tiles;
+    const LevelDesc *levs;   // FP32 hierarchy
+    double *const *u64;      // [2][n_slices] device table of FP64 iterates (pitch = level-0 pitch)
+    int in_sel, e_sel;       // which FP64 buffer is read; which FP32 level-0 buffer holds e
+    int first;               // 1: no correction to add (u64_in = 0)
+    const int *active;
+    double *part_rr;
+};
+hipError_t launch_refine(const RefineArgs &a, hipStream_t s);
+
+// Mixed precision output: f = g_o + u64 (buffer sel).
+hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *f,
+                             const SliceIO *io_dev, int n_slices, long long n_tiles,
+                             double *const *u64, int sel, const LevelDesc *levs, hipStream_t s);
+
+// ---- smoothing ------------------------------------------------------------
+
+struct SmoothArgs {
+    const uint8_t *stack;
+    long long pitch_row, pitch_slice;
+    int S, H, W;
+    int rxy, rz;
+    double wxy[8];        // in-plane taps (0..rxy)
+    double wz[16];        // cross-slice taps (0..rz)
+    double alpha;
+    void *gs_out;         // optional smoothed stack (contiguous [S][H][W])
+    const LevelDesc *levs;  // level-0 descriptor of slice z at index z * lev_stride (b written there)
+    int lev_stride;
+    double *part_bb;      // [S][tiles] partial ||alpha g_s + L g_o||^2
+    double *part_b0;      // [S][tiles] partial ||b_u||^2
+    double *part_bs;      // [S][tiles] partial sum(b_u)
+    int tiles_x, tiles_y;
+};
+
+hipError_t launch_smooth(bool fp64, const SmoothArgs &a, hipStream_t s);
+
+}  // namespace gdf

@@ -1,0 +1,393 @@
+// Multigrid kernels for the per-slice screened-Poisson solve of Eq. (1),
+//     (alpha I + L) f = alpha g_s + L g_o,
+// solved in correction form u = f - g_o:  (alpha I + L) u = alpha (g_s - g_o).
+//
+// Level l of a slice is a finite-volume discretisation of the same operator on
+// cells of side h = 2^l (cell-centred coarsening by ceil-halving), written per
+// cell area h^2: a full cell reads sigma_l e + sum_q (e - e_q) = rhs with
+// sigma_l = alpha h^2 and unit couplings.  When a side is odd the last coarse
+// column/row is narrower; there the mass term scales with the cell's area and
+// each coupling is face length / centre distance, so the coarse problem covers
+// exactly the fine domain.  The right-hand side of a coarse cell is the plain
+// sum of its children's residuals (area-integrated).  Prolongation is
+// cell-centred bilinear interpolation (weights 9/16, 3/16, 3/16, 1/16) with
+// mirrored coarse values at the slice edges.  The smoother is red-black
+// Gauss-Seidel; cell (y, x) is red when x + y is even.  Level 0 (unit cells)
+// runs a specialised update with unit coefficients.
+//
+// The strip kernel is the hot path.  One wavefront owns a strip of 128
+// columns (two adjacent columns per lane) and marches down its rows, keeping a
+// ring of rows in registers.  Successive half-sweeps are skewed by two rows
+// (stage s processes the row loaded 2s steps earlier), which is exactly the
+// schedule under which each red/black update sees its neighbours at the
+// previous half-sweep, so several sweeps plus the residual happen in a single
+// pass over HBM.  Horizontal neighbours across lanes come from DPP wave
+// shifts; there is no LDS traffic and no barrier.  The strip reads a halo of
+// G columns and G rows on each side and recomputes it redundantly.
+#include "internal.h"
+
+namespace gdf {
+
+// ------------------------------------------------------------------ DPP ---
+
+// lane i receives lane i-1's value (lane 0 receives 0)
+__device__ __forceinline__ float wave_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+// lane i receives lane i+1's value (lane 63 receives 0)
+__device__ __forceinline__ float wave_shl1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double wave_shr1(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_shl1(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Map hardware block ids to logical blocks so that consecutive logical blocks
+// (neighbouring strips, which share halo rows/columns) run on the same XCD and
+// hit the same L2.  Hardware dispatch places block b on XCD b % 8; the grid
+// is padded to a multiple of 8 blocks.
+__device__ __forceinline__ int xcd_logical_block()
+{
+    const int nb8 = gridDim.x >> 3;
+    return (blockIdx.x & 7) * nb8 + (blockIdx.x >> 3);
+}
+
+// ------------------------------------------------------------ strip pass ---
+
+template <bool PROLONG, int NHS, int RMODE> struct StripShape {
+    static constexpr int NS = NHS + (RMODE != RES_NONE ? 1 : 0);  // stages after the load
+    static constexpr int G = (NS + (PROLONG ? 1 : 0) + 1) & ~1;   // halo, even
+    static constexpr int VW = kStripCols - 2 * G;                  // owned columns
+    static constexpr int RS = 2 * NS + 2;                          // register ring rows
+};
+
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
+__global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
+{
+    using Sh = StripShape<PROLONG, NHS, RMODE>;
+    constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS;
+    using V2 = typename Vec2<T>::type;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int item_id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6));
+    if (item_id >= a.n_items) return;
+    const Item it = a.items[item_id];
+    const LevelDesc L = a.levs[it.lev];
+    if (!a.active[L.slice]) {
+        if ((RMODE & RES_NORM) && lane == 0) a.partials[item_id] = make_float2(0.f, 0.f);
+        return;
+    }
+    // copy what is used into scalars (a by-reference lambda capture of the
+    // descriptor would force it into scratch memory)
+    const int H = L.H, W = L.W, pitch = L.pitch;
+    const int Hc = L.Hc, Wc = L.Wc, pitch_c = L.pitch_c;
+    const T sig = (T)L.sigma;
+
+    // ---- per-lane column geometry
+    const int cx0 = it.x0 - G + 2 * lane;   // even; this lane holds columns cx0, cx0 + 1
+    const bool in0 = cx0 >= 0 && cx0 < W;
+    const bool in1 = cx0 + 1 >= 0 && cx0 + 1 < W;
+    const int cxl = min(max(cx0, 0), (W - 1) & ~1);  // clamped, even: safe vector address
+    const bool own = in0 && cx0 >= it.x0 && cx0 < it.x0 + VW;
+    const T m0 = in0 ? T(1) : T(0), m1 = in1 ? T(1) : T(0);
+    // neighbour-inside masks (zero for columns outside the slice)
+    const T ml0 = (in0 && cx0 - 1 >= 0) ? T(1) : T(0);
+    const T mr0 = (in0 && cx0 + 1 < W) ? T(1) : T(0);
+    const T ml1 = (in1 && cx0 >= 0) ? T(1) : T(0);
+    const T mr1 = (in1 && cx0 + 2 < W) ? T(1) : T(0);
+    // inverse diagonal sigma + deg for 0, 1, 2 vertical neighbours (0 outside)
+    T inv0[3], inv1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        inv0[d] = in0 ? T(1) / (sig + ml0 + mr0 + T(d)) : T(0);
+        inv1[d] = in1 ? T(1) / (sig + ml1 + mr1 + T(d)) : T(0);
+    }
+    // ---- finite-volume coefficients of a coarse level (GEN)
+    // columns: relative width wx (only the last column may be narrower); the
+    // coupling across a column face is 2 / (wx_left + wx_right) per unit row height
+    const T wxL = (T)L.wxL, wyL = (T)L.wyL;
+    const T kxe = T(2) / (T(1) + wxL);                 // face next to the last column
+    const T wx0 = (cx0 == W - 1) ? wxL : T(1), wx1 = (cx0 + 1 == W - 1) ? wxL : T(1);
+    const T kl0 = ml0 * ((cx0 == W - 1) ? kxe : T(1));
+    const T kr0 = mr0 * ((cx0 + 1 == W - 1) ? kxe : T(1));
+    const T kl1 = ml1 * ((cx0 + 1 == W - 1) ? kxe : T(1));
+    const T kr1 = mr1 * ((cx0 + 2 == W - 1) ? kxe : T(1));
+    // rows: class 0 interior, 1 first, 2 second-to-last, 3 last; (wy, k_up, k_down)
+    const T kye = T(2) / (T(1) + wyL);
+    // (scalars with explicit selects: a runtime-indexed array would live in scratch)
+    const T ckd1 = (H == 2) ? kye : T(1), cku3 = (H == 1) ? T(0) : kye;
+    auto ginv = [sig](T wx, T kl, T kr, bool in, T wy, T ku, T kd) -> T {
+        return GEN && in ? T(1) / (sig * wx * wy + wy * (kl + kr) + wx * (ku + kd)) : T(0);
+    };
+    const T gi00 = ginv(wx0, kl0, kr0, in0, T(1), T(1), T(1)), gi10 = ginv(wx1, kl1, kr1, in1, T(1), T(1), T(1));
+    const T gi01 = ginv(wx0, kl0, kr0, in0, T(1), T(0), ckd1), gi11 = ginv(wx1, kl1, kr1, in1, T(1), T(0), ckd1);
+    const T gi02 = ginv(wx0, kl0, kr0, in0, T(1), T(1), kye), gi12 = ginv(wx1, kl1, kr1, in1, T(1), T(1), kye);
+    const T gi03 = ginv(wx0, kl0, kr0, in0, wyL, cku3, T(0)), gi13 = ginv(wx1, kl1, kr1, in1, wyL, cku3, T(0));
+    // row class: 0 interior, 1 first, 2 second-to-last, 3 last -> (wy, k_up, k_down, inverses)
+    struct RowC { T wy, ku, kd, i0, i1; };
+    auto row_coef = [=](int y) -> RowC {
+        if (y == H - 1) return RowC{wyL, cku3, T(0), gi03, gi13};
+        if (y == 0) return RowC{T(1), T(0), ckd1, gi01, gi11};
+        if (y == H - 2) return RowC{T(1), T(1), kye, gi02, gi12};
+        return RowC{T(1), T(1), T(1), gi00, gi10};
+    };
+
+    const T *__restrict__ bsrc = static_cast<const T *>(L.b);
+    const double *bshift_p = L.bshift;
+    // level 0: the slice's mean right-hand side is removed on load, so the
+    // iterate is the zero-mean part of the correction (smaller values, smaller
+    // FP32 rounding); the mean is added back when f is formed
+    const T bsh = bshift_p ? (T)*bshift_p : T(0);
+    // (selects, not a runtime index into the descriptor's array: that would spill it)
+    const T *__restrict__ usrc = static_cast<const T *>(a.in_sel ? L.u[1] : L.u[0]);
+    T *__restrict__ udst = static_cast<T *>(a.out_sel ? L.u[1] : L.u[0]);
+
+    // ---- prolongation state (coarse column lc = cx0 / 2)
+    const int lc = cx0 >> 1;
+    const bool cin = PROLONG && lc >= 0 && lc < Wc;
+    const int lcl = PROLONG ? min(max(lc, 0), Wc - 1) : 0;
+    const bool ledge = lc == 0, redge = PROLONG && lc == Wc - 1;
+    const T *__restrict__ ecp = static_cast<const T *>(L.ec);
+    auto ld_coarse = [ecp, cin, lcl, Hc, pitch_c](int m) -> T {
+        m = min(max(m, 0), Hc - 1);
+        return cin ? ecp[(size_t)m * pitch_c + lcl] : T(0);
+    };
+
+    // ---- restriction state: a coarse cell's right-hand side is the sum of its
+    // children's residuals (children outside the slice contribute zero)
+    T *__restrict__ bcp = static_cast<T *>(L.bc);
+    T rpair = T(0);
+
+    const int y0 = it.y0, y1 = it.y1;
+    const int ybase = y0 - G, yend = y1 + G;
+    const int NL = yend - ybase;
+    const int yo0 = max(y0, 0), yo1 = min(y1, H);   // owned rows inside the slice
+
+    T u[RS][2], b[RS][2];
+#pragma unroll
+    for (int k = 0; k < RS; ++k) u[k][0] = u[k][1] = b[k][0] = b[k][1] = T(0);
+
+    T e_lo = T(0), e_hi = T(0), e_nx = T(0);
+    if (PROLONG) {
+        const int mb = ybase >> 1;
+        e_lo = ld_coarse(mb - 1);
+        e_hi = ld_coarse(mb);
+    }
+    float nacc = 0.f, sacc = 0.f;
+
+    const int T_end = NL + 2 * NS;
+    for (int tb = 0; tb < T_end; tb += RS) {
+#pragma unroll
+        for (int k = 0; k < RS; ++k) {
+            const int t = tb + k;
+            // ------------------------------------------------ load (stage 0)
+            if (t < NL) {
+                const int y = ybase + t;
+                T cor0 = T(0), cor1 = T(0);
+                if (PROLONG) {
+                    T V;
+                    if ((k & 1) == 0) {            // y even: coarse rows m-1 (lo), m (hi)
+                        V = T(0.75) * e_hi + T(0.25) * e_lo;
+                        e_nx = ld_coarse((y >> 1) + 1);
+                    } else {                        // y odd: coarse rows m (lo), m+1 (hi)
+                        e_lo = e_hi;
+                        e_hi = e_nx;
+                        V = T(0.75) * e_lo + T(0.25) * e_hi;
+                    }
+                    T VL = wave_shr1(V), VR = wave_shl1(V);
+                    VL = ledge ? V : VL;
+                    VR = redge ? V : VR;
+                    cor0 = T(0.75) * V + T(0.25) * VL;
+                    cor1 = T(0.75) * V + T(0.25) * VR;
+                }
+                if (y >= 0 && y < H) {
+                    const size_t ro = (size_t)y * pitch + cxl;
+                    const V2 bv = *reinterpret_cast<const V2 *>(bsrc + ro);
+                    b[k][0] = in0 ? bv.x - bsh : T(0);
+                    b[k][1] = in1 ? bv.y - bsh : T(0);
+                    if (!ZERO) {
+                        const V2 uv = *reinterpret_cast<const V2 *>(usrc + ro);
+                        u[k][0] = in0 ? uv.x + cor0 : T(0);
+                        u[k][1] = in1 ? uv.y + cor1 : T(0);
+                    } else {
+                        u[k][0] = u[k][1] = T(0);
+                    }
+                } else {
+                    u[k][0] = u[k][1] = b[k][0] = b[k][1] = T(0);
+                }
+            }
+            // ------------------------------------------------ stages 1..NS
+#pragma unroll
+            for (int s = 1; s <= NS; ++s) {
+                const int sl = ((k - 2 * s) % RS + RS) % RS;
+                const int su = (sl + RS - 1) % RS;   // row y-1
+                const int sd = (sl + 1) % RS;        // row y+1
+                const int y = ybase + t - 2 * s;
+                if (s <= NHS) {
+                    const int lo = max(ybase + s, 0), hi = min(yend - s, H);
+                    if (y >= lo && y < hi) {
+                        const int c = (s - 1) & 1;         // 0: red, 1: black
+                        const int j = (k & 1) ^ c;         // column of that colour (y parity = k parity)
+                        if (!GEN) {
+                            const int dy = (y > 0) + (y < H - 1);
+                            if (j == 0) {
+                                const T iv = dy == 2 ? inv0[2] : (dy == 1 ? inv0[1] : inv0[0]);
+                                const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
+                                u[sl][0] = (b[sl][0] + nb) * iv;
+                            } else {
+                                const T iv = dy == 2 ? inv1[2] : (dy == 1 ? inv1[1] : inv1[0]);
+                                const T nb = u[sl][0] + wave_shl1(u[sl][0]) + u[su][1] + u[sd][1];
+                                u[sl][1] = (b[sl][1] + nb) * iv;
+                            }
+                        } else {
+                            const RowC rc = row_coef(y);
+                            if (j == 0) {
+                                const T h = fma(kl0, wave_shr1(u[sl][1]), kr0 * u[sl][1]);
+                                const T v = fma(rc.ku, u[su][0], rc.kd * u[sd][0]);
+                                u[sl][0] = (b[sl][0] + fma(rc.wy, h, wx0 * v)) * rc.i0;
+                            } else {
+                                const T h = fma(kl1, u[sl][0], kr1 * wave_shl1(u[sl][0]));
+                                const T v = fma(rc.ku, u[su][1], rc.kd * u[sd][1]);
+                                u[sl][1] = (b[sl][1] + fma(rc.wy, h, wx1 * v)) * rc.i1;
+                            }
+                        }
+                        if (s == NHS && y >= yo0 && y < yo1 && own) {
+                            V2 o;
+                            o.x = u[sl][0];
+                            o.y = u[sl][1];
+                            *reinterpret_cast<V2 *>(udst + (size_t)y * pitch + cx0) = o;
+                        }
+                    }
+                } else if (RMODE != RES_NONE) {
+                    if (y >= yo0 && y < yo1) {
+                        const T uc0 = u[sl][0], uc1 = u[sl][1];
+                        const T l0 = wave_shr1(uc1), r1 = wave_shl1(uc0);
+                        // r = b - sigma u - sum_q k_q (u - u_q): neighbour differences are
+                        // (nearly) exact, so the residual stays accurate in FP32
+                        T r0, rr1;
+                        if (!GEN) {
+                            const T mu = y > 0 ? T(1) : T(0), md = y < H - 1 ? T(1) : T(0);
+                            T acc0 = ml0 * (uc0 - l0);
+                            acc0 = fma(mr0, uc0 - uc1, acc0);
+                            acc0 = fma(mu, uc0 - u[su][0], acc0);
+                            acc0 = fma(md, uc0 - u[sd][0], acc0);
+                            T acc1 = ml1 * (uc1 - uc0);
+                            acc1 = fma(mr1, uc1 - r1, acc1);
+                            acc1 = fma(mu, uc1 - u[su][1], acc1);
+                            acc1 = fma(md, uc1 - u[sd][1], acc1);
+                            r0 = fma(-sig, uc0, b[sl][0]) - acc0;
+                            rr1 = fma(-sig, uc1, b[sl][1]) - acc1;
+                        } else {
+                            const RowC rc = row_coef(y);
+                            const T wy = rc.wy, ku = rc.ku, kd = rc.kd;
+                            const T h0 = fma(kl0, uc0 - l0, kr0 * (uc0 - uc1));
+                            const T v0 = fma(ku, uc0 - u[su][0], kd * (uc0 - u[sd][0]));
+                            const T h1 = fma(kl1, uc1 - uc0, kr1 * (uc1 - r1));
+                            const T v1 = fma(ku, uc1 - u[su][1], kd * (uc1 - u[sd][1]));
+                            r0 = fma(-sig * wx0 * wy, uc0, b[sl][0]) - fma(wy, h0, wx0 * v0);
+                            rr1 = fma(-sig * wx1 * wy, uc1, b[sl][1]) - fma(wy, h1, wx1 * v1);
+                        }
+                        if (RMODE & RES_NORM) {
+                            if (own) {
+                                const float f0 = (float)r0, f1 = (float)rr1;
+                                nacc = fmaf(f0, f0, nacc);
+                                nacc = fmaf(f1, f1, nacc);
+                                sacc += f0 + f1;   // zero for columns outside the slice
+                            }
+                        }
+                        if (RMODE & RES_RESTRICT) {
+                            const T pr = r0 + rr1;      // zero for columns outside the slice
+                            if ((k & 1) == 0) {         // y even: first row of a coarse cell
+                                if (y + 1 >= H) {
+                                    if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = pr;
+                                } else {
+                                    rpair = pr;
+                                }
+                            } else {
+                                if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = rpair + pr;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if (RMODE & RES_NORM) {
+        double v = (double)nacc, w = (double)sacc;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            v += __shfl_xor(v, off);
+            w += __shfl_xor(w, off);
+        }
+        if (lane == 0) a.partials[item_id] = make_float2((float)v, (float)w);
+    }
+}
+
+int strip_halo(StripKind k, int nu)
+{
+    switch (k) {
+    case SK_DOWN_FIRST: return nu == 1 ? StripShape<false, 2, RES_BOTH>::G : StripShape<false, 4, RES_BOTH>::G;
+    case SK_FINE: return nu == 1 ? StripShape<true, 4, RES_BOTH>::G : StripShape<true, 8, RES_BOTH>::G;
+    case SK_DOWN: return nu == 1 ? StripShape<false, 2, RES_RESTRICT>::G : StripShape<false, 4, RES_RESTRICT>::G;
+    case SK_UP: return nu == 1 ? StripShape<true, 2, RES_NONE>::G : StripShape<true, 4, RES_NONE>::G;
+    case SK_COARSE_ZERO:
+    case SK_COARSE: return StripShape<false, 4, RES_NONE>::G;
+    case SK_SINGLE_ZERO:
+    case SK_SINGLE: return StripShape<false, 4, RES_NORM>::G;
+    default: return 0;
+    }
+}
+
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
+static hipError_t go(const StripLaunch &a, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
+    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_strip_t(StripKind k, int nu, const StripLaunch &a, hipStream_t s)
+{
+    const bool n1 = nu == 1;
+    switch (k) {
+    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, s) : go<T, false, true, 4, RES_BOTH>(a, s);
+    case SK_FINE: return n1 ? go<T, true, false, 4, RES_BOTH>(a, s) : go<T, true, false, 8, RES_BOTH>(a, s);
+    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, s);
+    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, s) : go<T, true, false, 4, RES_NONE, true>(a, s);
+    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, s);
+    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, s);
+    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, s);
+    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_strip(StripKind k, int nu, bool fp64, const StripLaunch &a, hipStream_t s)
+{
+    return fp64 ? launch_strip_t<double>(k, nu, a, s) : launch_strip_t<float>(k, nu, a, s);
+}
+
+}  // namespace gdf
