@@ -168,7 +168,10 @@ gdf_status solve_slices(int n, const gdf_slice_desc *desc_host, int gs_dtype, co
  *     dLoss/dg_s = alpha lambda,  dLoss/dg_o = L lambda,
  *     dLoss/dalpha_j = lambda_j . (g_s,j - f_j)   (FP64 sum per slice).
  * dtype (GDF_F32 or GDF_F64) applies to grad_f, f, g_s and the gradient
- * outputs.  grad_f, f, grad_gs and grad_go use (off_f, pitch_f) of each
+ * outputs; it must match opts.precision (F64 <-> GDF_PREC_FP64).  With F32
+ * data the adjoint system is solved by FP32 V-cycles inside FP64 iterative
+ * refinement: grad_f is usually rough (e.g. a data-misfit gradient) and lambda
+ * then has large smooth components that an FP32 iterate cannot resolve to tol.  grad_f, f, grad_gs and grad_go use (off_f, pitch_f) of each
  * descriptor; g_s uses (off_gs, pitch_gs).  grad_gs_dev, grad_go_dev and
  * grad_alpha_host may each be NULL.                                          */
 size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *desc_host,

@@ -551,7 +551,7 @@ struct Run {
     }
 
     gdf_status strip(int li, StripKind kind, int in_sel, int out_sel, float2 *partials, bool fp64,
-                     int cls, double per_px)
+                     int cls, double per_px, bool slice_parity = false)
     {
         if (li < 0) return GDF_OK;
         const List &L = P.lists[li];
@@ -562,6 +562,8 @@ struct Run {
         a.n_items = L.count;
         a.in_sel = in_sel;
         a.out_sel = out_sel;
+        a.cycles = slice_parity ? &st[0].cycles : nullptr;
+        a.cycles_stride = (int)(sizeof(SliceState) / sizeof(int));
         a.active = active;
         a.partials = partials;
         ProfScope ps(cls, g_prof_on ? pass_bytes(li, per_px) : 0.0, s, capturing);
@@ -601,14 +603,16 @@ struct Run {
         return GDF_OK;
     }
 
-    gdf_status cycle(int k, bool fp64)
+    // slice_par: F/S passes take each slice's buffer parity from its cycle
+    // count (plain solve); otherwise from k (the inner solves of the mixed mode)
+    gdf_status cycle(int k, bool fp64, bool slice_par = true)
     {
         const double e = fp64 ? 8.0 : 4.0;
         gdf_status r;
         if ((r = coarse(fp64))) return r;
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
-        if ((r = strip(P.list_fine, SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE, 3.5 * e))) return r;
-        if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e))) return r;
+        if ((r = strip(P.list_fine, SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE, 3.5 * e, slice_par))) return r;
+        if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e, slice_par))) return r;
         return GDF_OK;
     }
 
@@ -625,12 +629,15 @@ struct Run {
         return GDF_OK;
     }
 
-    // V-cycles until every slice meets tol (host checks the flags after each cycle)
-    gdf_status iterate(bool fp64)
+    // V-cycles until every slice meets tol (host checks the flags after each
+    // cycle).  With first = false, continues from the current iterates.
+    gdf_status iterate(bool fp64, bool first = true)
     {
         gdf_status r;
-        if ((r = first_pass(fp64))) return r;
-        if ((r = finish(r_first, partf, nullptr, FIN_CHECK, 0))) return r;
+        if (first) {
+            if ((r = first_pass(fp64))) return r;
+            if ((r = finish(r_first, partf, nullptr, FIN_CHECK, 0))) return r;
+        }
         if (capturing) {
             for (int k = 1; k <= max_cycles; ++k) {
                 if ((r = cycle(k, fp64))) return r;
@@ -645,6 +652,25 @@ struct Run {
             if ((r = cycle(k, fp64))) return r;
             if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
         }
+        return GDF_OK;
+    }
+
+    // After the exact FP64 residual of the output: slices that stopped on the
+    // in-loop (working-precision) estimate but miss tol resume iterating.
+    gdf_status resume_missed(bool &any)
+    {
+        std::vector<SliceState> h(P.n);
+        HIP_TRY(hipMemcpyAsync(h.data(), st, sizeof(SliceState) * P.n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        std::vector<int> act(P.n, 0);
+        any = false;
+        for (int i = 0; i < P.n; ++i)
+            if (h[i].status == 0 && std::isfinite(h[i].rel) && h[i].rel > tol && h[i].cycles < max_cycles) {
+                act[i] = 1;
+                any = true;
+            }
+        if (any) HIP_TRY(hipMemcpyAsync(active, act.data(), sizeof(int) * P.n, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
         return GDF_OK;
     }
 };
@@ -725,26 +751,23 @@ struct SolveIO {
     void *f;
 };
 
-// Prepared right-hand side (prep kernel or smoothing) -> iterate -> output.
-gdf_status solve_body(Run &R, const SolveIO &x)
+// FP64 iterative refinement around FP32 V-cycles.  The FP64 iterate u64 starts
+// at zero; each step solves A e = r (r the FP64 residual, stored as FP32 in the
+// level-0 right-hand side) with inner_cycles FP32 V-cycles from e = 0, then
+// u64 += e and the FP64 residual is formed again, until every slice's FP64
+// relative residual meets tol.  The right-hand side is alpha (g_s - g_o), or
+// `rhs` when given (the adjoint system).
+gdf_status mixed_iterate(Run &R, int gs_dtype, const void *gs, int go_dtype, const void *go,
+                         const void *rhs)
 {
     Plan &P = R.P;
     gdf_status r;
-    if (!P.mixed) {
-        if ((r = R.iterate(P.fp64))) return r;
-        {
-            ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
-            HIP_TRY(launch_finalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
-                                    R.desc, R.st, R.partd, R.s));
-        }
-        return R.finish(R.r_tiles, nullptr, R.partd, FIN_FINAL, 0);
-    }
-    // mixed: FP64 refinement around FP32 V-cycles
     RefineArgs ra;
-    ra.gs_dtype = x.gs_dtype;
-    ra.go_dtype = x.go_dtype;
-    ra.gs = x.gs;
-    ra.go = x.go;
+    ra.gs_dtype = gs_dtype;
+    ra.go_dtype = go_dtype;
+    ra.gs = gs;
+    ra.go = go;
+    ra.rhs = rhs;
     ra.io = R.io;
     ra.n_slices = P.n;
     ra.n_tiles = P.n_tiles;
@@ -771,7 +794,7 @@ gdf_status solve_body(Run &R, const SolveIO &x)
         }
         if ((r = R.first_pass(false))) return r;
         for (int c = 1; c <= P.o.inner; ++c)
-            if ((r = R.cycle(c, false))) return r;
+            if ((r = R.cycle(c, false, false))) return r;
         ra.first = 0;
         ra.in_sel = (k - 1) & 1;
         ra.e_sel = P.o.inner & 1;
@@ -782,10 +805,36 @@ gdf_status solve_body(Run &R, const SolveIO &x)
         if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_CHECK, 1))) return r;
     }
     R.max_cycles = saved_max;
+    return GDF_OK;
+}
+
+// Prepared right-hand side (prep kernel or smoothing) -> iterate -> output.
+gdf_status solve_body(Run &R, const SolveIO &x)
+{
+    Plan &P = R.P;
+    gdf_status r;
+    if (!P.mixed) {
+        for (int round = 0; round < 4; ++round) {
+            if ((r = R.iterate(P.fp64, round == 0))) return r;
+            {
+                ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
+                HIP_TRY(launch_finalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
+                                        R.desc, R.st, R.partd, R.s));
+            }
+            if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_FINAL, 0))) return r;
+            if (R.capturing) break;
+            bool again = false;
+            if ((r = R.resume_missed(again))) return r;
+            if (!again) break;
+        }
+        return GDF_OK;
+    }
+    gdf_status q;
+    if ((q = mixed_iterate(R, x.gs_dtype, x.gs, x.go_dtype, x.go, nullptr))) return q;
     {
         ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
         HIP_TRY(launch_finalize64(x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
-                                  R.u64tab, 0, R.desc, R.s));
+                                  R.u64tab, R.st, R.desc, R.s));
     }
     return GDF_OK;
 }
@@ -1003,7 +1052,12 @@ size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_
 
 size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
 {
-    return gdf_solve_workspace_size(n, d, opts);
+    // FP32 adjoints run inside FP64 refinement (see solve_slices_backward)
+    gdf_solve_opts o;
+    std::memset(&o, 0, sizeof o);
+    if (opts) o = *opts;
+    if (o.precision != GDF_PREC_FP64) o.precision = GDF_PREC_MIXED;
+    return gdf_solve_workspace_size(n, d, &o);
 }
 
 gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
@@ -1113,9 +1167,12 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     gdf_status r;
     if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
     if (dtype != GDF_F32 && dtype != GDF_F64) return set_err(GDF_EINVAL, "dtype must be GDF_F32 or GDF_F64");
-    if (o.prec == GDF_PREC_MIXED) return set_err(GDF_EUNSUPPORTED, "the adjoint solve runs in FP32 or FP64");
     if ((dtype == GDF_F64) != (o.prec == GDF_PREC_FP64))
-        return set_err(GDF_EINVAL, "dtype must match opts.precision (F32 <-> FP32, F64 <-> FP64)");
+        return set_err(GDF_EINVAL, "dtype must match opts.precision (F32 <-> FP32 or MIXED, F64 <-> FP64)");
+    // FP32 data: the adjoint right-hand side grad_f is typically rough and its
+    // solution has large smooth components, beyond what an FP32 iterate can
+    // resolve to tol; it is solved with FP32 V-cycles inside FP64 refinement
+    if (dtype == GDF_F32) o.prec = GDF_PREC_MIXED;
     if (!grad_f || !f || !gs) return set_err(GDF_EINVAL, "grad_f, f and gs must be non-null");
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
     Plan P;
@@ -1136,11 +1193,15 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_BB, 0))) return r;
     if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_INIT, 0))) return r;
     if ((r = R.finish(R.r_tiles, nullptr, R.partd3, FIN_MEAN, 0))) return r;
-    if ((r = R.iterate(P.fp64))) return r;
+    if (P.mixed) {
+        if ((r = mixed_iterate(R, dtype, nullptr, GDF_F32, nullptr, grad_f))) return r;
+    } else {
+        if ((r = R.iterate(P.fp64))) return r;
+    }
     {
         ProfScope ps(PC_ADJOINT, 0.0, s, false);
         HIP_TRY(launch_adjoint_assemble(P.fp64, gs, f, grad_gs, grad_go, R.io, n, P.n_tiles, R.desc, R.st,
-                                        R.partd, s));
+                                        P.mixed ? R.u64tab : nullptr, R.partd, s));
     }
     if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_SUM, 0))) return r;
     std::vector<SliceState> h(n);

@@ -49,6 +49,8 @@ struct StripLaunch {
     const Item *items;
     int n_items;
     int in_sel, out_sel;     // which u buffer is read / written
+    const int *cycles;       // if non-null: read buffer (cycles[slice] & 1), write the other
+    int cycles_stride;       // ints between consecutive slices' counters
     const int *active;       // per-slice "still iterating" flags
     float2 *partials;        // per-item partial sums (r^2, r) (RES_NORM / RES_BOTH)
 };
@@ -141,10 +143,13 @@ hipError_t launch_prep_adjoint(bool fp64, const void *grad_f, const SliceIO *io_
 
 // From lambda (level-0 iterate): grad_gs = alpha lambda, grad_go = L lambda,
 // partials of lambda . (g_s - f).  Buffers share the dtype of the solve.
+// With u64 non-null, lambda is the FP64 iterate of the mixed solve (buffer
+// state[s].cycles & 1) instead of the level-0 working-precision iterate.
 hipError_t launch_adjoint_assemble(bool fp64, const void *gs, const void *f, void *grad_gs,
                                    void *grad_go, const SliceIO *io_dev, int n_slices,
                                    long long n_tiles, const LevelDesc *levs,
-                                   const SliceState *state, double *part_da, hipStream_t s);
+                                   const SliceState *state, double *const *u64, double *part_da,
+                                   hipStream_t s);
 
 // Mixed precision refinement step: u64_out = u64_in + e (e = level-0 FP32
 // iterate, buffer e_sel; skipped when first), r = alpha (g_s - g_o) - A u64_out
@@ -152,6 +157,8 @@ hipError_t launch_adjoint_assemble(bool fp64, const void *gs, const void *f, voi
 struct RefineArgs {
     int gs_dtype, go_dtype;
     const void *gs, *go;
+    const void *rhs;         // if non-null: b = rhs (dtype gs_dtype, indexed like f) instead of
+                             // alpha (g_s - g_o) -- the adjoint system A lambda = grad_f
     const SliceIO *io;
     int n_slices;
     long long n_tiles;
@@ -164,10 +171,11 @@ struct RefineArgs {
 };
 hipError_t launch_refine(const RefineArgs &a, hipStream_t s);
 
-// Mixed precision output: f = g_o + u64 (buffer sel).
+// Mixed precision output: f = g_o + u64 (buffer state[s].cycles & 1).
 hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *f,
                              const SliceIO *io_dev, int n_slices, long long n_tiles,
-                             double *const *u64, int sel, const LevelDesc *levs, hipStream_t s);
+                             double *const *u64, const SliceState *state, const LevelDesc *levs,
+                             hipStream_t s);
 
 // ---- smoothing ------------------------------------------------------------
 

@@ -158,8 +158,13 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
     // FP32 rounding); the mean is added back when f is formed
     const T bsh = bshift_p ? (T)*bshift_p : T(0);
     // (selects, not a runtime index into the descriptor's array: that would spill it)
-    const T *__restrict__ usrc = static_cast<const T *>(a.in_sel ? L.u[1] : L.u[0]);
-    T *__restrict__ udst = static_cast<T *>(a.out_sel ? L.u[1] : L.u[0]);
+    int in_sel = a.in_sel, out_sel = a.out_sel;
+    if (a.cycles) {   // per-slice parity: the latest iterate sits in buffer cycles & 1
+        in_sel = a.cycles[(size_t)L.slice * a.cycles_stride] & 1;
+        out_sel = in_sel ^ 1;
+    }
+    const T *__restrict__ usrc = static_cast<const T *>(in_sel ? L.u[1] : L.u[0]);
+    T *__restrict__ udst = static_cast<T *>(out_sel ? L.u[1] : L.u[0]);
 
     // ---- prolongation state (coarse column lc = cx0 / 2)
     const int lc = cx0 >> 1;

@@ -310,21 +310,12 @@ hipError_t launch_prep_adjoint(bool fp64, const void *grad_f, const SliceIO *io_
 
 // lambda = A^{-1} grad_f (level-0 iterate): grad_gs = alpha lambda,
 // grad_go = L lambda, partials of lambda . (g_s - f).
-template <typename T>
-__global__ __launch_bounds__(256) void adjoint_kernel(const T *gs, const T *f, T *ggs, T *ggo,
-                                                      const SliceIO *io, int n, long long n_tiles,
-                                                      const LevelDesc *levs, const SliceState *st,
-                                                      double *part_da)
+template <typename T, typename TL>
+__device__ __forceinline__ void adjoint_tile(const TL *lam, double shift, const T *gs, const T *f,
+                                             T *ggs, T *ggo, const TileCtx &c, int pl, double &sda)
 {
-    __shared__ double red[256];
-    TileCtx c;
-    if (!tile_ctx(io, n, n_tiles, c)) return;
     const SliceIO &P = c.P;
-    const LevelDesc &L = levs[P.lev0];
-    const T *lam = static_cast<const T *>(L.u[st[c.si].cycles & 1]);
-    const double shift = st[c.si].shift + st[c.si].uoff;   // constant parts of lambda
-    const int pl = L.pitch, x = c.x;
-    double sda = 0.0;
+    const int x = c.x;
     for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
         const int y = c.ty0 + r;
         if (y >= P.H || x >= P.W) continue;
@@ -341,20 +332,42 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const T *gs, const T *f, T
         if (ggo) ggo[fo] = (T)lap;
         sda += l * ((double)gs[P.off_gs + (long long)y * P.pitch_gs + x] - (double)f[fo]);
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adjoint_kernel(const T *gs, const T *f, T *ggs, T *ggo,
+                                                      const SliceIO *io, int n, long long n_tiles,
+                                                      const LevelDesc *levs, const SliceState *st,
+                                                      double *const *u64, double *part_da)
+{
+    __shared__ double red[256];
+    TileCtx c;
+    if (!tile_ctx(io, n, n_tiles, c)) return;
+    const SliceIO &P = c.P;
+    const LevelDesc &L = levs[P.lev0];
+    const int par = st[c.si].cycles & 1;
+    double sda = 0.0;
+    if (u64) {
+        adjoint_tile<T, double>(u64[par * n + c.si], 0.0, gs, f, ggs, ggo, c, L.pitch, sda);
+    } else {
+        const T *lam = static_cast<const T *>(L.u[par]);
+        const double shift = st[c.si].shift + st[c.si].uoff;   // constant parts of lambda
+        adjoint_tile<T, T>(lam, shift, gs, f, ggs, ggo, c, L.pitch, sda);
+    }
     const double t = block_sum(sda, red);
     if (threadIdx.x == 0) part_da[blockIdx.x] = t;
 }
 
 hipError_t launch_adjoint_assemble(bool fp64, const void *gs, const void *f, void *ggs, void *ggo,
                                    const SliceIO *io_dev, int n, long long n_tiles,
-                                   const LevelDesc *levs, const SliceState *st, double *part_da,
-                                   hipStream_t s)
+                                   const LevelDesc *levs, const SliceState *st, double *const *u64,
+                                   double *part_da, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (fp64)
-        hipLaunchKernelGGL(adjoint_kernel<double>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const double *)gs, (const double *)f, (double *)ggs, (double *)ggo, io_dev, n, n_tiles, levs, st, part_da);
+        hipLaunchKernelGGL(adjoint_kernel<double>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const double *)gs, (const double *)f, (double *)ggs, (double *)ggo, io_dev, n, n_tiles, levs, st, u64, part_da);
     else
-        hipLaunchKernelGGL(adjoint_kernel<float>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const float *)gs, (const float *)f, (float *)ggs, (float *)ggo, io_dev, n, n_tiles, levs, st, part_da);
+        hipLaunchKernelGGL(adjoint_kernel<float>, dim3((unsigned)n_tiles), dim3(256), 0, s, (const float *)gs, (const float *)f, (float *)ggs, (float *)ggo, io_dev, n, n_tiles, levs, st, u64, part_da);
     return hipGetLastError();
 }
 
@@ -389,9 +402,15 @@ __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a)
             if (x < W - 1) acc += uc - val(p + 1);
             if (y > 0) acc += uc - val(p - pl);
             if (y < H - 1) acc += uc - val(p + pl);
-            const double sv = (double)gs[P.off_gs + (long long)y * P.pitch_gs + x];
-            const double o = (double)go[P.off_go + (long long)y * P.pitch_go + x];
-            const double res = P.alpha * (sv - o) - P.alpha * uc - acc;
+            double bval;
+            if (a.rhs) {
+                bval = (double)static_cast<const TS *>(a.rhs)[P.off_f + (long long)y * P.pitch_f + x];
+            } else {
+                const double sv = (double)gs[P.off_gs + (long long)y * P.pitch_gs + x];
+                const double o = (double)go[P.off_go + (long long)y * P.pitch_go + x];
+                bval = P.alpha * (sv - o);
+            }
+            const double res = bval - P.alpha * uc - acc;
             uout[p] = uc;
             rdst[p] = (float)res;
             srr += res * res;
@@ -426,12 +445,13 @@ hipError_t launch_refine(const RefineArgs &a, hipStream_t s)
 template <typename TO, typename TF>
 __global__ __launch_bounds__(256) void finalize64_kernel(const TO *go, TF *f, const SliceIO *io,
                                                          int n, long long n_tiles,
-                                                         double *const *u64, int sel, const LevelDesc *levs)
+                                                         double *const *u64, const SliceState *st,
+                                                         const LevelDesc *levs)
 {
     TileCtx c;
     if (!tile_ctx(io, n, n_tiles, c)) return;
     const SliceIO &P = c.P;
-    const double *u = u64[sel * n + c.si];
+    const double *u = u64[(st[c.si].cycles & 1) * n + c.si];   // latest FP64 iterate
     const int pl = levs[P.lev0].pitch;
     for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
         const int y = c.ty0 + r;
@@ -442,12 +462,12 @@ __global__ __launch_bounds__(256) void finalize64_kernel(const TO *go, TF *f, co
 }
 
 hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *f,
-                             const SliceIO *io, int n, long long nt, double *const *u64, int sel,
-                             const LevelDesc *levs, hipStream_t s)
+                             const SliceIO *io, int n, long long nt, double *const *u64,
+                             const SliceState *st, const LevelDesc *levs, hipStream_t s)
 {
     if (nt <= 0) return hipSuccess;
     const dim3 g((unsigned)nt), b(256);
-#define GDF_F64(TO, TF) hipLaunchKernelGGL((finalize64_kernel<TO, TF>), g, b, 0, s, (const TO *)go, (TF *)f, io, n, nt, u64, sel, levs)
+#define GDF_F64(TO, TF) hipLaunchKernelGGL((finalize64_kernel<TO, TF>), g, b, 0, s, (const TO *)go, (TF *)f, io, n, nt, u64, st, levs)
     if (out_dtype == 2) {
         if (go_dtype == 0) GDF_F64(uint8_t, double); else if (go_dtype == 1) GDF_F64(float, double); else GDF_F64(double, double);
     } else {

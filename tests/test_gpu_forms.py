@@ -1,0 +1,178 @@
+"""GPU checks of the three solver forms beside the plain solve -- FP64
+iterative refinement around FP32 V-cycles, the adjoint solve behind the
+autograd function, graph-captured uneven batches -- and of the plain solve at
+the full 64 x 2048 x 2048 benchmark size (sampled against the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1506_02079_amd as gdf
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+# ------------------------------------------------------------------ mixed
+
+@pytest.mark.parametrize("shape,alpha", [((4, 300, 257), 0.001), ((3, 256, 256), 0.01)])
+def test_mixed_precision_reaches_1e8(shape, alpha):
+    stack = synth.make_stack(*shape, seed=21 + shape[1], ramp=True)
+    print("mixed", shape, alpha, flush=True)
+    f, rep, gsm = gdf.fuse_stack(torch.from_numpy(stack).to(DEV), alpha, tol=1e-8,
+                                 precision="mixed", return_smooth=True)
+    f = f.cpu().numpy()
+    assert f.dtype == np.float64
+    gsm = gsm.cpu().numpy().astype(np.float64)
+    f_ref = oracle.solve_stack(gsm, stack.astype(np.float64), alpha, tol=1e-13)
+    err = np.abs(f - f_ref).max()
+    rel = [oracle.relres(f[j], gsm[j], stack[j].astype(np.float64), alpha) for j in range(shape[0])]
+    print("err", err, "rel", max(rel), [r["vcycles"] for r in rep])
+    assert max(rel) <= 1e-8 * 1.01
+    assert all(r["rel_residual"] <= 1e-8 for r in rep)
+    assert err <= 1e-4
+
+
+def test_mixed_solve_slices_float_inputs():
+    gs, go = zip(*[(s, o.astype(np.float32)) for o, s in
+                   (synth.batch_slice(H, W, 40 + H) for H, W in ((200, 300), (64, 64)))])
+    tg = [torch.from_numpy(a).to(DEV) for a in gs]
+    to = [torch.from_numpy(a).to(DEV) for a in go]
+    f, rep = gdf.solve_slices(tg, to, [0.005, 0.05], tol=1e-9, precision="mixed")
+    for i, a in enumerate((0.005, 0.05)):
+        fr = oracle.solve(gs[i], go[i], a, tol=1e-13)
+        assert np.abs(f[i].cpu().numpy() - fr).max() <= 1e-5
+        assert oracle.relres(f[i].cpu().numpy(), gs[i], go[i], a) <= 1.01e-9
+
+
+# ---------------------------------------------------------------- adjoint
+
+def _adj_data(S, H, W, seed):
+    stack = synth.make_stack(S, H, W, seed=seed)
+    go = stack.astype(np.float64)
+    gs = oracle.smooth(stack)
+    t = np.random.default_rng(seed).uniform(0, 255, size=go.shape)
+    return gs, go, t
+
+
+@pytest.mark.parametrize("dtype,tol,rtol", [(torch.float64, 1e-11, 1e-7), (torch.float32, 1e-6, 2e-3)])
+def test_adjoint_matches_oracle(dtype, tol, rtol):
+    gs, go, t = _adj_data(3, 96, 130, 5)
+    alpha = 0.01
+    f = oracle.solve_stack(gs, go, alpha, tol=1e-13)
+    gbar = 2 * (f - t)
+    T = lambda a: torch.from_numpy(a).to(DEV, dtype)
+    dgs, dgo, da, rep = gdf.solve_slices_backward(T(gbar), T(f), T(gs), alpha, tol=tol)
+    for j in range(3):
+        r_gs, r_go, r_a = oracle.adjoint(gbar[j], gs[j], f[j], alpha, tol=1e-13)
+        scale = np.abs(r_gs).max()
+        assert np.abs(dgs[j].cpu().numpy() - r_gs).max() <= rtol * scale
+        assert np.abs(dgo[j].cpu().numpy() - r_go).max() <= rtol * np.abs(r_go).max()
+        assert abs(float(da[j]) - r_a) <= rtol * abs(r_a) * 10
+        assert rep[j]["rel_residual"] <= tol
+
+
+def test_adjoint_central_differences():
+    # loss = sum (f - t)^2 with the GPU FP64 solve; eps = 1e-3 at 32 voxels.
+    # f is affine in g_s and g_o, so central differences are exact up to rounding.
+    gs, go, t = _adj_data(2, 64, 80, 9)
+    alpha = 0.01
+    G = lambda a: torch.from_numpy(a).to(DEV)
+    solve = lambda s, o: gdf.solve_slices(G(s), G(o), alpha, tol=1e-13, precision="fp64",
+                                          max_vcycles=200)[0].cpu().numpy()
+    f = solve(gs, go)
+    dgs, dgo, da, _ = gdf.solve_slices_backward(G(2 * (f - t)), G(f), G(gs), alpha, tol=1e-12)
+    dgs, dgo = dgs.cpu().numpy(), dgo.cpu().numpy()
+    rng = np.random.default_rng(3)
+    eps = 1e-3
+    for _ in range(32):
+        j, y, x = rng.integers(0, 2), rng.integers(0, 64), rng.integers(0, 80)
+        for which, grad in (("gs", dgs), ("go", dgo)):
+            p, m = (gs.copy(), gs.copy()) if which == "gs" else (go.copy(), go.copy())
+            p[j, y, x] += eps
+            m[j, y, x] -= eps
+            fp = solve(p, go) if which == "gs" else solve(gs, p)
+            fm = solve(m, go) if which == "gs" else solve(gs, m)
+            fd = np.sum((fp - fm) * (fp + fm - 2 * t)) / (2 * eps)
+            assert abs(fd - grad[j, y, x]) <= 1e-5 * max(1.0, abs(grad[j, y, x])), (which, fd, grad[j, y, x])
+
+
+def test_autograd_gradcheck():
+    torch.manual_seed(0)
+    gs = (torch.rand(2, 8, 8, dtype=torch.float64, device=DEV) * 255).requires_grad_()
+    go = (torch.rand(2, 8, 8, dtype=torch.float64, device=DEV) * 255).requires_grad_()
+    alpha = torch.tensor(0.05, dtype=torch.float64, device=DEV, requires_grad=True)
+    fn = lambda a, b, c: gdf.ScreenedPoissonSolve.apply(a, b, c, 1e-13)
+    assert torch.autograd.gradcheck(fn, (gs, go, alpha), eps=1e-4, atol=1e-6, rtol=1e-5)
+
+
+def test_autograd_loss_backward_fp32():
+    stack = synth.make_stack(4, 128, 96, seed=77)
+    gs = torch.from_numpy(oracle.smooth(stack).astype(np.float32)).to(DEV).requires_grad_()
+    go = torch.from_numpy(stack.astype(np.float32)).to(DEV).requires_grad_()
+    alpha = torch.tensor(0.01, device=DEV, requires_grad=True)
+    tgt = torch.rand(4, 128, 96, device=DEV) * 255
+    f = gdf.ScreenedPoissonSolve.apply(gs, go, alpha)
+    ((f - tgt) ** 2).sum().backward()
+    f64 = oracle.solve_stack(gs.detach().cpu().double().numpy(), stack.astype(np.float64), 0.01,
+                             tol=1e-13)
+    gbar = 2 * (f64 - tgt.cpu().double().numpy())
+    da = 0.0
+    for j in range(4):
+        r_gs, r_go, r_a = oracle.adjoint(gbar[j], gs.detach().cpu().double().numpy()[j], f64[j], 0.01)
+        assert np.abs(gs.grad[j].cpu().numpy() - r_gs).max() <= 2e-3 * np.abs(r_gs).max()
+        assert np.abs(go.grad[j].cpu().numpy() - r_go).max() <= 2e-3 * np.abs(r_go).max()
+        da += r_a
+    assert abs(float(alpha.grad) - da) <= 5e-3 * abs(da)
+
+
+# ----------------------------------------------------------- uneven batch
+
+def test_graph_uneven_batch_moderate():
+    desc = synth.uneven_batch(24, seed=2, max_side=1536)
+    pairs = [synth.batch_slice(H, W, sd) for H, W, _, sd in desc]
+    al = [a for _, _, a, _ in desc]
+    tg = [torch.from_numpy(s).to(DEV) for _, s in pairs]
+    to = [torch.from_numpy(o).to(DEV) for o, _ in pairs]
+    f1, rep1 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, max_vcycles=16)
+    f2, rep2 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, max_vcycles=16)   # replay
+    f3, rep3 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=False, max_vcycles=16)
+    for i in range(len(desc)):
+        assert torch.equal(f1[i], f2[i])
+        assert torch.equal(f1[i], f3[i])
+        assert rep1[i]["rel_residual"] <= 1e-6 and rep1[i]["status"] == gdf.GDF_OK
+    for i in (0, 7, 23):
+        o, s = pairs[i]
+        fr = oracle.solve(s, o.astype(np.float64), al[i], tol=1e-11)
+        err = np.abs(f1[i].cpu().numpy() - fr).max()
+        print(desc[i], "err", err)
+        assert err <= 1e-3
+
+
+# ------------------------------------------------------ full benchmark size
+
+def test_full_size_plain_fp32_sampled():
+    S, H, W, alpha = 64, 2048, 2048, 0.01
+    stack = synth.make_stack(S, H, W, seed=1001, ramp=True)
+    print("generated", flush=True)
+    f, rep, gsm = gdf.fuse_stack(torch.from_numpy(stack).to(DEV), alpha, tol=1e-6,
+                                 return_smooth=True)
+    assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep)
+    rng = np.random.default_rng(0)
+    # smoothing at sampled voxels, edges and corners included
+    pts = np.stack([rng.integers(0, n, 4000) for n in (S, H, W)], axis=1)
+    pts[:8] = [[0, 0, 0], [S - 1, H - 1, W - 1], [0, H - 1, 0], [S - 1, 0, W - 1],
+               [5, 0, 100], [60, 2047, 5], [30, 1000, 0], [31, 7, 2047]]
+    ref = oracle.smooth_points(stack, pts)
+    got = gsm.cpu().numpy()[pts[:, 0], pts[:, 1], pts[:, 2]]
+    assert np.abs(got - ref).max() <= 2e-4
+    # whole slices through the oracle (edge slice and a middle one)
+    for z in (0, 37):
+        yy, xx = np.mgrid[0:H, 0:W]
+        p = np.stack([np.full(H * W, z), yy.ravel(), xx.ravel()], axis=1)
+        gs_z = oracle.smooth_points(stack, p).reshape(H, W)
+        fz = oracle.solve(gs_z, stack[z].astype(np.float64), alpha, tol=1e-10)
+        err = np.abs(f[z].cpu().numpy().astype(np.float64) - fz).max()
+        print("slice", z, "max abs err", err, rep[z], flush=True)
+        assert err <= 1e-3
