@@ -74,6 +74,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nu", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run plain 1 GiB device copies (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slices are "
@@ -95,6 +97,16 @@ def main():
     for _ in range(args.warmup):
         f, rep = gdf.fuse_stack(st, ALPHA, **kw)
     torch.cuda.synchronize()
+
+    if args.calib_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale
+        # the counters of the solver kernels to bytes
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     gdf.profile_reset()
     gdf.profile_enable(True)

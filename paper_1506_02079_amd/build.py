@@ -19,7 +19,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdf.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["mg_kernels.hip", "tile_kernels.hip", "smooth_kernel.hip", "api.cpp"]
+SOURCES = ["smooth_rz_c.hip", "mg_kernels.hip", "smooth_rz_a.hip", "smooth_rz_b.hip",
+           "smooth_rz_d.hip", "tile_kernels.hip", "smooth_kernel.hip", "api.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("GDF_OFFLOAD_ARCH", "gfx950")
@@ -39,7 +40,7 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 4) -> str:
+def build(jobs: int = 8) -> str:
     """Compile all sources and link libgdf.so; returns the library path."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:

@@ -35,10 +35,11 @@ struct LevelDesc {
 // A strip work item: one wave processes columns [x0 - G, x0 - G + 128) of
 // rows [y0 - G, y1 + G) and owns output columns [x0, x0 + 128 - 2G) x rows [y0, y1).
 struct Item {
-    int lev;  // index into the LevelDesc table
+    int lev;   // index into the LevelDesc table
     int x0;
     int y0;
     int y1;
+    int pidx;  // slot of this item's partial sums (a slice's slots are contiguous)
 };
 
 enum ResidMode { RES_NONE = 0, RES_NORM = 1, RES_RESTRICT = 2, RES_BOTH = 3 };
@@ -72,8 +73,12 @@ enum StripKind {
 // rounded up to even.  Valid output width per strip is 128 - 2G.
 int strip_halo(StripKind k, int nu);
 
-// Enqueue one strip pass.  fp64 selects double precision.
-hipError_t launch_strip(StripKind k, int nu, bool fp64, const StripLaunch &a, hipStream_t s);
+// Enqueue one strip pass.  fp64 selects double precision.  fast: every item
+// of the list stays clear of the slice's edges (rows y0 - G .. y1 + G in
+// [1, H - 2], columns x0 - G .. x0 - G + 127 in [1, W - 2]), so the kernel
+// variant without row guards and edge masks runs.
+hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, const StripLaunch &a,
+                        hipStream_t s);
 
 // ---- per-slice reductions and flags ------------------------------------
 
@@ -131,10 +136,11 @@ hipError_t launch_prep(bool fp64, int gs_dtype, const void *gs, int go_dtype, co
 
 // f = g_o + u (out dtype), FP64 partials of ||b_u - A u||^2 per tile.  The
 // level-0 iterate of slice s is buffer (state[s].cycles & 1).
+// With `only` non-null, tiles of slices with only[s] == 0 are skipped.
 hipError_t launch_finalize(bool fp64, int go_dtype, const void *go, int out_dtype, void *f,
                            const SliceIO *io_dev, int n_slices, long long n_tiles,
-                           const LevelDesc *levs, const SliceState *state, double *part_rr,
-                           hipStream_t s);
+                           const LevelDesc *levs, const SliceState *state, const int *only,
+                           double *part_rr, hipStream_t s);
 
 // Adjoint right-hand side: b = grad_f (converted), partials of ||grad_f||^2 and sum(grad_f).
 hipError_t launch_prep_adjoint(bool fp64, const void *grad_f, const SliceIO *io_dev, int n_slices,

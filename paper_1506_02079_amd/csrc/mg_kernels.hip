@@ -55,9 +55,14 @@ __device__ __forceinline__ double wave_shl1(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <typename T> struct Vec2;
-template <> struct Vec2<float> { using type = float2; };
-template <> struct Vec2<double> { using type = double2; };
+// Descriptor fields are generic pointers; naming the global address space
+// explicitly keeps loads/stores on the global (not flat) path, whose waits do
+// not stall on LDS/scalar traffic.
+#define GDF_GLOBAL __attribute__((address_space(1)))
+
+// native two-element vector (loads/stores through a global-address-space
+// pointer as one vector access)
+template <typename T> struct Vec2 { typedef T type __attribute__((ext_vector_type(2))); };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -73,18 +78,38 @@ __device__ __forceinline__ int xcd_logical_block()
 
 // ------------------------------------------------------------ strip pass ---
 
+// length of the load queue for a register ring of rs rows (a divisor of rs, so
+// that queue slots are compile-time constants in the unrolled ring loop)
+constexpr int queue_len(int rs)
+{
+    for (int q = 6; q >= 2; --q)
+        if (rs % q == 0) return q;
+    return 1;
+}
+
 template <bool PROLONG, int NHS, int RMODE> struct StripShape {
     static constexpr int NS = NHS + (RMODE != RES_NONE ? 1 : 0);  // stages after the load
     static constexpr int G = (NS + (PROLONG ? 1 : 0) + 1) & ~1;   // halo, even
     static constexpr int VW = kStripCols - 2 * G;                  // owned columns
     static constexpr int RS = 2 * NS + 2;                          // register ring rows
+    // loads run Q - 1 rows ahead of the row entering the ring, so each wave keeps
+    // several rows of HBM reads in flight
+    static constexpr int Q = queue_len(RS);
 };
 
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
+// FAST: the item's rows y0 - G .. y1 + G all lie in [1, H - 2] and its columns
+// x0 - G .. x0 - G + 127 in [1, W - 2] (no slice edge inside).  Then every
+// stage runs on every step with no row guards: a row outside a stage's cone of
+// validity ([y0 - G + s, y1 + G - s) at stage s) gets a finite throwaway value,
+// and no row inside the cone ever reads one (the cones are nested), so the
+// owned rows come out exactly as in the guarded variant.  Interior rows also
+// fix the vertical coefficients.
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
     using Sh = StripShape<PROLONG, NHS, RMODE>;
-    constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS;
+    constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS, Q = Sh::Q;
+    static_assert((RS & 1) == 0 && RS % Q == 0, "ring slots and queue slots must be static");
     using V2 = typename Vec2<T>::type;
 
     const int lane = threadIdx.x & (kWave - 1);
@@ -93,7 +118,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
     const Item it = a.items[item_id];
     const LevelDesc L = a.levs[it.lev];
     if (!a.active[L.slice]) {
-        if ((RMODE & RES_NORM) && lane == 0) a.partials[item_id] = make_float2(0.f, 0.f);
+        if ((RMODE & RES_NORM) && lane == 0) a.partials[it.pidx] = make_float2(0.f, 0.f);
         return;
     }
     // copy what is used into scalars (a by-reference lambda capture of the
@@ -151,7 +176,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
         return RowC{T(1), T(1), T(1), gi00, gi10};
     };
 
-    const T *__restrict__ bsrc = static_cast<const T *>(L.b);
+    const GDF_GLOBAL T *__restrict__ bsrc = (const GDF_GLOBAL T *)L.b;
     const double *bshift_p = L.bshift;
     // level 0: the slice's mean right-hand side is removed on load, so the
     // iterate is the zero-mean part of the correction (smaller values, smaller
@@ -163,23 +188,24 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
         in_sel = a.cycles[(size_t)L.slice * a.cycles_stride] & 1;
         out_sel = in_sel ^ 1;
     }
-    const T *__restrict__ usrc = static_cast<const T *>(in_sel ? L.u[1] : L.u[0]);
-    T *__restrict__ udst = static_cast<T *>(out_sel ? L.u[1] : L.u[0]);
+    const GDF_GLOBAL T *__restrict__ usrc = (const GDF_GLOBAL T *)(in_sel ? L.u[1] : L.u[0]);
+    GDF_GLOBAL T *__restrict__ udst = (GDF_GLOBAL T *)(out_sel ? L.u[1] : L.u[0]);
 
     // ---- prolongation state (coarse column lc = cx0 / 2)
     const int lc = cx0 >> 1;
     const bool cin = PROLONG && lc >= 0 && lc < Wc;
     const int lcl = PROLONG ? min(max(lc, 0), Wc - 1) : 0;
     const bool ledge = lc == 0, redge = PROLONG && lc == Wc - 1;
-    const T *__restrict__ ecp = static_cast<const T *>(L.ec);
-    auto ld_coarse = [ecp, cin, lcl, Hc, pitch_c](int m) -> T {
+    const GDF_GLOBAL T *__restrict__ ecp = (const GDF_GLOBAL T *)L.ec;
+    // raw coarse value (clamped row and column: always a valid address)
+    auto ld_coarse = [ecp, lcl, Hc, pitch_c](int m) -> T {
         m = min(max(m, 0), Hc - 1);
-        return cin ? ecp[(size_t)m * pitch_c + lcl] : T(0);
+        return ecp[(size_t)m * pitch_c + lcl];
     };
 
     // ---- restriction state: a coarse cell's right-hand side is the sum of its
     // children's residuals (children outside the slice contribute zero)
-    T *__restrict__ bcp = static_cast<T *>(L.bc);
+    GDF_GLOBAL T *__restrict__ bcp = (GDF_GLOBAL T *)L.bc;
     T rpair = T(0);
 
     const int y0 = it.y0, y1 = it.y1;
@@ -191,13 +217,28 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 #pragma unroll
     for (int k = 0; k < RS; ++k) u[k][0] = u[k][1] = b[k][0] = b[k][1] = T(0);
 
-    T e_lo = T(0), e_hi = T(0), e_nx = T(0);
-    if (PROLONG) {
-        const int mb = ybase >> 1;
-        e_lo = ld_coarse(mb - 1);
-        e_hi = ld_coarse(mb);
-    }
     float nacc = 0.f, sacc = 0.f;
+
+    // ---- load queue: raw values of the rows ybase + t + 1 .. ybase + t + Q - 1,
+    // issued with clamped (always valid) addresses and consumed Q - 1 steps
+    // later, when the row enters the ring (masks and corrections applied there)
+    V2 qb[Q], qu[Q];
+    T qe0[Q], qe1[Q];   // coarse rows m and m -/+ 1 of the row (prolongation)
+    auto issue_row = [&](int tq, V2 &vb, V2 &vu, T &ve0, T &ve1) {
+        // past the last loaded row the queue re-reads that row (cache hits);
+        // outside the slice the row is clamped (the commit zeroes it)
+        const int yq = ybase + min(tq, NL - 1);
+        const size_t ro = (size_t)min(max(yq, 0), H - 1) * pitch + cxl;
+        vb = *reinterpret_cast<const GDF_GLOBAL V2 *>(bsrc + ro);
+        if (!ZERO) vu = *reinterpret_cast<const GDF_GLOBAL V2 *>(usrc + ro);
+        if (PROLONG) {
+            const int m = yq >> 1;
+            ve0 = ld_coarse(m);
+            ve1 = ld_coarse((yq & 1) ? m + 1 : m - 1);
+        }
+    };
+#pragma unroll
+    for (int q = 0; q < Q - 1; ++q) issue_row(q, qb[q], qu[q], qe0[q], qe1[q]);
 
     const int T_end = NL + 2 * NS;
     for (int tb = 0; tb < T_end; tb += RS) {
@@ -205,34 +246,44 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
         for (int k = 0; k < RS; ++k) {
             const int t = tb + k;
             // ------------------------------------------------ load (stage 0)
-            if (t < NL) {
+            // issue and commit are unconditional: a conditional consumer would let
+            // the compiler sink each load down to it and wait right there
+            issue_row(t + Q - 1, qb[(k + Q - 1) % Q], qu[(k + Q - 1) % Q], qe0[(k + Q - 1) % Q],
+                      qe1[(k + Q - 1) % Q]);
+            {
+                // rows past the loaded range enter the ring as throwaway copies: no
+                // stage inside its cone of validity reads them
                 const int y = ybase + t;
+                const int qs = k % Q;
                 T cor0 = T(0), cor1 = T(0);
                 if (PROLONG) {
-                    T V;
-                    if ((k & 1) == 0) {            // y even: coarse rows m-1 (lo), m (hi)
-                        V = T(0.75) * e_hi + T(0.25) * e_lo;
-                        e_nx = ld_coarse((y >> 1) + 1);
-                    } else {                        // y odd: coarse rows m (lo), m+1 (hi)
-                        e_lo = e_hi;
-                        e_hi = e_nx;
-                        V = T(0.75) * e_lo + T(0.25) * e_hi;
-                    }
+                    // cell-centred bilinear: 3/4 of the parent row plus 1/4 of the
+                    // next coarse row towards this fine row, then the same in x
+                    const T e0 = (FAST || cin) ? qe0[qs] : T(0), e1 = (FAST || cin) ? qe1[qs] : T(0);
+                    const T V = T(0.75) * e0 + T(0.25) * e1;
                     T VL = wave_shr1(V), VR = wave_shl1(V);
-                    VL = ledge ? V : VL;
-                    VR = redge ? V : VR;
+                    if (!FAST) {
+                        VL = ledge ? V : VL;
+                        VR = redge ? V : VR;
+                    }
                     cor0 = T(0.75) * V + T(0.25) * VL;
                     cor1 = T(0.75) * V + T(0.25) * VR;
                 }
-                if (y >= 0 && y < H) {
-                    const size_t ro = (size_t)y * pitch + cxl;
-                    const V2 bv = *reinterpret_cast<const V2 *>(bsrc + ro);
-                    b[k][0] = in0 ? bv.x - bsh : T(0);
-                    b[k][1] = in1 ? bv.y - bsh : T(0);
+                if (FAST) {
+                    b[k][0] = qb[qs].x - bsh;
+                    b[k][1] = qb[qs].y - bsh;
                     if (!ZERO) {
-                        const V2 uv = *reinterpret_cast<const V2 *>(usrc + ro);
-                        u[k][0] = in0 ? uv.x + cor0 : T(0);
-                        u[k][1] = in1 ? uv.y + cor1 : T(0);
+                        u[k][0] = qu[qs].x + cor0;
+                        u[k][1] = qu[qs].y + cor1;
+                    } else {
+                        u[k][0] = u[k][1] = T(0);
+                    }
+                } else if (y >= 0 && y < H) {
+                    b[k][0] = in0 ? qb[qs].x - bsh : T(0);
+                    b[k][1] = in1 ? qb[qs].y - bsh : T(0);
+                    if (!ZERO) {
+                        u[k][0] = in0 ? qu[qs].x + cor0 : T(0);
+                        u[k][1] = in1 ? qu[qs].y + cor1 : T(0);
                     } else {
                         u[k][0] = u[k][1] = T(0);
                     }
@@ -249,11 +300,11 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
                 const int y = ybase + t - 2 * s;
                 if (s <= NHS) {
                     const int lo = max(ybase + s, 0), hi = min(yend - s, H);
-                    if (y >= lo && y < hi) {
+                    if (FAST || (y >= lo && y < hi)) {
                         const int c = (s - 1) & 1;         // 0: red, 1: black
                         const int j = (k & 1) ^ c;         // column of that colour (y parity = k parity)
                         if (!GEN) {
-                            const int dy = (y > 0) + (y < H - 1);
+                            const int dy = FAST ? 2 : (y > 0) + (y < H - 1);
                             if (j == 0) {
                                 const T iv = dy == 2 ? inv0[2] : (dy == 1 ? inv0[1] : inv0[0]);
                                 const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
@@ -264,7 +315,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
                                 u[sl][1] = (b[sl][1] + nb) * iv;
                             }
                         } else {
-                            const RowC rc = row_coef(y);
+                            const RowC rc = FAST ? RowC{T(1), T(1), T(1), gi00, gi10} : row_coef(y);
                             if (j == 0) {
                                 const T h = fma(kl0, wave_shr1(u[sl][1]), kr0 * u[sl][1]);
                                 const T v = fma(rc.ku, u[su][0], rc.kd * u[sd][0]);
@@ -279,7 +330,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
                             V2 o;
                             o.x = u[sl][0];
                             o.y = u[sl][1];
-                            *reinterpret_cast<V2 *>(udst + (size_t)y * pitch + cx0) = o;
+                            *reinterpret_cast<GDF_GLOBAL V2 *>(udst + (size_t)y * pitch + cx0) = o;
                         }
                     }
                 } else if (RMODE != RES_NONE) {
@@ -290,7 +341,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
                         // (nearly) exact, so the residual stays accurate in FP32
                         T r0, rr1;
                         if (!GEN) {
-                            const T mu = y > 0 ? T(1) : T(0), md = y < H - 1 ? T(1) : T(0);
+                            const T mu = (FAST || y > 0) ? T(1) : T(0), md = (FAST || y < H - 1) ? T(1) : T(0);
                             T acc0 = ml0 * (uc0 - l0);
                             acc0 = fma(mr0, uc0 - uc1, acc0);
                             acc0 = fma(mu, uc0 - u[su][0], acc0);
@@ -302,7 +353,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
                             r0 = fma(-sig, uc0, b[sl][0]) - acc0;
                             rr1 = fma(-sig, uc1, b[sl][1]) - acc1;
                         } else {
-                            const RowC rc = row_coef(y);
+                            const RowC rc = FAST ? RowC{T(1), T(1), T(1), gi00, gi10} : row_coef(y);
                             const T wy = rc.wy, ku = rc.ku, kd = rc.kd;
                             const T h0 = fma(kl0, uc0 - l0, kr0 * (uc0 - uc1));
                             const T v0 = fma(ku, uc0 - u[su][0], kd * (uc0 - u[sd][0]));
@@ -344,7 +395,7 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
             v += __shfl_xor(v, off);
             w += __shfl_xor(w, off);
         }
-        if (lane == 0) a.partials[item_id] = make_float2((float)v, (float)w);
+        if (lane == 0) a.partials[it.pidx] = make_float2((float)v, (float)w);
     }
 }
 
@@ -364,35 +415,38 @@ int strip_halo(StripKind k, int nu)
 }
 
 template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
-static hipError_t go(const StripLaunch &a, hipStream_t s)
+static hipError_t go(const StripLaunch &a, bool fast, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
     const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
     const int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
-    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN>), dim3(grid), dim3(256), 0, s, a);
+    if (fast)
+        hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, true>), dim3(grid), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, false>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_strip_t(StripKind k, int nu, const StripLaunch &a, hipStream_t s)
+static hipError_t launch_strip_t(StripKind k, int nu, bool f, const StripLaunch &a, hipStream_t s)
 {
     const bool n1 = nu == 1;
     switch (k) {
-    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, s) : go<T, false, true, 4, RES_BOTH>(a, s);
-    case SK_FINE: return n1 ? go<T, true, false, 4, RES_BOTH>(a, s) : go<T, true, false, 8, RES_BOTH>(a, s);
-    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, s);
-    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, s) : go<T, true, false, 4, RES_NONE, true>(a, s);
-    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, s);
-    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, s);
-    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, s);
-    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, s);
+    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, f, s) : go<T, false, true, 4, RES_BOTH>(a, f, s);
+    case SK_FINE: return n1 ? go<T, true, false, 4, RES_BOTH>(a, f, s) : go<T, true, false, 8, RES_BOTH>(a, f, s);
+    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, f, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, f, s);
+    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, f, s) : go<T, true, false, 4, RES_NONE, true>(a, f, s);
+    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, f, s);
+    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, f, s);
+    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, f, s);
+    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, f, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_strip(StripKind k, int nu, bool fp64, const StripLaunch &a, hipStream_t s)
+hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, const StripLaunch &a, hipStream_t s)
 {
-    return fp64 ? launch_strip_t<double>(k, nu, a, s) : launch_strip_t<float>(k, nu, a, s);
+    return fp64 ? launch_strip_t<double>(k, nu, fast, a, s) : launch_strip_t<float>(k, nu, fast, a, s);
 }
 
 }  // namespace gdf

@@ -1,0 +1,260 @@
+// Anisotropic Gaussian smoothing of a uint8 stack across slices (Section
+// III-A), truncated at three standard deviations per axis (Implementation
+// subsection), renormalised over the taps that fall inside the stack.  The
+// kernel and the in-stack box are both products over the axes, so the
+// renormalised 3D sum factors into three 1D passes, each divided by its own
+// in-range weight sum.
+//
+// One workgroup owns a 64 x 16 tile of every slice and marches through the
+// stack.  While it blurs slice z along x and y, the raw tile of slice z + 1
+// (with an in-plane halo) is already in flight as 4-byte loads held in
+// registers; the raw tiles of the slices between the current output and input
+// slice stay in an LDS byte ring (they also give the Laplacian of the original
+// slice at output time, with no second read from HBM).  Blurred planes go into
+// a register ring of 2 rz + 1 planes; the z blur of an output slice is a
+// weighted sum over that ring.  The output is written straight into the
+// right-hand side of the solve, b_u = alpha (I1 - I0), together with per-wave
+// partial sums of ||alpha I1 + L I0||^2 (the norm of Eq. (1)'s right-hand
+// side), ||b_u||^2 and sum(b_u).  The smoothed stack is written only when asked.
+#pragma once
+#include "internal.h"
+
+namespace gdf {
+
+constexpr int kSTX = 64, kSTY = 16, kMaxRxy = 7;
+constexpr int kRawW = 80;                 // bytes per raw row: x in [X0 - 8, X0 + 72)
+constexpr int kRawDw = kRawW / 4;         // 20 dwords per raw row
+constexpr int kRawHMax = kSTY + 2 * kMaxRxy;
+constexpr int kPrefetch = (kRawHMax * kRawDw + 255) / 256;   // dwords per thread
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// One raw dword (pixels gx .. gx + 3 of row gy), zero outside the slice.
+__device__ __forceinline__ uint32_t load_raw_dword(const uint8_t *src, long long pitch, int H, int W,
+                                                   int gy, int gx, bool aligned)
+{
+    if (gy < 0 || gy >= H || gx + 3 < 0 || gx >= W) return 0u;
+    const uint8_t *row = src + (long long)gy * pitch;
+    if (aligned && gx >= 0 && gx + 3 < W) return *reinterpret_cast<const uint32_t *>(row + gx);
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (gx + i >= 0 && gx + i < W) v |= (uint32_t)row[gx + i] << (8 * i);
+    return v;
+}
+
+// RT: compile-time in-plane tap radius (>= the true radius; taps beyond it
+// carry zero weight), RZ: cross-slice tap radius.
+template <typename T, int RZ, int RT>
+__global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
+{
+    constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
+    constexpr int NRAW = RZ + 2;       // LDS ring of raw tiles: slices zo .. zi + 1
+    constexpr int RH = RT > 0 ? RT : 1;   // raw halo rows (>= 1 for the Laplacian of I0)
+    __shared__ uint32_t ring_raw[NRAW][kRawHMax * kRawDw];
+    __shared__ T hb[kRawHMax * kSTX];  // x-blurred rows of the current input slice
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, wv = tid >> 6;
+    const int tile = blockIdx.x;
+    const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
+    const int X0 = tile_x * kSTX, Y0 = tile_y * kSTY;
+    const int S = a.S, H = a.H, W = a.W, R = a.rxy;
+    constexpr int rawH = kSTY + 2 * RH;
+    const int n_dw = rawH * kRawDw;
+    const bool aligned = ((a.pitch_row & 3) == 0) && ((a.pitch_slice & 3) == 0) &&
+                         ((reinterpret_cast<uintptr_t>(a.stack) & 3) == 0);
+    const int x = X0 + tx;
+    const int yb = wv * 4;             // this thread's 4 output rows (tile-local)
+
+    T wxy[RT + 1];
+#pragma unroll
+    for (int d = 0; d <= RT; ++d) wxy[d] = d <= R ? (T)a.wxy[d] : T(0);
+    T wz[RZ + 1];
+#pragma unroll
+    for (int d = 0; d <= RZ; ++d) wz[d] = (T)a.wz[d];
+
+    // in-plane renormalisation 1 / (sum_x w * sum_y w) per output pixel
+    T wsx = T(0);
+    for (int d = -R; d <= R; ++d)
+        if (x + d >= 0 && x + d < W) wsx += wxy[d < 0 ? -d : d];
+    T inv_xy[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int y = Y0 + yb + i;
+        T wsy = T(0);
+        for (int d = -R; d <= R; ++d)
+            if (y + d >= 0 && y + d < H) wsy += wxy[d < 0 ? -d : d];
+        inv_xy[i] = T(1) / (wsx * wsy);
+    }
+
+    T ring[NZ][4];
+#pragma unroll
+    for (int k = 0; k < NZ; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ring[k][i] = T(0);
+
+    const T alT = (T)a.alpha;
+    const long long nparts = (long long)a.tiles_x * a.tiles_y * 4;
+
+    uint32_t pf[kPrefetch];   // raw tile of the next input slice, in flight
+    auto issue = [&](int zi) {
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            const int e = tid + q * 256;
+            pf[q] = 0u;
+            if (zi < S && e < n_dw) {
+                const int r = e / kRawDw, c = e - r * kRawDw;
+                pf[q] = load_raw_dword(a.stack + (long long)zi * a.pitch_slice, a.pitch_row, H, W,
+                                       Y0 - RH + r, X0 - 8 + 4 * c, aligned);
+            }
+        }
+    };
+    auto commit = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < kPrefetch; ++q) {
+            const int e = tid + q * 256;
+            if (e < n_dw) ring_raw[slot][e] = pf[q];
+        }
+    };
+    // raw byte at tile-local raw row r (row 0 = Y0 - RH) and byte column c (x = X0 - 8 + c)
+    auto raw_at = [&](int slot, int r, int c) -> float {
+        const uint32_t w = ring_raw[slot][r * kRawDw + (c >> 2)];
+        return (float)((w >> (8 * (c & 3))) & 0xffu);
+    };
+
+    issue(0);
+    commit(0);
+    __syncthreads();
+
+    for (int zb = 0; zb < S + RZ; zb += NZ) {
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+            const int zi = zb + k;   // input slice of this step (register ring slot k)
+            if (zi < S + RZ) {       // uniform across the block
+                const int islot = zi % NRAW;
+                issue(zi + 1);       // next raw tile: its latency is hidden by this step
+                // ------------- x blur of every raw row, 4 consecutive outputs per work item
+                if (zi < S) {
+                    for (int wi = tid; wi < rawH * 16; wi += 256) {
+                        const int r = wi >> 4, seg = (wi & 15) * 4;
+                        const uint32_t *rowp = &ring_raw[islot][r * kRawDw + (seg >> 2)];
+                        T v[20];   // v[j] = pixel X0 + seg - 8 + j
+#pragma unroll
+                        for (int q = 0; q < 5; ++q) {
+                            const uint32_t w = rowp[q];
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) v[4 * q + i] = (T)((w >> (8 * i)) & 0xffu);
+                        }
+#pragma unroll
+                        for (int o = 0; o < 4; ++o) {
+                            T acc = wxy[0] * v[8 + o];
+#pragma unroll
+                            for (int d = 1; d <= RT; ++d) acc += wxy[d] * (v[8 + o - d] + v[8 + o + d]);
+                            hb[r * kSTX + seg + o] = acc;
+                        }
+                    }
+                }
+                __syncthreads();
+                // ------------- y blur into the register ring
+                if (zi < S) {
+                    T col[4 + 2 * RT];   // col[j]: x-blurred raw row yb + RH - RT + j
+#pragma unroll
+                    for (int j = 0; j < 4 + 2 * RT; ++j) col[j] = hb[(yb + RH - RT + j) * kSTX + tx];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        T acc = wxy[0] * col[i + RT];
+#pragma unroll
+                        for (int d = 1; d <= RT; ++d) acc += wxy[d] * (col[i + RT - d] + col[i + RT + d]);
+                        ring[k][i] = acc * inv_xy[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ring[k][i] = T(0);
+                }
+                // ------------- output slice zo = zi - RZ
+                const int zo = zi - RZ;
+                if (zo >= 0) {
+                    T wsz = T(0);
+#pragma unroll
+                    for (int d = -RZ; d <= RZ; ++d)
+                        if (zo + d >= 0 && zo + d < S) wsz += wz[d < 0 ? -d : d];
+                    const T iz = T(1) / wsz;
+                    const int oslot = zo % NRAW;
+                    const LevelDesc &L = a.levs[(long long)zo * a.lev_stride];
+                    T *bdst = static_cast<T *>(L.b);
+                    T sbb = T(0), sb0 = T(0), sbs = T(0);
+                    // original slice around this thread's column
+                    float oc[6], ol[4], orr[4];
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) oc[j] = raw_at(oslot, yb + RH - 1 + j, tx + 8);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        ol[i] = raw_at(oslot, yb + RH + i, tx + 7);
+                        orr[i] = raw_at(oslot, yb + RH + i, tx + 9);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        // register slot of zo is k - RZ (mod NZ): static for each k
+                        T acc = wz[0] * ring[((k - RZ) % NZ + NZ) % NZ][i];
+#pragma unroll
+                        for (int d = 1; d <= RZ; ++d)
+                            acc += wz[d] * (ring[((k - RZ - d) % NZ + NZ) % NZ][i] +
+                                            ring[((k - RZ + d) % NZ + NZ) % NZ][i]);
+                        const int y = Y0 + yb + i;
+                        if (y < H && x < W) {
+                            const T g = acc * iz;
+                            const float o = oc[i + 1];
+                            float lap = 0.f;   // (L g_o)_p over in-slice neighbours
+                            if (x > 0) lap += o - ol[i];
+                            if (x < W - 1) lap += o - orr[i];
+                            if (y > 0) lap += o - oc[i];
+                            if (y < H - 1) lap += o - oc[i + 2];
+                            const T bu = alT * (g - (T)o);
+                            const T bf = alT * g + (T)lap;
+                            bdst[(size_t)y * L.pitch + x] = bu;
+                            if (a.gs_out) static_cast<T *>(a.gs_out)[((long long)zo * H + y) * W + x] = g;
+                            sbb += bf * bf;
+                            sb0 += bu * bu;
+                            sbs += bu;
+                        }
+                    }
+                    const double tbb = (double)wave_sum<T>(sbb), tb0 = (double)wave_sum<T>(sb0),
+                                 tbs = (double)wave_sum<T>(sbs);
+                    if ((tid & 63) == 0) {
+                        const long long pi = (long long)zo * nparts + tile * 4 + wv;
+                        a.part_bb[pi] = tbb;
+                        a.part_b0[pi] = tb0;
+                        a.part_bs[pi] = tbs;
+                    }
+                }
+                commit((zi + 1) % NRAW);   // no reader of that slot in this phase
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// Launch one (precision, radius) instance; defined per cross-slice radius in
+// the smooth_rz*.hip translation units so they compile in parallel.
+template <typename T, int RZ, int RT>
+hipError_t smooth_launch(const SmoothArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((smooth_kernel<T, RZ, RT>), dim3(a.tiles_x * a.tiles_y), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// All instances for one cross-slice radius RZ.
+#define GDF_SMOOTH_RZ(RZ)                                                                  \
+    hipError_t smooth_rz_##RZ(bool fp64, const SmoothArgs &a, hipStream_t s)               \
+    {                                                                                      \
+        if (fp64) return smooth_launch<double, RZ, kMaxRxy>(a, s);                         \
+        return a.rxy == 3 ? smooth_launch<float, RZ, 3>(a, s) : smooth_launch<float, RZ, kMaxRxy>(a, s); \
+    }
+
+}  // namespace gdf

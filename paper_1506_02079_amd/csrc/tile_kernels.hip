@@ -138,8 +138,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const TS *gs, const TO *go, c
     const double al = P.alpha;
     double sbb = 0.0, sb0 = 0.0, sbs = 0.0;
     T *bdst = static_cast<T *>(L.b);
-    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
-        const int y = c.ty0 + r;
+#pragma unroll
+    for (int r0 = 0; r0 < kTileH; r0 += 4) {
+        const int y = c.ty0 + r0 + (threadIdx.x >> 6);
         if (y >= P.H || x >= P.W) continue;
         const long long go_row = P.off_go + (long long)y * P.pitch_go;
         const double o = ldv(go, go_row + x);
@@ -202,11 +203,13 @@ template <typename T, typename TO, typename TF>
 __global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, const SliceIO *io,
                                                        int n_slices, long long n_tiles,
                                                        const LevelDesc *levs,
-                                                       const SliceState *st, double *part_rr)
+                                                       const SliceState *st, const int *only,
+                                                       double *part_rr)
 {
     __shared__ double red[256];
     TileCtx c;
     if (!tile_ctx(io, n_slices, n_tiles, c)) return;
+    if (only && !only[c.si]) return;   // uniform per block: keeps this slice's partial sum
     const SliceIO &P = c.P;
     const LevelDesc &L = levs[P.lev0];
     const int x = c.x;
@@ -218,8 +221,9 @@ __global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, cons
     const double shift = st[c.si].shift + st[c.si].uoff;
     const int pu = L.pitch;
     double srr = 0.0;
-    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
-        const int y = c.ty0 + r;
+#pragma unroll
+    for (int r0 = 0; r0 < kTileH; r0 += 4) {
+        const int y = c.ty0 + r0 + (threadIdx.x >> 6);
         if (y >= P.H || x >= P.W) continue;
         const size_t p = (size_t)y * pu + x;
         const double uc = (double)u[p] + shift;
@@ -239,31 +243,31 @@ __global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, cons
 
 template <typename T, typename TO>
 static hipError_t fin_go(int out_dtype, const void *go, void *f, const SliceIO *io, int n,
-                         long long nt, const LevelDesc *levs, const SliceState *st, double *prr,
-                         hipStream_t s)
+                         long long nt, const LevelDesc *levs, const SliceState *st, const int *only,
+                         double *prr, hipStream_t s)
 {
     const dim3 g((unsigned)nt), blk(256);
     if (out_dtype == 2)
-        hipLaunchKernelGGL((finalize_kernel<T, TO, double>), g, blk, 0, s, (const TO *)go, (double *)f, io, n, nt, levs, st, prr);
+        hipLaunchKernelGGL((finalize_kernel<T, TO, double>), g, blk, 0, s, (const TO *)go, (double *)f, io, n, nt, levs, st, only, prr);
     else
-        hipLaunchKernelGGL((finalize_kernel<T, TO, float>), g, blk, 0, s, (const TO *)go, (float *)f, io, n, nt, levs, st, prr);
+        hipLaunchKernelGGL((finalize_kernel<T, TO, float>), g, blk, 0, s, (const TO *)go, (float *)f, io, n, nt, levs, st, only, prr);
     return hipGetLastError();
 }
 
 hipError_t launch_finalize(bool fp64, int go_dtype, const void *go, int out_dtype, void *f,
                            const SliceIO *io_dev, int n, long long n_tiles,
-                           const LevelDesc *levs, const SliceState *st, double *part_rr,
-                           hipStream_t s)
+                           const LevelDesc *levs, const SliceState *st, const int *only,
+                           double *part_rr, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (fp64) {
-        if (go_dtype == 0) return fin_go<double, uint8_t>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, part_rr, s);
-        if (go_dtype == 1) return fin_go<double, float>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, part_rr, s);
-        return fin_go<double, double>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, part_rr, s);
+        if (go_dtype == 0) return fin_go<double, uint8_t>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+        if (go_dtype == 1) return fin_go<double, float>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+        return fin_go<double, double>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
     }
-    if (go_dtype == 0) return fin_go<float, uint8_t>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, part_rr, s);
-    if (go_dtype == 1) return fin_go<float, float>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, part_rr, s);
-    return fin_go<float, double>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, part_rr, s);
+    if (go_dtype == 0) return fin_go<float, uint8_t>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+    if (go_dtype == 1) return fin_go<float, float>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+    return fin_go<float, double>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
 }
 
 // ------------------------------------------------------------ adjoint ---
