@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -22,6 +23,8 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402  (seeded input generator)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 S, H, W = 64, 2048, 2048
@@ -34,15 +37,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(per_launch_px):
-    """HBM bytes per launch of the fused finest pass from committed rocprofv3
-    counter summaries, or None if the kernel source changed since."""
+def traffic_from_profile():
+    """HBM bytes per launch of the fused finest pass from the committed
+    rocprofv3 counter summary, or None if the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", "vcycle_fine_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1506_02079_amd", "csrc", "mg_kernels.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec.get("mg_kernels_sha256"):
+    if hashlib.sha256(open(MG_SRC, "rb").read()).hexdigest() != rec.get("mg_kernels_sha256"):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -66,6 +68,138 @@ def cpu_baseline(stack, z):
                       "unpreconditioned CG to rel. residual 1e-6 (%.1f s)" % (z, t1 - t0, t2 - t1)}
 
 
+# the fused finest pass (FP32): prolongation, no zero start, residual norm + restriction, unit stencil
+FINE_KERNEL_RE = r"strip_kernel<float, true, false, \d+, 3, false, (true|false)>"
+MG_SRC = os.path.join(ROOT, "paper_1506_02079_amd", "csrc", "mg_kernels.hip")
+
+
+def _counter_rows(d):
+    import csv
+    path = os.path.join(d, "run_counter_collection.csv")
+    return list(csv.DictReader(open(path)))
+
+
+def summarize_pmc(fetch_dir, write_dir, out_json, command):
+    """HBM bytes per launch of the fused finest pass from two rocprofv3 --pmc
+    runs of `bench.py --calib-copy` (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch).  Each counter is scaled by what it reads for the plain 1 GiB
+    device copies the run performs (3 copies of 2^30 bytes)."""
+    res = {}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ratio = sum(copy) / (3.0 * (1 << 30) / 1024.0)   # counter KiB per KiB copied
+        fine = [r for r in rows if re.search(FINE_KERNEL_RE, r["Kernel_Name"])]
+        # one fused pass = an unguarded and a guarded launch, in dispatch order
+        fine.sort(key=lambda r: int(r["Dispatch_Id"]))
+        vals = [float(r["Counter_Value"]) for r in fine]
+        passes = len(vals) // 2
+        kib = sum(vals[:2 * passes]) / max(1, passes)
+        res[name] = {"kib_per_pass": kib, "passes": passes, "copy_counter_ratio": ratio,
+                     "bytes_per_pass": kib * 1024.0 / ratio if ratio > 0 else None}
+    rd, wr = res["FETCH_SIZE"]["bytes_per_pass"], res["WRITE_SIZE"]["bytes_per_pass"]
+    rec = {"kernel": "vcycle_fine (strip_kernel SK_FINE, FP32; unguarded + guarded launch per pass)",
+           "workload": "fuse_stack 64 x 2048 x 2048, alpha 0.01, tol 1e-6",
+           "mg_kernels_sha256": hashlib.sha256(open(MG_SRC, "rb").read()).hexdigest(),
+           "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr,
+           "hbm_bytes_per_launch": (rd + wr) if rd and wr else None,
+           "counters": res, "command": command}
+    with open(out_json, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def _timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        out = fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, out
+
+
+def bench_batched(gdf, torch, dev, steps):
+    """512 uneven slices (sides 512..4096 step 256, alpha ~ U(0.001, 0.1)) in one
+    graph-captured solve_slices call, settings autotuned on the first call."""
+    desc = synth.uneven_batch(512, seed=synth.CONFIG_SEED[2])
+    log("batched: generating %d slices" % len(desc))
+    go, gs, al = [], [], []
+    for H, W, a, sd in desc:
+        o, s = synth.batch_slice_t(H, W, sd, dev)
+        go.append(o)
+        gs.append(s)
+        al.append(a)
+    px = float(sum(H * W for H, W, _, _ in desc))
+    kw = dict(tol=TOL, use_graph=True, autotune=True)
+    log("batched: autotuning")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gdf.solve_slices(gs, go, al, **kw)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    tuned = gdf.autotune_last()
+    log("batched: tuned %s in %.1f s; timing" % (tuned, t_tune))
+    ms, (f, rep) = _timed(torch, lambda: gdf.solve_slices(gs, go, al, **kw), steps, 1)
+    vc = [r["vcycles"] for r in rep]
+    return {"value": px / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+            "workload": "solve_slices: 512 uneven slices (H, W uniform on 512..4096 step 256, %.3f Gpx), "
+                        "alpha per slice U(0.001, 0.1), FP32, tol 1e-6, one captured graph per call" % (px / 1e9),
+            "autotuned": tuned, "autotune_s": t_tune,
+            "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+
+
+def bench_mixed(gdf, torch, dev, steps, alpha):
+    """4 slices of 21504 x 26624: FP32 V-cycles inside FP64 refinement to 1e-8."""
+    S3, H3, W3 = 4, 21504, 26624
+    log("mixed: generating %dx%dx%d" % (S3, H3, W3))
+    st = synth.make_stack_t(S3, H3, W3, synth.CONFIG_SEED[3], dev)
+    run = lambda: gdf.fuse_stack(st, alpha, tol=1e-8, precision="mixed")
+    log("mixed alpha=%g: timing" % alpha)
+    ms, (f, rep) = _timed(torch, run, steps, 1)
+    del f
+    vc = [r["vcycles"] for r in rep]
+    return {"value": S3 * H3 * W3 / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+            "workload": "fuse_stack mixed: 4 x 21504 x 26624 uint8, sigma_xy=1, sigma_z=3, alpha=%g, FP32 "
+                        "V-cycles (3 per refinement step) + FP64 residual/update to FP64 rel. residual 1e-8"
+                        % alpha,
+            "worst_rel_residual": max(r["rel_residual"] for r in rep), "inner_vcycles_min_max": [min(vc), max(vc)]}
+
+
+def bench_adjoint(gdf, torch, dev, steps):
+    """16 x 1024 x 1024 FP32: loss = sum (f - t)^2 through the autograd function."""
+    S4, H4, W4 = 16, 1024, 1024
+    stack = synth.make_stack_t(S4, H4, W4, synth.CONFIG_SEED[4], dev)
+    _, _, gsm = gdf.fuse_stack(stack, ALPHA, return_smooth=True)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.CONFIG_SEED[4])
+    tgt = torch.rand((S4, H4, W4), generator=gen, device=dev) * 255.0
+    gs = gsm.clone().requires_grad_()
+    go = stack.float().requires_grad_()
+    alpha = torch.tensor(ALPHA, device=dev, requires_grad=True)
+
+    def fwd():
+        return gdf.ScreenedPoissonSolve.apply(gs, go, alpha)
+
+    def fwd_bwd():
+        gs.grad = go.grad = alpha.grad = None
+        loss = ((fwd() - tgt) ** 2).sum()
+        loss.backward()
+        return loss
+
+    log("adjoint: timing")
+    ms_f, _ = _timed(torch, fwd, steps, 1)
+    ms_fb, _ = _timed(torch, fwd_bwd, steps, 1)
+    vox = S4 * H4 * W4
+    return {"value": vox / (ms_fb * 1e-3) / 1e6, "unit": "Mvoxels/s (forward + backward)",
+            "ms_per_step": ms_fb, "steps": steps, "forward_ms": ms_f, "backward_ms": ms_fb - ms_f,
+            "backward_Mvoxels_s": vox / ((ms_fb - ms_f) * 1e-3) / 1e6,
+            "workload": "ScreenedPoissonSolve on 16 x 1024 x 1024 FP32 (g_s = the method's smoothing), "
+                        "alpha=0.01, loss sum (f - t)^2; backward = adjoint solve (FP32 V-cycles in FP64 "
+                        "refinement) to 1e-6 + gradient assembly"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,9 +208,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nu", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the batched, mixed-precision and adjoint measurements")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--launch", default="default", choices=["default", "grid", "persistent"])
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run plain 1 GiB device copies (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "OUT_JSON"),
+                    help="no run: write the traffic summary from two rocprofv3 --pmc output folders")
+    ap.add_argument("--pmc-command", default="", help="command recorded in the traffic summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, command=args.pmc_command)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (slices are "
               "independent; sharding along z is described in the design notes). Use --gpus 1.",
@@ -85,18 +229,21 @@ def main():
 
     import torch
     import paper_1506_02079_amd as gdf
-    import synth
 
     dev = torch.device("cuda:0")
     log("generating %dx%dx%d stack" % (S, H, W))
     stack = synth.make_stack(S, H, W, seed=SEED, ramp=True)
     st = torch.from_numpy(stack).to(dev)
-    kw = dict(tol=TOL, precision="fp32", nu=args.nu, tile_rows=args.tile_rows)
+    kw = dict(tol=TOL, precision="fp32", nu=args.nu, tile_rows=args.tile_rows, launch_mode=args.launch,
+              autotune=not args.no_autotune)
 
-    log("warmup")
+    log("warmup (autotuning on the first call)")
+    t0 = time.perf_counter()
     for _ in range(args.warmup):
         f, rep = gdf.fuse_stack(st, ALPHA, **kw)
     torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    tuned = gdf.autotune_last()
 
     if args.calib_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale
@@ -152,13 +299,28 @@ def main():
                    "slices": S, "height": H, "width": W, "alpha": ALPHA, "tol": TOL},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic_from_profile(per_launch_bytes),
+                     "traffic": traffic_from_profile(),
                      "kernel": "vcycle_fine (fused finest-level pass)",
                      "algo_bytes_per_launch": per_launch_bytes, "avg_launch_ms": avg_ms},
         "worst_rel_residual": worst,
         "vcycles": cycles,
+        "autotuned": tuned,
+        "warmup_s": t_warm,
         "breakdown": breakdown,
     }
+    del f, st
+    if not args.no_forms:
+        plain = out["value"]
+        forms = {}
+        forms["batched"] = bench_batched(gdf, torch, dev, 3)
+        torch.cuda.empty_cache()
+        forms["mixed"] = bench_mixed(gdf, torch, dev, 2, 0.001)
+        forms["mixed_alpha_0.01"] = bench_mixed(gdf, torch, dev, 2, 0.01)
+        torch.cuda.empty_cache()
+        forms["adjoint"] = bench_adjoint(gdf, torch, dev, 5)
+        for v in forms.values():
+            v["vs_plain"] = v["value"] / plain
+        out["forms"] = forms
     if not args.no_cpu:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(stack, S // 2)

@@ -88,8 +88,18 @@ typedef struct {
                           replay it, with per-slice convergence flags on the device */
     int tile_rows;     /* rows per strip work item (even, >= 16); 0 = tuned default */
     int inner_cycles;  /* MIXED: FP32 V-cycles per refinement step (default 3) */
-    int reserved[9];
+    int launch_mode;   /* gdf_launch_mode for the multigrid passes (default GDF_LAUNCH_GRID) */
+    int autotune;      /* 1: pick tile_rows, nu and launch_mode by timing candidate solves
+                          of this very call (see "Autotuning" below); 0: off */
+    int reserved[7];
 } gdf_solve_opts;
+
+typedef enum {
+    GDF_LAUNCH_DEFAULT = 0,     /* library default (GDF_LAUNCH_GRID) */
+    GDF_LAUNCH_GRID = 1,        /* one wavefront per work item: the grid covers the work list */
+    GDF_LAUNCH_PERSISTENT = 2   /* grid capped at the workgroups resident on the GPU at once;
+                                   each wavefront loops over the work list */
+} gdf_launch_mode;
 
 /* Per-slice outcome (host memory, filled when a report pointer is given). */
 typedef struct {
@@ -116,8 +126,9 @@ const char *gdf_last_error(void);
 /* Library version string. */
 const char *gdf_version(void);
 
-/* Releases the per-device graph cache.  Safe to call at any time when no
- * other call is running. */
+/* Releases the library's caches: captured graphs (per device), autotuning
+ * choices and recent host-side plans (work lists and workspace layouts).
+ * Safe to call at any time when no other call is running. */
 void gdf_release(void);
 
 /* ------------------------------------------------------------------------ */
@@ -183,6 +194,24 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *desc_host, int dty
                                  double *grad_alpha_host, const gdf_solve_opts *opts,
                                  void *workspace_dev, size_t workspace_bytes,
                                  gdf_slice_report *report_host, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Autotuning.  With opts.autotune = 1, any of the three solve entry points
+ * first times complete solves of its own arguments under candidate settings
+ * and then runs once more with the fastest, whose outputs and report it
+ * returns.  Tuned, in this order, each among the values left at 0 by the
+ * caller: nu (2, 1: sweeps per smoothing step, i.e. how many red-black sweeps
+ * each pass over HBM fuses), tile_rows (heuristic, 32, 64, 128, 256 rows per
+ * work item) and launch_mode (grid, persistent).  The choice is cached per
+ * batch signature (entry point, sizes, alphas, tol, precision, dtypes, fixed
+ * options) until gdf_release.  The workspace size functions return the
+ * largest size over the candidates when opts.autotune = 1.  Candidate runs
+ * write the outputs several times; a candidate that does not finish with
+ * GDF_OK is discarded.
+ *
+ * gdf_autotune_last copies the settings used by the last autotuned call on
+ * the calling thread into *opts_host and returns 1 (0 if there was none).   */
+int gdf_autotune_last(gdf_solve_opts *opts_host);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing for measurement.  When enabled, the library brackets every

@@ -21,10 +21,12 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -55,16 +57,26 @@ gdf_status set_err(gdf_status st, const char *fmt, ...)
     } while (0)
 
 constexpr double kSigmaStop = 2.0;
+// An FP32 V-cycle that shrinks the residual by less than this factor (the
+// usual factor is 0.05 - 0.3) means the iterate has reached FP32's floor.
+constexpr double kStallRatio = 0.6;
 constexpr int kCoarsePasses = 3;   // x 2 sweeps on the coarsest level
 constexpr int kTileW = 64, kTileH = 16;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
+template <typename T> void key_push(std::vector<unsigned long long> &k, const T &v)
+{
+    unsigned long long x = 0;
+    std::memcpy(&x, &v, std::min(sizeof v, sizeof x));
+    k.push_back(x);
+}
+
 // ------------------------------------------------------------------ options
 
 struct Opts {
-    int prec, max_vc, nu, out_dtype, use_graph, tile_rows, inner;
+    int prec, max_vc, nu, out_dtype, use_graph, tile_rows, inner, launch, autotune;
 };
 
 gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
@@ -90,6 +102,13 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
     r.inner = o->inner_cycles ? o->inner_cycles : 3;
     if (r.inner < 1 || r.inner > 64)
         return set_err(GDF_EINVAL, "opts.inner_cycles must be in [1, 64] (got %d)", r.inner);
+    r.launch = o->launch_mode ? o->launch_mode : GDF_LAUNCH_GRID;
+    if (r.launch != GDF_LAUNCH_GRID && r.launch != GDF_LAUNCH_PERSISTENT)
+        return set_err(GDF_EINVAL, "opts.launch_mode must be 0, GDF_LAUNCH_GRID or GDF_LAUNCH_PERSISTENT (got %d)",
+                       o->launch_mode);
+    r.autotune = o->autotune;
+    if (r.autotune != 0 && r.autotune != 1)
+        return set_err(GDF_EINVAL, "opts.autotune must be 0 or 1 (got %d)", r.autotune);
     return GDF_OK;
 }
 
@@ -159,6 +178,7 @@ struct List {
     int off, count;            // all items: [off, off + count) = fast part then guarded part
     int n_fast;
     int G, VW, TH;
+    std::vector<std::pair<int, double>> slice_px;   // (slice, pixels at this level)
 };
 
 enum ProfClass { PC_SMOOTH, PC_FINE, PC_FIRST, PC_COARSE, PC_FINALIZE, PC_PREP, PC_REFINE, PC_ADJOINT, PC_COUNT };
@@ -222,6 +242,7 @@ int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
     for (int s : slices) {
         const SliceGeom &g = P.g[s];
         const int H = g.h[level], W = g.w[level];
+        L.slice_px.emplace_back(s, (double)H * W);
         for (int y0 = 0; y0 < H; y0 += L.TH) {
             const int y1 = std::min(y0 + L.TH, H);
             const bool yin = y0 - L.G >= 1 && y1 + L.G <= H - 1;
@@ -403,14 +424,15 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
 
 // Fills device pointers into the descriptors and returns the host image of
 // the tables region.
-std::vector<char> bind_tables(Plan &P, char *ws)
+std::vector<char> bind_tables(const Plan &P, char *ws, const std::vector<SliceIO> &io)
 {
     char *arena = ws + P.off_arena;
     SliceState *st_dev = reinterpret_cast<SliceState *>(ws + P.off_state);
+    std::vector<LevelDesc> descs = P.descs;
     for (int s = 0; s < P.n; ++s) {
         const SliceGeom &g = P.g[s];
         for (int l = 0; l < g.nlev; ++l) {
-            LevelDesc &d = P.descs[P.desc_base[s] + l];
+            LevelDesc &d = descs[P.desc_base[s] + l];
             d.u[0] = arena + g.off_u[l][0];
             d.u[1] = arena + g.off_u[l][1];
             d.b = arena + g.off_b[l];
@@ -433,14 +455,14 @@ std::vector<char> bind_tables(Plan &P, char *ws)
         st[s].alpha = P.g[s].alpha;
         act[s] = 1;
     }
-    std::memcpy(img.data() + P.off_desc, P.descs.data(), sizeof(LevelDesc) * P.descs.size());
+    std::memcpy(img.data() + P.off_desc, descs.data(), sizeof(LevelDesc) * descs.size());
     if (!P.items.empty()) std::memcpy(img.data() + P.off_items, P.items.data(), sizeof(Item) * P.items.size());
     std::memcpy(img.data() + P.off_r_first, P.ranges_first.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_cycle, P.ranges_cycle.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_tiles, P.ranges_tiles.data(), sizeof(int) * 2 * P.n);
     if (!P.ranges_smooth.empty())
         std::memcpy(img.data() + P.off_r_smooth, P.ranges_smooth.data(), sizeof(int) * 2 * P.n);
-    std::memcpy(img.data() + P.off_io, P.io.data(), sizeof(SliceIO) * P.n);
+    std::memcpy(img.data() + P.off_io, io.data(), sizeof(SliceIO) * P.n);
     if (P.mixed) {
         double **tab = reinterpret_cast<double **>(img.data() + P.off_u64tab);
         for (int s = 0; s < P.n; ++s) {
@@ -449,6 +471,48 @@ std::vector<char> bind_tables(Plan &P, char *ws)
         }
     }
     return img;
+}
+
+// --------------------------------------------------------------- plan cache
+//
+// A plan is a pure function of the batch shape and the options; for large
+// batches it holds hundreds of thousands of work items and takes milliseconds
+// to build, so recent plans are kept, read-only, and shared between calls.
+
+std::mutex g_plan_mu;
+std::vector<std::pair<std::vector<unsigned long long>, std::shared_ptr<const Plan>>> g_plans;
+
+gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vector<int> &H,
+                       const std::vector<int> &W, const std::vector<double> &al, const Opts &o, int smooth_S,
+                       bool need_gs)
+{
+    std::vector<unsigned long long> key;
+    for (int v : {n, smooth_S, need_gs ? 1 : 0, o.prec, o.max_vc, o.nu, o.out_dtype, o.use_graph, o.tile_rows,
+                  o.inner, o.launch})
+        key_push(key, v);
+    for (int i = 0; i < n; ++i) {
+        key_push(key, H[i]);
+        key_push(key, W[i]);
+        key_push(key, al[i]);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (size_t i = 0; i < g_plans.size(); ++i)
+            if (g_plans[i].first == key) {
+                out = g_plans[i].second;
+                std::rotate(g_plans.begin() + i, g_plans.begin() + i + 1, g_plans.end());   // most recent last
+                return GDF_OK;
+            }
+    }
+    auto p = std::make_shared<Plan>();
+    p->need_gs_copy = need_gs;
+    const gdf_status r = make_plan(*p, n, H, W, al, o, smooth_S);
+    if (r) return r;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plans.size() >= 16) g_plans.erase(g_plans.begin());
+    g_plans.emplace_back(std::move(key), p);
+    out = p;
+    return GDF_OK;
 }
 
 // ---------------------------------------------------------------- profiling
@@ -514,7 +578,7 @@ struct ProfScope {
 // ------------------------------------------------------------------ driver
 
 struct Run {
-    Plan &P;
+    const Plan &P;
     char *ws;
     hipStream_t s;
     bool capturing = false;
@@ -531,8 +595,9 @@ struct Run {
     std::vector<char> active_host;
     double tol;
     int max_cycles;
+    double stall_ratio = 0.0;   // FIN_CHECK stall test (FP32 iterates only)
 
-    Run(Plan &p, char *w, hipStream_t st_) : P(p), ws(w), s(st_)
+    Run(const Plan &p, char *w, hipStream_t st_) : P(p), ws(w), s(st_)
     {
         st = reinterpret_cast<SliceState *>(ws + P.off_state);
         active = reinterpret_cast<int *>(ws + P.off_active);
@@ -555,15 +620,9 @@ struct Run {
     // algorithmic bytes of a list's pass over the slices still iterating
     double pass_bytes(int li, double per_px) const
     {
-        const List &L = P.lists[li];
-        std::vector<char> seen(P.n, 0);
         double px = 0.0;
-        for (int i = 0; i < L.count; ++i) {
-            const int s = P.descs[P.items[L.off + i].lev].slice;
-            if (seen[s]) continue;
-            seen[s] = 1;
-            if (active_host[s]) px += (double)P.g[s].h[L.level] * P.g[s].w[L.level];
-        }
+        for (const auto &e : P.lists[li].slice_px)
+            if (active_host[e.first]) px += e.second;
         return px * per_px;
     }
 
@@ -584,10 +643,11 @@ struct Run {
         ProfScope ps(cls, g_prof_on ? pass_bytes(li, per_px) : 0.0, s, capturing);
         a.items = items + L.off;
         a.n_items = L.n_fast;
-        HIP_TRY(launch_strip(kind, P.o.nu, fp64, true, a, s));
+        const bool pers = P.o.launch == GDF_LAUNCH_PERSISTENT;
+        HIP_TRY(launch_strip(kind, P.o.nu, fp64, true, pers, a, s));
         a.items = items + L.off + L.n_fast;
         a.n_items = L.count - L.n_fast;
-        HIP_TRY(launch_strip(kind, P.o.nu, fp64, false, a, s));
+        HIP_TRY(launch_strip(kind, P.o.nu, fp64, false, pers, a, s));
         return GDF_OK;
     }
 
@@ -595,8 +655,10 @@ struct Run {
     // hair below the exact FP64 residual of the output, which is checked after.
     gdf_status finish(const int *range, const float2 *pf, const double *pd, int mode, int count)
     {
-        const double t = (mode == FIN_CHECK && pf) ? 0.99 * tol : tol;
-        HIP_TRY(launch_finish(P.n, range, pf, pd, mode, t, max_cycles, count, st, active, s));
+        const bool in_loop = mode == FIN_CHECK && pf;
+        const double t = in_loop ? 0.99 * tol : tol;
+        HIP_TRY(launch_finish(P.n, range, pf, pd, mode, t, max_cycles, count, in_loop ? stall_ratio : 0.0, st,
+                              active, s));
         return GDF_OK;
     }
 
@@ -653,8 +715,10 @@ struct Run {
     }
 
     // V-cycles until every slice meets tol (host checks the flags after each
-    // cycle).  With first = false, continues from the current iterates.
-    gdf_status iterate(bool fp64, bool first = true)
+    // cycle).  With first = false, continues from the current iterates.  A
+    // captured schedule has no host checks: it holds `captured` cycles, which
+    // frozen slices skip on the device.
+    gdf_status iterate(bool fp64, bool first = true, int captured = 0)
     {
         gdf_status r;
         if (first) {
@@ -662,7 +726,7 @@ struct Run {
             if ((r = finish(r_first, partf, nullptr, FIN_CHECK, 0))) return r;
         }
         if (capturing) {
-            for (int k = 1; k <= max_cycles; ++k) {
+            for (int k = 1; k <= (captured ? captured : max_cycles); ++k) {
                 if ((r = cycle(k, fp64))) return r;
                 if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
             }
@@ -688,7 +752,8 @@ struct Run {
         std::vector<int> act(P.n, 0);
         any = false;
         for (int i = 0; i < P.n; ++i)
-            if (h[i].status == 0 && std::isfinite(h[i].rel) && h[i].rel > tol && h[i].cycles < max_cycles) {
+            if (h[i].status == 0 && !h[i].stalled && std::isfinite(h[i].rel) && h[i].rel > tol &&
+                h[i].cycles < max_cycles) {
                 act[i] = 1;
                 any = true;
             }
@@ -701,9 +766,9 @@ struct Run {
     }
 };
 
-gdf_status upload_tables(Plan &P, char *ws, hipStream_t s)
+gdf_status upload_tables(const Plan &P, char *ws, const std::vector<SliceIO> &io, hipStream_t s)
 {
-    std::vector<char> img = bind_tables(P, ws);
+    std::vector<char> img = bind_tables(P, ws, io);
     HIP_TRY(hipMemcpyAsync(ws + P.off_tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
     // pageable source: the copy is staged before the call returns; synchronise
     // so the host image can be released safely
@@ -711,11 +776,13 @@ gdf_status upload_tables(Plan &P, char *ws, hipStream_t s)
     return GDF_OK;
 }
 
-gdf_status collect(Plan &P, char *ws, hipStream_t s, gdf_slice_report *rep, double tol, int cycles_scale)
+gdf_status collect(const Plan &P, char *ws, hipStream_t s, gdf_slice_report *rep, double tol, int cycles_scale,
+                   std::vector<SliceState> *states = nullptr)
 {
     std::vector<SliceState> h(P.n);
     HIP_TRY(hipMemcpyAsync(h.data(), ws + P.off_state, sizeof(SliceState) * P.n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (states) *states = h;
     gdf_status worst = GDF_OK;
     for (int i = 0; i < P.n; ++i) {
         int status = GDF_OK;
@@ -762,12 +829,6 @@ void graph_store(const std::vector<unsigned long long> &key, hipGraphExec_t ex)
     g_graphs.push_back(GraphEntry{key, ex});
 }
 
-template <typename T> void key_push(std::vector<unsigned long long> &k, const T &v)
-{
-    unsigned long long x = 0;
-    std::memcpy(&x, &v, std::min(sizeof v, sizeof x));
-    k.push_back(x);
-}
 
 // ------------------------------------------------------------ solve body
 
@@ -786,7 +847,7 @@ struct SolveIO {
 gdf_status mixed_iterate(Run &R, int gs_dtype, const void *gs, int go_dtype, const void *go,
                          const void *rhs)
 {
-    Plan &P = R.P;
+    const Plan &P = R.P;
     gdf_status r;
     RefineArgs ra;
     ra.gs_dtype = gs_dtype;
@@ -837,18 +898,25 @@ gdf_status mixed_iterate(Run &R, int gs_dtype, const void *gs, int go_dtype, con
 // Prepared right-hand side (prep kernel or smoothing) -> iterate -> output.
 gdf_status solve_body(Run &R, const SolveIO &x)
 {
-    Plan &P = R.P;
+    const Plan &P = R.P;
     gdf_status r;
     if (!P.mixed) {
+        // rounds after the first resume slices whose exact residual missed tol
+        // (decided on the host, or on the device inside a captured graph, which
+        // holds two such rounds of two cycles each)
         for (int round = 0; round < 4; ++round) {
-            if ((r = R.iterate(P.fp64, round == 0))) return r;
+            if ((r = R.iterate(P.fp64, round == 0, round ? 2 : 0))) return r;
             {
                 ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
                 HIP_TRY(launch_finalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
                                         R.desc, R.st, round ? R.only : nullptr, R.partd, R.s));
             }
             if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_FINAL, 0))) return r;
-            if (R.capturing) break;
+            if (R.capturing) {
+                if (round == 2) break;
+                HIP_TRY(launch_resume_flags(P.n, R.st, R.tol, R.max_cycles, R.active, R.only, R.s));
+                continue;
+            }
             bool again = false;
             if ((r = R.resume_missed(again))) return r;
             if (!again) break;
@@ -865,6 +933,129 @@ gdf_status solve_body(Run &R, const SolveIO &x)
     return GDF_OK;
 }
 
+// ------------------------------------------------------------- autotuning
+//
+// A call with opts.autotune = 1 times whole solves of its own batch under
+// candidate settings and keeps the fastest: first the sweep count nu per
+// smoothing step (fewer sweeps per pass against more V-cycles), then the rows
+// per strip work item (tile_rows: halo overhead against the number of items
+// in flight), then the launch mode (one wave per item against a persistent
+// grid).  Fields the caller set explicitly are not tuned.  The result is
+// cached per batch signature (sizes, screening weights, tolerances, precision
+// and dtypes; not the data or the pointers) until gdf_release.
+
+struct Tuned { int nu, tile_rows, launch; };
+std::mutex g_tune_mu;
+std::vector<std::pair<std::vector<unsigned long long>, Tuned>> g_tuned;
+thread_local gdf_solve_opts g_last_tuned;
+thread_local bool g_last_tuned_ok = false;
+
+std::vector<int> tune_nus(const gdf_solve_opts &b)
+{
+    return b.nu ? std::vector<int>{b.nu} : std::vector<int>{2, 1};
+}
+std::vector<int> tune_tiles(const gdf_solve_opts &b)
+{
+    return b.tile_rows ? std::vector<int>{b.tile_rows} : std::vector<int>{0, 32, 64, 128, 256};
+}
+std::vector<int> tune_launches(const gdf_solve_opts &b)
+{
+    return b.launch_mode ? std::vector<int>{b.launch_mode}
+                         : std::vector<int>{GDF_LAUNCH_GRID, GDF_LAUNCH_PERSISTENT};
+}
+
+gdf_solve_opts opts_or_zero(const gdf_solve_opts *o)
+{
+    gdf_solve_opts z;
+    std::memset(&z, 0, sizeof z);
+    return o ? *o : z;
+}
+
+// Largest workspace over the candidate settings (size_of(opts) per candidate),
+// memoised per signature: each candidate size builds a full plan.
+std::mutex g_wsz_mu;
+std::vector<std::pair<std::vector<unsigned long long>, size_t>> g_wsz;
+
+template <class SizeOf>
+size_t tuned_workspace(const std::vector<unsigned long long> &key, const gdf_solve_opts &base, SizeOf size_of)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_wsz_mu);
+        for (auto &e : g_wsz)
+            if (e.first == key) return e.second;
+    }
+    size_t m = 0;
+    for (int nu : tune_nus(base))
+        for (int tr : tune_tiles(base)) {
+            gdf_solve_opts c = base;
+            c.autotune = 0;
+            c.nu = nu;
+            c.tile_rows = tr;
+            const size_t b = size_of(&c);
+            if (b == 0) return 0;
+            m = std::max(m, b);
+        }
+    std::lock_guard<std::mutex> lk(g_wsz_mu);
+    if (g_wsz.size() >= 64) g_wsz.erase(g_wsz.begin());
+    g_wsz.emplace_back(key, m);
+    return m;
+}
+
+template <class Call>
+gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve_opts &base, Call call)
+{
+    gdf_solve_opts best = base;
+    best.autotune = 0;
+    Tuned t{0, 0, 0};
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (auto &e : g_tuned)
+            if (e.first == key) { t = e.second; have = true; break; }
+    }
+    if (!have) {
+        const double inf = HUGE_VAL;
+        auto timeit = [&](const gdf_solve_opts &c) -> double {
+            double tmin = inf;
+            for (int rep = 0; rep < 2; ++rep) {   // the first run also captures a graph
+                const auto t0 = std::chrono::steady_clock::now();
+                if (call(&c) != GDF_OK) return inf;
+                const auto t1 = std::chrono::steady_clock::now();
+                tmin = std::min(tmin, std::chrono::duration<double>(t1 - t0).count());
+            }
+            return tmin;
+        };
+        const std::vector<int> nus = tune_nus(base), tiles = tune_tiles(base), ls = tune_launches(base);
+        gdf_solve_opts cur = best;
+        cur.nu = nus[0];
+        cur.tile_rows = tiles[0];
+        cur.launch_mode = ls[0];
+        double tcur = timeit(cur);
+        auto try_field = [&](int gdf_solve_opts::*field, const std::vector<int> &vals) {
+            for (size_t i = 1; i < vals.size(); ++i) {
+                gdf_solve_opts c = cur;
+                c.*field = vals[i];
+                const double tc = timeit(c);
+                if (tc < tcur) { cur = c; tcur = tc; }
+            }
+        };
+        try_field(&gdf_solve_opts::nu, nus);
+        try_field(&gdf_solve_opts::tile_rows, tiles);
+        try_field(&gdf_solve_opts::launch_mode, ls);
+        if (!(tcur < inf)) return call(&best);   // no candidate ran cleanly: report the plain call
+        t = Tuned{cur.nu, cur.tile_rows, cur.launch_mode};
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tuned.size() >= 64) g_tuned.erase(g_tuned.begin());
+        g_tuned.emplace_back(key, t);
+    }
+    best.nu = t.nu;
+    best.tile_rows = t.tile_rows;
+    best.launch_mode = t.launch;
+    g_last_tuned = best;
+    g_last_tuned_ok = true;
+    return call(&best);
+}
+
 }  // namespace
 
 // ===================================================================== ABI
@@ -877,9 +1068,28 @@ const char *gdf_version(void) { return "gdf-mi355x 0.1 (gfx950)"; }
 
 void gdf_release(void)
 {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    for (auto &e : g_graphs) hipGraphExecDestroy(e.exec);
-    g_graphs.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_graph_mu);
+        for (auto &e : g_graphs) hipGraphExecDestroy(e.exec);
+        g_graphs.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_wsz_mu);
+        g_wsz.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        g_plans.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
+
+int gdf_autotune_last(gdf_solve_opts *opts_host)
+{
+    if (!g_last_tuned_ok) return 0;
+    if (opts_host) *opts_host = g_last_tuned;
+    return 1;
 }
 
 void gdf_profile_enable(int on)
@@ -910,6 +1120,33 @@ int gdf_profile_read(const char *cls, double *ms, double *bytes)
 
 // ---------------------------------------------------------------- fuse_stack
 
+// Opts of the FP64-refinement re-solve of slices that stall in FP32
+static Opts escalation_opts(const Opts &o)
+{
+    Opts m = o;
+    m.prec = GDF_PREC_MIXED;
+    m.max_vc = 40;
+    m.inner = 3;
+    m.use_graph = 0;
+    m.autotune = 0;
+    return m;
+}
+
+// FP32 solves reserve room to re-solve their largest slice with FP64 refinement
+static size_t escalation_bytes(const Opts &o, int H, int W, double alpha)
+{
+    if (o.prec != GDF_PREC_FP32) return 0;
+    std::shared_ptr<const Plan> Q;
+    if (cached_plan(Q, 1, {H}, {W}, {alpha}, escalation_opts(o), 0, false)) return 0;
+    return Q->total;
+}
+
+static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
+                           const void *go, int bc, double tol, void *f, const Opts &o, void *ws,
+                           size_t ws_bytes, const std::vector<SliceState> &h, gdf_slice_report *report,
+                           void *stream);
+
+
 static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long long pr, long long ps,
                                 double alpha, int bc, double tol, double sxy, double sz,
                                 const void *f, const gdf_solve_opts *opts, Opts &o)
@@ -929,31 +1166,72 @@ static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long 
     return GDF_OK;
 }
 
-static gdf_status fuse_plan(Plan &P, int S, int H, int W, double alpha, const Opts &o, bool need_gs)
+static gdf_status fuse_plan(std::shared_ptr<const Plan> &P, int S, int H, int W, double alpha, const Opts &o,
+                            bool need_gs)
 {
     std::vector<int> Hs(S, H), Ws(S, W);
     std::vector<double> al(S, alpha);
-    P.need_gs_copy = need_gs;
-    return make_plan(P, S, Hs, Ws, al, o, S);
+    return cached_plan(P, S, Hs, Ws, al, o, S, need_gs);
 }
 
-size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
+static size_t fuse_workspace_plain(int S, int H, int W, const gdf_solve_opts *opts)
 {
     Opts o;
     if (parse_opts(opts, o)) return 0;
     if (S < 1 || H < 1 || W < 1) return 0;
-    Plan P;
+    std::shared_ptr<const Plan> P, Q;
     if (fuse_plan(P, S, H, W, 1.0, o, o.prec == GDF_PREC_MIXED)) return 0;
     // the hierarchy depth depends on alpha; size for the deepest (smallest alpha)
-    Plan Q;
     if (fuse_plan(Q, S, H, W, 1e-12, o, o.prec == GDF_PREC_MIXED)) return 0;
-    return std::max(P.total, Q.total);
+    return std::max({P->total, Q->total, escalation_bytes(o, H, W, 1e-12)});
 }
+
+size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
+{
+    const gdf_solve_opts b = opts_or_zero(opts);
+    if (b.autotune != 1) return fuse_workspace_plain(S, H, W, opts);
+    std::vector<unsigned long long> key;
+    key_push(key, 0);
+    for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.tile_rows,
+                  b.launch_mode})
+        key_push(key, v);
+    return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
+}
+
+static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, long long pitch_row,
+                                   long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
+                                   double sigma_z, void *f, void *g_smooth, const gdf_solve_opts *opts,
+                                   void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream);
 
 gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch_row,
                       long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
                       double sigma_z, void *f, void *g_smooth, const gdf_solve_opts *opts,
                       void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream)
+{
+    const gdf_solve_opts b = opts_or_zero(opts);
+    if (b.autotune != 1)
+        return fuse_stack_plain(stack, S, H, W, pitch_row, pitch_slice, alpha, bc, tol, sigma_xy, sigma_z, f,
+                                g_smooth, opts, workspace, ws_bytes, report, stream);
+    Opts o;
+    gdf_status r;
+    if ((r = fuse_validate(stack, S, H, W, pitch_row, pitch_slice, alpha, bc, tol, sigma_xy, sigma_z, f, opts, o)))
+        return r;
+    std::vector<unsigned long long> key;
+    key_push(key, 0);
+    for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu,
+                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0})
+        key_push(key, v);
+    for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
+    return autotuned(key, b, [&](const gdf_solve_opts *c) {
+        return fuse_stack_plain(stack, S, H, W, pitch_row, pitch_slice, alpha, bc, tol, sigma_xy, sigma_z, f,
+                                g_smooth, c, workspace, ws_bytes, report, stream);
+    });
+}
+
+static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, long long pitch_row,
+                                   long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
+                                   double sigma_z, void *f, void *g_smooth, const gdf_solve_opts *opts,
+                                   void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream)
 {
     Opts o;
     gdf_status r;
@@ -961,25 +1239,28 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
         return r;
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
     const bool mixed = o.prec == GDF_PREC_MIXED;
-    Plan P;
-    if ((r = fuse_plan(P, S, H, W, alpha, o, mixed && !g_smooth))) return r;
+    std::shared_ptr<const Plan> PP;
+    if ((r = fuse_plan(PP, S, H, W, alpha, o, mixed && !g_smooth))) return r;
+    const Plan &P = *PP;
     if (ws_bytes < P.total)
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
     // g_o is the stack itself; f (and the FP32 copy of g_s when kept) are contiguous
+    std::vector<SliceIO> io = P.io;
     for (int z = 0; z < S; ++z) {
-        P.io[z].off_go = (long long)z * pitch_slice;
-        P.io[z].pitch_go = pitch_row;
-        P.io[z].off_f = (long long)z * H * W;
-        P.io[z].pitch_f = W;
-        P.io[z].off_gs = (long long)z * H * W;
-        P.io[z].pitch_gs = W;
+        io[z].off_go = (long long)z * pitch_slice;
+        io[z].pitch_go = pitch_row;
+        io[z].off_f = (long long)z * H * W;
+        io[z].pitch_f = W;
+        io[z].off_gs = (long long)z * H * W;
+        io[z].pitch_gs = W;
     }
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((r = upload_tables(P, ws, s))) return r;
+    if ((r = upload_tables(P, ws, io, s))) return r;
     Run R(P, ws, s);
     R.tol = tol;
     R.max_cycles = o.max_vc;
+    R.stall_ratio = o.prec == GDF_PREC_FP32 ? kStallRatio : 0.0;
 
     // smoothing writes the level-0 right-hand side of every slice
     SmoothArgs a;
@@ -1021,7 +1302,24 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
     x.go = stack;
     x.f = f;
     if ((r = solve_body(R, x))) return r;
-    return collect(P, ws, s, report, tol, mixed ? o.inner : 1);
+    std::vector<SliceState> h;
+    const gdf_status st = collect(P, ws, s, report, tol, mixed ? o.inner : 1, &h);
+    if (st != GDF_ENOCONV || o.prec != GDF_PREC_FP32 || !g_smooth) return st;
+    // stalled slices are re-solved from the returned g_s (FP32) and the stack
+    std::vector<gdf_slice_desc> d(S);
+    for (int z = 0; z < S; ++z) {
+        d[z].H = H;
+        d[z].W = W;
+        d[z].alpha = alpha;
+        d[z].off_gs = (long long)z * H * W;
+        d[z].pitch_gs = W;
+        d[z].off_go = (long long)z * pitch_slice;
+        d[z].pitch_go = pitch_row;
+        d[z].off_f = (long long)z * H * W;
+        d[z].pitch_f = W;
+    }
+    return escalate(S, d.data(), GDF_F32, g_smooth, GDF_U8, stack, bc, tol, f, o, workspace, ws_bytes, h, report,
+                    stream);
 }
 
 // -------------------------------------------------------------- solve_slices
@@ -1053,27 +1351,50 @@ static gdf_status slices_validate(int n, const gdf_slice_desc *d, double tol, in
     return GDF_OK;
 }
 
-static void fill_io(Plan &P, const gdf_slice_desc *d)
+static std::vector<SliceIO> slice_io(const Plan &P, const gdf_slice_desc *d)
 {
+    std::vector<SliceIO> io = P.io;
     for (int i = 0; i < P.n; ++i) {
-        P.io[i].off_gs = d[i].off_gs;
-        P.io[i].pitch_gs = d[i].pitch_gs;
-        P.io[i].off_go = d[i].off_go;
-        P.io[i].pitch_go = d[i].pitch_go;
-        P.io[i].off_f = d[i].off_f;
-        P.io[i].pitch_f = d[i].pitch_f;
+        io[i].off_gs = d[i].off_gs;
+        io[i].pitch_gs = d[i].pitch_gs;
+        io[i].off_go = d[i].off_go;
+        io[i].pitch_go = d[i].pitch_go;
+        io[i].off_f = d[i].off_f;
+        io[i].pitch_f = d[i].pitch_f;
     }
+    return io;
 }
 
-size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
+static size_t solve_workspace_plain(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
 {
     Opts o;
     std::vector<int> H, W;
     std::vector<double> al;
     if (slices_validate(n, d, 0.5, GDF_BC_NEUMANN, opts, o, H, W, al)) return 0;
-    Plan P;
-    if (make_plan(P, n, H, W, al, o, 0)) return 0;
-    return P.total;
+    std::shared_ptr<const Plan> P;
+    if (cached_plan(P, n, H, W, al, o, 0, false)) return 0;
+    int big = 0;
+    for (int i = 1; i < n; ++i)
+        if ((long long)H[i] * W[i] > (long long)H[big] * W[big]) big = i;
+    return std::max(P->total, escalation_bytes(o, H[big], W[big], al[big]));
+}
+
+size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
+{
+    const gdf_solve_opts b = opts_or_zero(opts);
+    if (b.autotune != 1) return solve_workspace_plain(n, d, opts);
+    if (n < 1 || !d) return 0;
+    std::vector<unsigned long long> key;
+    key_push(key, 1);
+    for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.tile_rows,
+                  b.launch_mode})
+        key_push(key, v);
+    for (int i = 0; i < n; ++i) {
+        key_push(key, d[i].H);
+        key_push(key, d[i].W);
+        key_push(key, d[i].alpha);
+    }
+    return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return solve_workspace_plain(n, d, c); });
 }
 
 size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_opts *opts)
@@ -1086,9 +1407,111 @@ size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *d, const gdf_sol
     return gdf_solve_workspace_size(n, d, &o);
 }
 
+static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs,
+                                     int go_dtype, const void *go, int bc, double tol, void *f,
+                                     const gdf_solve_opts *opts, void *workspace, size_t ws_bytes,
+                                     gdf_slice_report *report, void *stream);
+
+// Slices whose FP32 iterate stopped at the precision floor (stalled, above
+// tol) are solved again, from zero, by FP32 V-cycles inside FP64 iterative
+// refinement, in groups that fit the workspace, writing their f in place.
+static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
+                           const void *go, int bc, double tol, void *f, const Opts &o, void *ws,
+                           size_t ws_bytes, const std::vector<SliceState> &h, gdf_slice_report *report,
+                           void *stream)
+{
+    const Opts mo = escalation_opts(o);
+    gdf_solve_opts m;
+    std::memset(&m, 0, sizeof m);
+    m.precision = mo.prec;
+    m.max_vcycles = mo.max_vc;
+    m.nu = mo.nu;
+    m.out_dtype = mo.out_dtype;
+    m.tile_rows = mo.tile_rows;
+    m.inner_cycles = mo.inner;
+    m.launch_mode = mo.launch;
+    std::vector<int> status(n), todo;
+    for (int i = 0; i < n; ++i) {
+        const bool bad = h[i].status == GDF_ENONFINITE || !std::isfinite(h[i].rel);
+        status[i] = bad ? GDF_ENONFINITE : (h[i].rel > tol ? GDF_ENOCONV : GDF_OK);
+        if (!bad && h[i].stalled && h[i].rel > tol) todo.push_back(i);
+    }
+    size_t k = 0;
+    while (k < todo.size()) {
+        std::vector<gdf_slice_desc> g;
+        std::vector<int> idx;
+        for (; k < todo.size(); ++k) {
+            g.push_back(d[todo[k]]);
+            const size_t need = solve_workspace_plain((int)g.size(), g.data(), &m);
+            if (need == 0 || need > ws_bytes) {
+                g.pop_back();
+                break;
+            }
+            idx.push_back(todo[k]);
+        }
+        if (g.empty()) {   // this slice alone does not fit: it keeps GDF_ENOCONV
+            ++k;
+            continue;
+        }
+        std::vector<gdf_slice_report> sub(g.size());
+        const gdf_status r = solve_slices_plain((int)g.size(), g.data(), gs_dtype, gs, go_dtype, go, bc, tol, f,
+                                                &m, ws, ws_bytes, sub.data(), stream);
+        if (r != GDF_OK && r != GDF_ENOCONV && r != GDF_ENONFINITE) return r;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const int i = idx[j];
+            status[i] = sub[j].status;
+            if (report) {
+                report[i].vcycles += sub[j].vcycles;
+                report[i].status = sub[j].status;
+                report[i].rel_residual = sub[j].rel_residual;
+            }
+        }
+    }
+    gdf_status worst = GDF_OK;
+    for (int i = 0; i < n; ++i) {
+        if (status[i] == GDF_ENONFINITE) worst = GDF_ENONFINITE;
+        else if (status[i] == GDF_ENOCONV && worst == GDF_OK) worst = GDF_ENOCONV;
+    }
+    if (worst == GDF_ENOCONV) set_err(worst, "some slices did not reach tol=%g", tol);
+    else if (worst == GDF_ENONFINITE) set_err(worst, "non-finite residual in some slices");
+    else g_err.clear();
+    return worst;
+}
+
 gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
                         const void *go, int bc, double tol, void *f, const gdf_solve_opts *opts,
                         void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream)
+{
+    const gdf_solve_opts b = opts_or_zero(opts);
+    if (b.autotune != 1)
+        return solve_slices_plain(n, d, gs_dtype, gs, go_dtype, go, bc, tol, f, opts, workspace, ws_bytes,
+                                  report, stream);
+    Opts o;
+    std::vector<int> H, W;
+    std::vector<double> al;
+    gdf_status r;
+    if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
+    std::vector<unsigned long long> key;
+    key_push(key, 1);
+    for (int v : {n, bc, gs_dtype, go_dtype, b.precision, b.max_vcycles, b.out_dtype, b.use_graph,
+                  b.inner_cycles, b.nu, b.tile_rows, b.launch_mode})
+        key_push(key, v);
+    key_push(key, tol);
+    for (int i = 0; i < n; ++i) {
+        key_push(key, d[i].H);
+        key_push(key, d[i].W);
+        key_push(key, d[i].alpha);
+    }
+    return autotuned(key, b, [&](const gdf_solve_opts *c) {
+        return solve_slices_plain(n, d, gs_dtype, gs, go_dtype, go, bc, tol, f, c, workspace, ws_bytes, report,
+                                  stream);
+    });
+}
+
+static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs,
+                                     int go_dtype, const void *go, int bc, double tol, void *f,
+                                     const gdf_solve_opts *opts, void *workspace, size_t ws_bytes,
+                                     gdf_slice_report *report, void *stream)
 {
     Opts o;
     std::vector<int> H, W;
@@ -1100,17 +1523,18 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
         return set_err(GDF_EINVAL, "go_dtype must be GDF_U8, GDF_F32 or GDF_F64");
     if (!gs || !go || !f) return set_err(GDF_EINVAL, "gs, go and f must be non-null");
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
-    Plan P;
-    if ((r = make_plan(P, n, H, W, al, o, 0))) return r;
+    std::shared_ptr<const Plan> PP;
+    if ((r = cached_plan(PP, n, H, W, al, o, 0, false))) return r;
+    const Plan &P = *PP;
     if (ws_bytes < P.total)
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
-    fill_io(P, d);
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((r = upload_tables(P, ws, s))) return r;
+    if ((r = upload_tables(P, ws, slice_io(P, d), s))) return r;
     Run R(P, ws, s);
     R.tol = tol;
     R.max_cycles = o.max_vc;
+    R.stall_ratio = o.prec == GDF_PREC_FP32 ? kStallRatio : 0.0;
     SolveIO x{gs_dtype, go_dtype, gs, go, f};
 
     auto body = [&]() -> gdf_status {
@@ -1145,6 +1569,7 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
         key_push(key, o.out_dtype);
         key_push(key, o.tile_rows);
         key_push(key, o.inner);
+        key_push(key, o.launch);
         for (int i = 0; i < n; ++i) {
             key_push(key, d[i].H);
             key_push(key, d[i].W);
@@ -1158,6 +1583,7 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
         }
         hipGraphExec_t ex = graph_lookup(key);
         if (!ex) {
+            if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.nu, P.fp64);
             R.capturing = true;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             gdf_status q = body();
@@ -1176,12 +1602,53 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
         }
         HIP_TRY(hipGraphLaunch(ex, s));
     }
-    return collect(P, ws, s, report, tol, o.prec == GDF_PREC_MIXED ? o.inner : 1);
+    std::vector<SliceState> h;
+    const gdf_status st = collect(P, ws, s, report, tol, o.prec == GDF_PREC_MIXED ? o.inner : 1, &h);
+    if (st == GDF_ENOCONV && o.prec == GDF_PREC_FP32)
+        return escalate(n, d, gs_dtype, gs, go_dtype, go, bc, tol, f, o, workspace, ws_bytes, h, report, stream);
+    return st;
 }
 
 // ----------------------------------------------------- solve_slices_backward
 
+static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
+                                 const void *f, const void *gs, int bc, double tol, void *grad_gs,
+                                 void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
+                                 void *workspace, size_t ws_bytes, gdf_slice_report *report,
+                                 void *stream);
+
 gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
+                                 const void *f, const void *gs, int bc, double tol, void *grad_gs,
+                                 void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
+                                 void *workspace, size_t ws_bytes, gdf_slice_report *report,
+                                 void *stream)
+{
+    const gdf_solve_opts b = opts_or_zero(opts);
+    if (b.autotune != 1)
+        return backward_plain(n, d, dtype, grad_f, f, gs, bc, tol, grad_gs, grad_go, grad_alpha, opts, workspace,
+                              ws_bytes, report, stream);
+    Opts o;
+    std::vector<int> H, W;
+    std::vector<double> al;
+    gdf_status r;
+    if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
+    std::vector<unsigned long long> key;
+    key_push(key, 2);
+    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.tile_rows, b.launch_mode})
+        key_push(key, v);
+    key_push(key, tol);
+    for (int i = 0; i < n; ++i) {
+        key_push(key, d[i].H);
+        key_push(key, d[i].W);
+        key_push(key, d[i].alpha);
+    }
+    return autotuned(key, b, [&](const gdf_solve_opts *c) {
+        return backward_plain(n, d, dtype, grad_f, f, gs, bc, tol, grad_gs, grad_go, grad_alpha, c, workspace,
+                              ws_bytes, report, stream);
+    });
+}
+
+static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
                                  const void *f, const void *gs, int bc, double tol, void *grad_gs,
                                  void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
                                  void *workspace, size_t ws_bytes, gdf_slice_report *report,
@@ -1201,14 +1668,14 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     if (dtype == GDF_F32) o.prec = GDF_PREC_MIXED;
     if (!grad_f || !f || !gs) return set_err(GDF_EINVAL, "grad_f, f and gs must be non-null");
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
-    Plan P;
-    if ((r = make_plan(P, n, H, W, al, o, 0))) return r;
+    std::shared_ptr<const Plan> PP;
+    if ((r = cached_plan(PP, n, H, W, al, o, 0, false))) return r;
+    const Plan &P = *PP;
     if (ws_bytes < P.total)
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
-    fill_io(P, d);
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((r = upload_tables(P, ws, s))) return r;
+    if ((r = upload_tables(P, ws, slice_io(P, d), s))) return r;
     Run R(P, ws, s);
     R.tol = tol;
     R.max_cycles = o.max_vc;

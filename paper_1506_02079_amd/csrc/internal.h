@@ -76,9 +76,14 @@ int strip_halo(StripKind k, int nu);
 // Enqueue one strip pass.  fp64 selects double precision.  fast: every item
 // of the list stays clear of the slice's edges (rows y0 - G .. y1 + G in
 // [1, H - 2], columns x0 - G .. x0 - G + 127 in [1, W - 2]), so the kernel
-// variant without row guards and edge masks runs.
-hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, const StripLaunch &a,
+// variant without row guards and edge masks runs.  persistent: the grid is
+// capped at the workgroups resident on the device at once and each wave loops
+// over the list's items; otherwise one wave per item.
+hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, bool persistent, const StripLaunch &a,
                         hipStream_t s);
+// Resolves the persistent grid sizes of every strip kernel variant for nu and
+// the precision (device queries; call before a stream capture begins).
+void strip_prepare(int nu, bool fp64);
 
 // ---- per-slice reductions and flags ------------------------------------
 
@@ -95,6 +100,8 @@ struct SliceState {
     double uoff;        // bmean / alpha: the solution's mean, added back at the end
     int cycles;         // coarse-grid corrections applied
     int status;         // 0 ok / iterating, GDF_ENONFINITE ...
+    int stalled;        // 1: stopped because a cycle no longer reduced the residual
+    int pad_;
 };
 
 enum FinishMode {
@@ -110,9 +117,19 @@ enum FinishMode {
 // order (deterministic) and update the slice state and flags.
 // partials_f: strip partials (r^2, r); partials_d: FP64 tile partials.
 // FIN_CHECK with strip partials also records the constant-mode correction.
+// FIN_CHECK with stall_ratio > 0: from the second counted cycle on, a slice
+// whose residual shrank by less than that factor in one cycle (while still
+// above tol) stops with state.stalled = 1 (the working precision's floor).
 hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_f,
                          const double *partials_d, int mode, double tol, int max_cycles,
-                         int count_cycle, SliceState *state, int *active, hipStream_t s);
+                         int count_cycle, double stall_ratio, SliceState *state, int *active,
+                         hipStream_t s);
+
+// After the exact residual of the output (FIN_FINAL): slices whose FP64
+// relative residual still exceeds tol, with cycles left and finite state,
+// get active = only = 1 (resume iterating, re-form f); others get 0.
+hipError_t launch_resume_flags(int n_slices, const SliceState *state, double tol, int max_cycles,
+                               int *active, int *only, hipStream_t s);
 
 // ---- elementwise / simple stencil kernels --------------------------------
 

@@ -26,6 +26,8 @@
 // G columns and G rows on each side and recomputes it redundantly.
 #include "internal.h"
 
+#include <atomic>
+
 namespace gdf {
 
 // ------------------------------------------------------------------ DPP ---
@@ -105,7 +107,7 @@ template <bool PROLONG, int NHS, int RMODE> struct StripShape {
 // owned rows come out exactly as in the guarded variant.  Interior rows also
 // fix the vertical coefficients.
 template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
-__global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
+__device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 {
     using Sh = StripShape<PROLONG, NHS, RMODE>;
     constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS, Q = Sh::Q;
@@ -113,8 +115,6 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
     using V2 = typename Vec2<T>::type;
 
     const int lane = threadIdx.x & (kWave - 1);
-    const int item_id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6));
-    if (item_id >= a.n_items) return;
     const Item it = a.items[item_id];
     const LevelDesc L = a.levs[it.lev];
     if (!a.active[L.slice]) {
@@ -399,6 +399,18 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
     }
 }
 
+// Each wave takes work items w, w + P, w + 2P, ... (P = waves in the grid).
+// With a grid covering the list every wave runs one item; a persistent grid
+// (capped at the waves the chip holds at once) loops over the list.
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+__global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
+{
+    const int stride = gridDim.x * kWavesPerBlock;
+    for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
+         id += stride)
+        strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>(a, id);
+}
+
 int strip_halo(StripKind k, int nu)
 {
     switch (k) {
@@ -414,39 +426,89 @@ int strip_halo(StripKind k, int nu)
     }
 }
 
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
-static hipError_t go(const StripLaunch &a, bool fast, hipStream_t s)
+// Workgroups of one kernel that fit on the device at once (occupancy x CUs),
+// a multiple of 8; 0 if the runtime cannot tell.
+static int resident_blocks(const void *kernel)
 {
-    if (a.n_items <= 0) return hipSuccess;
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess) return 0;
+    return (cus * per_cu) & ~7;
+}
+
+// Persistent grid size of one kernel instantiation, queried once (a query that
+// fails is retried on the next call).  One device type per process.
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+static int persistent_cap()
+{
+    static std::atomic<int> cap{0};
+    int c = cap.load(std::memory_order_relaxed);
+    if (c == 0) {
+        c = resident_blocks(reinterpret_cast<const void *>(&strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>));
+        if (c > 0) cap.store(c, std::memory_order_relaxed);
+    }
+    return c;
+}
+
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+static hipError_t go_variant(const StripLaunch &a, bool persistent, hipStream_t s)
+{
     const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
-    if (fast)
-        hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, true>), dim3(grid), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, false>), dim3(grid), dim3(256), 0, s, a);
+    int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
+    if (persistent) {
+        const int cap = persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>();
+        if (cap >= 8 && grid > cap) grid = cap;
+    }
+    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
+// n_items < 0: only resolve the persistent grid sizes (no launch)
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
+static hipError_t go(const StripLaunch &a, bool fast, bool persistent, hipStream_t s)
+{
+    if (a.n_items < 0) {
+        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, true>();
+        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, false>();
+        return hipSuccess;
+    }
+    if (a.n_items == 0) return hipSuccess;
+    return fast ? go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, persistent, s)
+                : go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, persistent, s);
+}
+
 template <typename T>
-static hipError_t launch_strip_t(StripKind k, int nu, bool f, const StripLaunch &a, hipStream_t s)
+static hipError_t launch_strip_t(StripKind k, int nu, bool f, bool p, const StripLaunch &a, hipStream_t s)
 {
     const bool n1 = nu == 1;
     switch (k) {
-    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, f, s) : go<T, false, true, 4, RES_BOTH>(a, f, s);
-    case SK_FINE: return n1 ? go<T, true, false, 4, RES_BOTH>(a, f, s) : go<T, true, false, 8, RES_BOTH>(a, f, s);
-    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, f, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, f, s);
-    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, f, s) : go<T, true, false, 4, RES_NONE, true>(a, f, s);
-    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, f, s);
-    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, f, s);
-    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, f, s);
-    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, f, s);
+    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, f, p, s) : go<T, false, true, 4, RES_BOTH>(a, f, p, s);
+    case SK_FINE: return n1 ? go<T, true, false, 4, RES_BOTH>(a, f, p, s) : go<T, true, false, 8, RES_BOTH>(a, f, p, s);
+    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, f, p, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, f, p, s);
+    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, f, p, s) : go<T, true, false, 4, RES_NONE, true>(a, f, p, s);
+    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, f, p, s);
+    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, f, p, s);
+    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, f, p, s);
+    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, f, p, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, const StripLaunch &a, hipStream_t s)
+void strip_prepare(int nu, bool fp64)
 {
-    return fp64 ? launch_strip_t<double>(k, nu, fast, a, s) : launch_strip_t<float>(k, nu, fast, a, s);
+    StripLaunch a;
+    a.n_items = -1;
+    for (int k = SK_DOWN_FIRST; k <= SK_SINGLE; ++k)
+        (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, true, true, a, nullptr)
+                    : launch_strip_t<float>((StripKind)k, nu, true, true, a, nullptr));
+}
+
+hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, bool persistent, const StripLaunch &a,
+                        hipStream_t s)
+{
+    return fp64 ? launch_strip_t<double>(k, nu, fast, persistent, a, s)
+                : launch_strip_t<float>(k, nu, fast, persistent, a, s);
 }
 
 }  // namespace gdf

@@ -63,7 +63,7 @@ __device__ __forceinline__ bool tile_ctx(const SliceIO *io, int n, long long n_t
 __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *range,
                                                      const float2 *pf, const double *pd, int mode,
                                                      double tol, int max_cycles, int count_cycle,
-                                                     SliceState *st, int *active)
+                                                     double stall_ratio, SliceState *st, int *active)
 {
     __shared__ double red[256];
     const int sidx = blockIdx.x;
@@ -98,9 +98,15 @@ __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *ra
     case FIN_CHECK:
     default:
         if (!active[sidx]) return;   // frozen slice keeps its last state
+        const double prev = S.rel;   // the previous check's (0 before the first)
         S.rr = sum;
         S.rel = S.bb > 0.0 ? sqrt(sum / S.bb) : sqrt(sum);
         if (count_cycle) S.cycles += 1;
+        if (stall_ratio > 0.0 && count_cycle && S.cycles >= 2 && prev > 0.0 && S.rel > tol &&
+            S.rel > stall_ratio * prev) {
+            S.stalled = 1;
+            active[sidx] = 0;
+        }
         // Neumann: 1^T A = alpha 1^T, so the constant-mode error of the iterate is
         // exactly -mean(r) / alpha; adding it back removes mean(r) from the residual
         S.shift = pf ? rsum / (S.npx * S.alpha) : 0.0;
@@ -112,11 +118,32 @@ __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *ra
 
 hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_f,
                          const double *partials_d, int mode, double tol, int max_cycles,
-                         int count_cycle, SliceState *state, int *active, hipStream_t s)
+                         int count_cycle, double stall_ratio, SliceState *state, int *active,
+                         hipStream_t s)
 {
     if (n_slices <= 0) return hipSuccess;
     hipLaunchKernelGGL(finish_kernel, dim3(n_slices), dim3(256), 0, s, n_slices, range, partials_f,
-                       partials_d, mode, tol, max_cycles, count_cycle, state, active);
+                       partials_d, mode, tol, max_cycles, count_cycle, stall_ratio, state, active);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void resume_flags_kernel(int n_slices, const SliceState *st, double tol,
+                                                          int max_cycles, int *active, int *only)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_slices) return;
+    const SliceState &S = st[i];
+    const int again = S.status == 0 && !S.stalled && isfinite(S.rel) && S.rel > tol && S.cycles < max_cycles;
+    active[i] = again;
+    only[i] = again;
+}
+
+hipError_t launch_resume_flags(int n_slices, const SliceState *state, double tol, int max_cycles,
+                               int *active, int *only, hipStream_t s)
+{
+    if (n_slices <= 0) return hipSuccess;
+    hipLaunchKernelGGL(resume_flags_kernel, dim3((n_slices + 255) / 256), dim3(256), 0, s, n_slices, state,
+                       tol, max_cycles, active, only);
     return hipGetLastError();
 }
 

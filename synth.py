@@ -167,3 +167,123 @@ def batch_slice(H: int, W: int, slice_seed: int):
 
 
 CONFIG_SEED = {0: 1000, 1: 1001, 2: 1002, 3: 1003, 4: 1004}
+
+
+# ------------------------------------------------------------------------
+# The same recipe evaluated with torch, on any device.  The benchmark's large
+# workloads (thousands of megapixels) are generated on the GPU this way; the
+# numpy functions above stay the definition, and the two agree to rounding
+# (checked on small slices on the CPU).
+
+def _s64(c: int) -> int:
+    """uint64 constant as the int64 with the same bits."""
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _lsr(z, k: int):
+    """Logical right shift of an int64 tensor holding uint64 bits."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _splitmix64_t(z):
+    z = z + _s64(0x9E3779B97F4A7C15)
+    z = (z ^ _lsr(z, 30)) * _s64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(z, 27)) * _s64(0x94D049BB133111EB)
+    return z ^ _lsr(z, 31)
+
+
+def white_noise_t(seed: int, y0: int, y1: int, x0: int, x1: int, device):
+    import torch
+    key = _s64(int(_splitmix64(np.full(1, seed, dtype=np.uint64))[0]))
+    ys = torch.arange(y0, y1, dtype=torch.int64, device=device)[:, None]
+    xs = torch.arange(x0, x1, dtype=torch.int64, device=device)[None, :]
+    h = _splitmix64_t((ys << 32) + xs + key)
+    u1 = (_lsr(h, 32).double() + 0.5) / 4294967296.0
+    u2 = ((h & 0xFFFFFFFF).double() + 0.5) / 4294967296.0
+    return torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * np.pi * u2)
+
+
+def _gauss_taps(sigma: float, truncate: float):
+    r = int(truncate * sigma + 0.5)
+    x = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-0.5 * x * x / (sigma * sigma))
+    return w / w.sum(), r
+
+
+def _filter_axis_t(a, sigma: float, truncate: float, axis: int, mode: str):
+    """1D Gaussian correlation along axis (0 or 1) of a 2D tensor; mode
+    'reflect' (half-sample symmetric) or 'nearest' (edge replicate), as scipy."""
+    import torch
+    w, r = _gauss_taps(sigma, truncate)
+    if axis == 0:
+        a = a.t()
+    n = a.shape[1]
+    if mode == "reflect":
+        if n < r:
+            raise ValueError("axis shorter than the filter radius")
+        left, right = a[:, :r].flip(1), a[:, n - r:].flip(1)
+    else:
+        left, right = a[:, :1].expand(-1, r), a[:, n - 1:].expand(-1, r)
+    p = torch.cat([left, a, right], dim=1)
+    out = torch.zeros_like(a)
+    for k in range(2 * r + 1):
+        out += float(w[k]) * p[:, k:k + n]
+    return out.t().contiguous() if axis == 0 else out
+
+
+def band_noise_t(seed: int, H: int, W: int, y0: int, y1: int, x0: int, x1: int, device):
+    r = _NOISE_R
+    ya, yb = max(0, y0 - r), min(H, y1 + r)
+    xa, xb = max(0, x0 - r), min(W, x1 + r)
+    n = white_noise_t(seed, ya, yb, xa, xb, device)
+    n = _filter_axis_t(n, NOISE_SIGMA, NOISE_TRUNC, 0, "reflect")
+    n = _filter_axis_t(n, NOISE_SIGMA, NOISE_TRUNC, 1, "reflect")
+    n *= NOISE_STD / _noise_gain()
+    return n[y0 - ya:y1 - ya, x0 - xa:x1 - xa]
+
+
+def base_texture_t(seed: int, H: int, W: int, y0: int, y1: int, x0: int, x1: int, device,
+                   n_blobs: int = 40):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cx, cy, sb, amp = _blob_params(rng, H, W, n_blobs)
+    B = band_noise_t(seed, H, W, y0, y1, x0, x1, device).contiguous()
+    for i in range(n_blobs):
+        rad = int(np.ceil(6.0 * sb[i]))
+        ya, yb = max(y0, int(cy[i]) - rad), min(y1, int(cy[i]) + rad + 1)
+        xa, xb = max(x0, int(cx[i]) - rad), min(x1, int(cx[i]) + rad + 1)
+        if ya >= yb or xa >= xb:
+            continue
+        yy = torch.arange(ya, yb, dtype=torch.float64, device=device)[:, None] - cy[i]
+        xx = torch.arange(xa, xb, dtype=torch.float64, device=device)[None, :] - cx[i]
+        B[ya - y0:yb - y0, xa - x0:xb - x0] += amp[i] * torch.exp(-(yy * yy + xx * xx) / (2.0 * sb[i] ** 2))
+    return B
+
+
+def make_stack_t(S: int, H: int, W: int, seed: int, device, ramp: bool = False,
+                 band_rows: int = 2048):
+    """make_stack evaluated with torch on `device` (uint8 tensor [S][H][W])."""
+    import torch
+    gain, off, sx, sy = slice_params(seed, S)
+    out = torch.empty((S, H, W), dtype=torch.uint8, device=device)
+    xx = torch.arange(0, W, dtype=torch.float64, device=device)[None, :] - W / 2.0
+    for ya in range(0, H, band_rows):
+        yb = min(H, ya + band_rows)
+        B = base_texture_t(seed, H, W, ya, yb, 0, W, device)
+        yy = torch.arange(ya, yb, dtype=torch.float64, device=device)[:, None] - H / 2.0
+        for j in range(S):
+            v = float(gain[j]) * B + float(off[j])
+            if ramp:
+                v = v + float(sx[j]) * xx + float(sy[j]) * yy
+            out[j, ya:yb] = torch.clamp(torch.round(v), 0, 255).to(torch.uint8)
+    return out
+
+
+def batch_slice_t(H: int, W: int, slice_seed: int, device):
+    """batch_slice evaluated with torch on `device`: (g_orig uint8, g_smooth float32)."""
+    import torch
+    g_o = make_stack_t(1, H, W, slice_seed, device)[0]
+    B = torch.clamp(torch.round(base_texture_t(slice_seed, H, W, 0, H, 0, W, device)), 0, 255)
+    g_s = _filter_axis_t(B, 1.0, 3.0, 0, "nearest")
+    g_s = _filter_axis_t(g_s, 1.0, 3.0, 1, "nearest")
+    return g_o, g_s.to(torch.float32)

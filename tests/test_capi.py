@@ -60,8 +60,13 @@ def _fuse(**kw):
     (dict(opts=gdf.make_opts(precision=5)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(tile_rows=7)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(out_dtype=0 + 9)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(launch_mode=3)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),
     (dict(wsb=16), gdf.GDF_ENOMEM),
+    # the autotuner validates first; every candidate then fails the workspace check
+    (dict(wsb=16, opts=gdf.make_opts(autotune=True)), gdf.GDF_ENOMEM),
+    (dict(alpha=0.0, opts=gdf.make_opts(autotune=True)), gdf.GDF_EINVAL),
 ])
 def test_fuse_stack_rejects_on_host(kw, status):
     assert _fuse(**kw) == status
@@ -109,3 +114,15 @@ def test_solve_slices_rejects_on_host():
                                    ctypes.byref(om), 1 << 23, 1 << 30, None, None) == gdf.GDF_EINVAL
     assert L.solve_slices_backward(1, d, 1, 1 << 20, 1 << 21, 1 << 22, 0, 1e-6, None, None, None,
                                    ctypes.byref(om), 1 << 23, 16, None, None) == gdf.GDF_ENOMEM
+
+
+def test_autotune_flag_and_workspace():
+    L = gdf.lib()
+    o = gdf.make_opts()
+    o.autotune = 2
+    assert _fuse(opts=o) == gdf.GDF_EINVAL
+    plain = L.gdf_fuse_workspace_size(8, 1000, 700, ctypes.byref(gdf.make_opts()))
+    tuned = L.gdf_fuse_workspace_size(8, 1000, 700, ctypes.byref(gdf.make_opts(autotune=True)))
+    small = L.gdf_fuse_workspace_size(8, 1000, 700, ctypes.byref(gdf.make_opts(tile_rows=32)))
+    # candidates include 32-row items (more items, larger work tables)
+    assert tuned >= max(plain, small) > 0

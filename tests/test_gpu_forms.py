@@ -176,3 +176,59 @@ def test_full_size_plain_fp32_sampled():
         err = np.abs(f[z].cpu().numpy().astype(np.float64) - fz).max()
         print("slice", z, "max abs err", err, rep[z], flush=True)
         assert err <= 1e-3
+
+
+# ----------------------------------------------- launch modes and autotuning
+
+def test_persistent_launch_matches_grid():
+    # 16-row items: several times more work items than the waves resident on
+    # the chip, so the persistent grid really loops
+    stack = synth.make_stack(8, 1024, 1024, seed=31, ramp=True)
+    st = torch.from_numpy(stack).to(DEV)
+    print("persistent vs grid", flush=True)
+    f1, r1 = gdf.fuse_stack(st, 0.01, tile_rows=16, launch_mode="grid")
+    f2, r2 = gdf.fuse_stack(st, 0.01, tile_rows=16, launch_mode="persistent")
+    assert torch.equal(f1, f2)
+    assert [r["vcycles"] for r in r1] == [r["vcycles"] for r in r2]
+    assert all(r["rel_residual"] <= 1e-6 for r in r2)
+
+
+def test_autotuned_uneven_batch_graph():
+    desc = synth.uneven_batch(10, seed=4, max_side=1024)
+    pairs = [synth.batch_slice(H, W, sd) for H, W, _, sd in desc]
+    al = [a for _, _, a, _ in desc]
+    tg = [torch.from_numpy(s).to(DEV) for _, s in pairs]
+    to = [torch.from_numpy(o).to(DEV) for o, _ in pairs]
+    print("autotune", [(H, W) for H, W, _, _ in desc], flush=True)
+    f1, rep1 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, autotune=True)
+    t = gdf.autotune_last()
+    print("tuned", t, flush=True)
+    assert t["nu"] in (1, 2) and t["tile_rows"] in (0, 32, 64, 128, 256) and t["launch_mode"] in (1, 2)
+    assert all(r["rel_residual"] <= 1e-6 and r["status"] == gdf.GDF_OK for r in rep1)
+    # cached choice: the same settings given explicitly reproduce the result
+    f2, rep2 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, nu=t["nu"],
+                                tile_rows=t["tile_rows"], launch_mode=t["launch_mode"])
+    for a, b in zip(f1, f2):
+        assert torch.equal(a, b)
+    i = min(range(len(desc)), key=lambda k: desc[k][0] * desc[k][1])
+    o, s = pairs[i]
+    fr = oracle.solve(s, o.astype(np.float64), al[i], tol=1e-11)
+    assert np.abs(f1[i].cpu().numpy() - fr).max() <= 1e-3
+
+
+def test_fp32_floor_slice_escalates_to_refinement():
+    # slice 56 of the seeded 512-slice uneven batch: 93% of it clips to 0, so
+    # ||b|| is small against the correction and FP32 iterates stall near
+    # 1.2e-6; the solver detects the stall and re-solves the slice with FP32
+    # V-cycles inside FP64 refinement
+    H, W, a, sd = synth.uneven_batch(512, seed=1002)[56]
+    o, s = synth.batch_slice(H, W, sd)
+    print("floor slice", H, W, a, flush=True)
+    for graph in (False, True):
+        f, rep = gdf.solve_slices([torch.from_numpy(s).to(DEV)], [torch.from_numpy(o).to(DEV)], [a],
+                                  tol=1e-6, use_graph=graph)
+        print(rep, flush=True)
+        assert rep[0]["status"] == gdf.GDF_OK and rep[0]["rel_residual"] <= 1e-6
+        assert rep[0]["vcycles"] < 40
+        fr = oracle.solve(s, o.astype(np.float64), a, tol=1e-12)
+        assert np.abs(f[0].cpu().numpy() - fr).max() <= 1e-3
