@@ -216,7 +216,9 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
 /* ------------------------------------------------------------------------ */
 /* Kernel timing for measurement.  When enabled, the library brackets every
  * launch of the named kernel class with HIP events on the launch stream and
- * accumulates their durations.  Classes: "smooth", "vcycle_fine" (the fused
+ * accumulates their durations.  gdf_profile_enable(1) times every class,
+ * gdf_profile_enable(2) only "vcycle_fine" (fewer events in flight),
+ * gdf_profile_enable(0) stops.  Classes: "smooth", "vcycle_fine" (the fused
  * finest-level post-/pre-smoothing pass), "restrict_first", "coarse",
  * "finalize", "prep", "refine", "adjoint".  Returns the number of launches
  * recorded and writes the summed milliseconds and the summed algorithmic

@@ -403,8 +403,9 @@ def __getattr__(name):
 
 # ------------------------------------------------------------------ profiling
 
-def profile_enable(on=True):
-    lib().gdf_profile_enable(int(bool(on)))
+def profile_enable(on=True, fine_only=False):
+    """Time kernel classes with HIP events (fine_only: only "vcycle_fine")."""
+    lib().gdf_profile_enable(0 if not on else (2 if fine_only else 1))
 
 
 def profile_reset():

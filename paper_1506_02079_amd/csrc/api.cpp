@@ -60,6 +60,11 @@ constexpr double kSigmaStop = 2.0;
 // An FP32 V-cycle that shrinks the residual by less than this factor (the
 // usual factor is 0.05 - 0.3) means the iterate has reached FP32's floor.
 constexpr double kStallRatio = 0.6;
+#ifndef GDF_MERGED_LAUNCH
+#define GDF_MERGED_LAUNCH 1
+#endif
+// one launch per strip pass (unguarded and guarded items together) or two
+constexpr bool kMergedLaunch = GDF_MERGED_LAUNCH != 0;
 constexpr int kCoarsePasses = 3;   // x 2 sweeps on the coarsest level
 constexpr int kTileW = 64, kTileH = 16;
 constexpr size_t kAlign = 256;
@@ -519,6 +524,7 @@ gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vecto
 
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+bool g_prof_fine_only = false;   // mode 2: only the fused finest pass is timed
 struct ProfRec { int cls; hipEvent_t a, b; double bytes; };
 std::vector<ProfRec> g_prof_recs;
 std::vector<hipEvent_t> g_prof_pool;
@@ -558,7 +564,7 @@ struct ProfScope {
     hipStream_t s;
     ProfScope(int cls, double bytes, hipStream_t st, bool capturing) : on(false), s(st)
     {
-        if (!g_prof_on || capturing) return;
+        if (!g_prof_on || capturing || (g_prof_fine_only && cls != PC_FINE)) return;
         std::lock_guard<std::mutex> lk(g_prof_mu);
         rec.cls = cls;
         rec.bytes = bytes;
@@ -640,14 +646,23 @@ struct Run {
         a.cycles_stride = (int)(sizeof(SliceState) / sizeof(int));
         a.active = active;
         a.partials = partials;
-        ProfScope ps(cls, g_prof_on ? pass_bytes(li, per_px) : 0.0, s, capturing);
-        a.items = items + L.off;
-        a.n_items = L.n_fast;
+        const bool timed = g_prof_on && (!g_prof_fine_only || cls == PC_FINE);
+        ProfScope ps(cls, timed ? pass_bytes(li, per_px) : 0.0, s, capturing);
         const bool pers = P.o.launch == GDF_LAUNCH_PERSISTENT;
-        HIP_TRY(launch_strip(kind, P.o.nu, fp64, true, pers, a, s));
+        a.items = items + L.off;
+        if (kMergedLaunch) {
+            a.n_items = L.count;
+            a.n_fast = L.n_fast;
+            HIP_TRY(launch_strip(kind, P.o.nu, fp64, SV_MERGED, pers, a, s));
+            return GDF_OK;
+        }
+        a.n_items = L.n_fast;
+        a.n_fast = L.n_fast;
+        HIP_TRY(launch_strip(kind, P.o.nu, fp64, SV_FAST, pers, a, s));
         a.items = items + L.off + L.n_fast;
         a.n_items = L.count - L.n_fast;
-        HIP_TRY(launch_strip(kind, P.o.nu, fp64, false, pers, a, s));
+        a.n_fast = 0;
+        HIP_TRY(launch_strip(kind, P.o.nu, fp64, SV_GUARDED, pers, a, s));
         return GDF_OK;
     }
 
@@ -900,6 +915,12 @@ gdf_status solve_body(Run &R, const SolveIO &x)
 {
     const Plan &P = R.P;
     gdf_status r;
+    // algorithmic bytes per pixel of the output pass: iterate and b (or the
+    // FP64 iterate), g_o, f
+    const double go_b = x.go_dtype == GDF_U8 ? 1.0 : (x.go_dtype == GDF_F32 ? 4.0 : 8.0);
+    const double f_b = P.o.out_dtype == GDF_F64 ? 8.0 : 4.0;
+    double all_px = 0.0;
+    for (int i = 0; i < P.n; ++i) all_px += (double)P.g[i].H * P.g[i].W;
     if (!P.mixed) {
         // rounds after the first resume slices whose exact residual missed tol
         // (decided on the host, or on the device inside a captured graph, which
@@ -907,7 +928,8 @@ gdf_status solve_body(Run &R, const SolveIO &x)
         for (int round = 0; round < 4; ++round) {
             if ((r = R.iterate(P.fp64, round == 0, round ? 2 : 0))) return r;
             {
-                ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
+                // (later rounds touch only the resumed slices: not counted)
+                ProfScope ps(PC_FINALIZE, round ? 0.0 : all_px * (2.0 * P.esz + go_b + f_b), R.s, R.capturing);
                 HIP_TRY(launch_finalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
                                         R.desc, R.st, round ? R.only : nullptr, R.partd, R.s));
             }
@@ -926,7 +948,7 @@ gdf_status solve_body(Run &R, const SolveIO &x)
     gdf_status q;
     if ((q = mixed_iterate(R, x.gs_dtype, x.gs, x.go_dtype, x.go, nullptr))) return q;
     {
-        ProfScope ps(PC_FINALIZE, 0.0, R.s, R.capturing);
+        ProfScope ps(PC_FINALIZE, all_px * (8.0 + go_b + f_b), R.s, R.capturing);
         HIP_TRY(launch_finalize64(x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
                                   R.u64tab, R.st, R.desc, R.s));
     }
@@ -1096,6 +1118,7 @@ void gdf_profile_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     g_prof_on = on != 0;
+    g_prof_fine_only = on == 2;
 }
 
 void gdf_profile_reset(void)

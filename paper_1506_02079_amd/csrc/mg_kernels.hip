@@ -68,6 +68,59 @@ template <typename T> struct Vec2 { typedef T type __attribute__((ext_vector_typ
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Values every lane of the wave holds alike, moved into scalar registers (the
+// work item and level descriptor are read with vector loads, so the compiler
+// cannot tell they are uniform; scalar copies keep the address arithmetic on
+// the scalar unit and allow scalar-base loads).
+template <typename P> __device__ __forceinline__ P *uniform_ptr(P *p)
+{
+    const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return reinterpret_cast<P *>(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double uniform_d(double d)
+{
+    const unsigned long long v = (unsigned long long)__double_as_longlong(d);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ Item uniform_item(const Item &i)
+{
+    return Item{uniform(i.lev), uniform(i.x0), uniform(i.y0), uniform(i.y1), uniform(i.pidx)};
+}
+__device__ __forceinline__ LevelDesc uniform_level(const LevelDesc &d)
+{
+    LevelDesc r;
+    r.u[0] = uniform_ptr(d.u[0]);
+    r.u[1] = uniform_ptr(d.u[1]);
+    r.b = uniform_ptr(d.b);
+    r.ec = uniform_ptr(d.ec);
+    r.bc = uniform_ptr(d.bc);
+    r.H = uniform(d.H);
+    r.W = uniform(d.W);
+    r.pitch = uniform(d.pitch);
+    r.Hc = uniform(d.Hc);
+    r.Wc = uniform(d.Wc);
+    r.pitch_c = uniform(d.pitch_c);
+    r.sigma = uniform_d(d.sigma);
+    r.wxL = uniform_d(d.wxL);
+    r.wyL = uniform_d(d.wyL);
+    r.bshift = uniform_ptr(d.bshift);
+    r.slice = uniform(d.slice);
+    r.pad_ = 0;
+    return r;
+}
+
+// Load from a uniform (scalar) base plus a 32-bit per-lane byte offset, the
+// form of the scalar-base global load (no per-lane 64-bit address math).
+template <typename X>
+__device__ __forceinline__ X ld_at(const GDF_GLOBAL void *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const GDF_GLOBAL X *>(reinterpret_cast<const GDF_GLOBAL char *>(base) + byte_off);
+}
+
 // Map hardware block ids to logical blocks so that consecutive logical blocks
 // (neighbouring strips, which share halo rows/columns) run on the same XCD and
 // hit the same L2.  Hardware dispatch places block b on XCD b % 8; the grid
@@ -82,9 +135,12 @@ __device__ __forceinline__ int xcd_logical_block()
 
 // length of the load queue for a register ring of rs rows (a divisor of rs, so
 // that queue slots are compile-time constants in the unrolled ring loop)
+#ifndef GDF_QUEUE_MAX
+#define GDF_QUEUE_MAX 6
+#endif
 constexpr int queue_len(int rs)
 {
-    for (int q = 6; q >= 2; --q)
+    for (int q = GDF_QUEUE_MAX; q >= 2; --q)
         if (rs % q == 0) return q;
     return 1;
 }
@@ -115,9 +171,9 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     using V2 = typename Vec2<T>::type;
 
     const int lane = threadIdx.x & (kWave - 1);
-    const Item it = a.items[item_id];
-    const LevelDesc L = a.levs[it.lev];
-    if (!a.active[L.slice]) {
+    const Item it = uniform_item(a.items[item_id]);
+    const LevelDesc L = uniform_level(a.levs[it.lev]);
+    if (!uniform(a.active[L.slice])) {
         if ((RMODE & RES_NORM) && lane == 0) a.partials[it.pidx] = make_float2(0.f, 0.f);
         return;
     }
@@ -132,6 +188,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     const bool in0 = cx0 >= 0 && cx0 < W;
     const bool in1 = cx0 + 1 >= 0 && cx0 + 1 < W;
     const int cxl = min(max(cx0, 0), (W - 1) & ~1);  // clamped, even: safe vector address
+    const unsigned cxb = (unsigned)cxl * (unsigned)sizeof(T);   // byte offset of the lane's pair
     const bool own = in0 && cx0 >= it.x0 && cx0 < it.x0 + VW;
     const T m0 = in0 ? T(1) : T(0), m1 = in1 ? T(1) : T(0);
     // neighbour-inside masks (zero for columns outside the slice)
@@ -181,11 +238,11 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     // level 0: the slice's mean right-hand side is removed on load, so the
     // iterate is the zero-mean part of the correction (smaller values, smaller
     // FP32 rounding); the mean is added back when f is formed
-    const T bsh = bshift_p ? (T)*bshift_p : T(0);
+    const T bsh = bshift_p ? (T)uniform_d(*bshift_p) : T(0);
     // (selects, not a runtime index into the descriptor's array: that would spill it)
     int in_sel = a.in_sel, out_sel = a.out_sel;
     if (a.cycles) {   // per-slice parity: the latest iterate sits in buffer cycles & 1
-        in_sel = a.cycles[(size_t)L.slice * a.cycles_stride] & 1;
+        in_sel = uniform(a.cycles[(size_t)L.slice * a.cycles_stride]) & 1;
         out_sel = in_sel ^ 1;
     }
     const GDF_GLOBAL T *__restrict__ usrc = (const GDF_GLOBAL T *)(in_sel ? L.u[1] : L.u[0]);
@@ -198,9 +255,12 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     const bool ledge = lc == 0, redge = PROLONG && lc == Wc - 1;
     const GDF_GLOBAL T *__restrict__ ecp = (const GDF_GLOBAL T *)L.ec;
     // raw coarse value (clamped row and column: always a valid address)
-    auto ld_coarse = [ecp, lcl, Hc, pitch_c](int m) -> T {
+    // (uniform row base + 32-bit lane offset: scalar-base addressing, no
+    // per-lane 64-bit address arithmetic)
+    const unsigned lclb = (unsigned)lcl * (unsigned)sizeof(T);
+    auto ld_coarse = [ecp, lclb, Hc, pitch_c](int m) -> T {
         m = min(max(m, 0), Hc - 1);
-        return ecp[(size_t)m * pitch_c + lcl];
+        return ld_at<T>(ecp + (size_t)m * pitch_c, lclb);
     };
 
     // ---- restriction state: a coarse cell's right-hand side is the sum of its
@@ -222,15 +282,26 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     // ---- load queue: raw values of the rows ybase + t + 1 .. ybase + t + Q - 1,
     // issued with clamped (always valid) addresses and consumed Q - 1 steps
     // later, when the row enters the ring (masks and corrections applied there)
+    // In the unguarded variant the first half-sweep (red) runs on every row
+    // before anything reads the row's red pixel, and a Gauss-Seidel update
+    // does not read the old value of the pixel it updates: the old red value
+    // is dead.  Only the lane's black column (1 - row parity; ybase and cx0 are
+    // even) is loaded, so no load result is dead on arrival (a dead half of a
+    // vector load would make the compiler wait for the load to land before
+    // reusing its register).
     V2 qb[Q], qu[Q];
+    T qus[Q];           // unguarded: the black column only
     T qe0[Q], qe1[Q];   // coarse rows m and m -/+ 1 of the row (prolongation)
-    auto issue_row = [&](int tq, V2 &vb, V2 &vu, T &ve0, T &ve1) {
+    auto issue_row = [&](int tq, int par, V2 &vb, V2 &vu, T &vus, T &ve0, T &ve1) {
         // past the last loaded row the queue re-reads that row (cache hits);
         // outside the slice the row is clamped (the commit zeroes it)
         const int yq = ybase + min(tq, NL - 1);
-        const size_t ro = (size_t)min(max(yq, 0), H - 1) * pitch + cxl;
-        vb = *reinterpret_cast<const GDF_GLOBAL V2 *>(bsrc + ro);
-        if (!ZERO) vu = *reinterpret_cast<const GDF_GLOBAL V2 *>(usrc + ro);
+        const size_t rowo = (size_t)min(max(yq, 0), H - 1) * pitch;   // uniform
+        vb = ld_at<V2>(bsrc + rowo, cxb);
+        if (!ZERO) {
+            if (FAST) vus = ld_at<T>(usrc + rowo, cxb + (1 - par) * (unsigned)sizeof(T));
+            else vu = ld_at<V2>(usrc + rowo, cxb);
+        }
         if (PROLONG) {
             const int m = yq >> 1;
             ve0 = ld_coarse(m);
@@ -238,7 +309,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         }
     };
 #pragma unroll
-    for (int q = 0; q < Q - 1; ++q) issue_row(q, qb[q], qu[q], qe0[q], qe1[q]);
+    for (int q = 0; q < Q - 1; ++q) issue_row(q, q & 1, qb[q], qu[q], qus[q], qe0[q], qe1[q]);
 
     const int T_end = NL + 2 * NS;
     for (int tb = 0; tb < T_end; tb += RS) {
@@ -248,8 +319,8 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
             // ------------------------------------------------ load (stage 0)
             // issue and commit are unconditional: a conditional consumer would let
             // the compiler sink each load down to it and wait right there
-            issue_row(t + Q - 1, qb[(k + Q - 1) % Q], qu[(k + Q - 1) % Q], qe0[(k + Q - 1) % Q],
-                      qe1[(k + Q - 1) % Q]);
+            issue_row(t + Q - 1, (k + Q - 1) & 1, qb[(k + Q - 1) % Q], qu[(k + Q - 1) % Q],
+                      qus[(k + Q - 1) % Q], qe0[(k + Q - 1) % Q], qe1[(k + Q - 1) % Q]);
             {
                 // rows past the loaded range enter the ring as throwaway copies: no
                 // stage inside its cone of validity reads them
@@ -273,8 +344,14 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                     b[k][0] = qb[qs].x - bsh;
                     b[k][1] = qb[qs].y - bsh;
                     if (!ZERO) {
-                        u[k][0] = qu[qs].x + cor0;
-                        u[k][1] = qu[qs].y + cor1;
+                        // row parity = k parity (ybase and tb even): black column 1 - (k & 1)
+                        if (k & 1) {
+                            u[k][0] = qus[qs] + cor0;
+                            u[k][1] = T(0);   // red: rewritten by the first half-sweep unread
+                        } else {
+                            u[k][0] = T(0);
+                            u[k][1] = qus[qs] + cor1;
+                        }
                     } else {
                         u[k][0] = u[k][1] = T(0);
                     }
@@ -402,13 +479,20 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 // Each wave takes work items w, w + P, w + 2P, ... (P = waves in the grid).
 // With a grid covering the list every wave runs one item; a persistent grid
 // (capped at the waves the chip holds at once) loops over the list.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+// VAR: SV_GUARDED / SV_FAST run one variant on every item; SV_MERGED runs the
+// unguarded variant on items [0, n_fast) and the guarded one on the rest, in
+// one launch.
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
     const int stride = gridDim.x * kWavesPerBlock;
     for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
-         id += stride)
-        strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>(a, id);
+         id += stride) {
+        if (VAR == SV_FAST || (VAR == SV_MERGED && id < a.n_fast))
+            strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, id);
+        else
+            strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, id);
+    }
 }
 
 int strip_halo(StripKind k, int nu)
@@ -439,47 +523,51 @@ static int resident_blocks(const void *kernel)
 
 // Persistent grid size of one kernel instantiation, queried once (a query that
 // fails is retried on the next call).  One device type per process.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
 static int persistent_cap()
 {
     static std::atomic<int> cap{0};
     int c = cap.load(std::memory_order_relaxed);
     if (c == 0) {
-        c = resident_blocks(reinterpret_cast<const void *>(&strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>));
+        c = resident_blocks(reinterpret_cast<const void *>(&strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, VAR>));
         if (c > 0) cap.store(c, std::memory_order_relaxed);
     }
     return c;
 }
 
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
 static hipError_t go_variant(const StripLaunch &a, bool persistent, hipStream_t s)
 {
     const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
     int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
     if (persistent) {
-        const int cap = persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>();
+        const int cap = persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, VAR>();
         if (cap >= 8 && grid > cap) grid = cap;
     }
-    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, FAST>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, VAR>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 // n_items < 0: only resolve the persistent grid sizes (no launch)
 template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
-static hipError_t go(const StripLaunch &a, bool fast, bool persistent, hipStream_t s)
+static hipError_t go(const StripLaunch &a, int var, bool persistent, hipStream_t s)
 {
     if (a.n_items < 0) {
-        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, true>();
-        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, false>();
+        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_FAST>();
+        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_GUARDED>();
+        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_MERGED>();
         return hipSuccess;
     }
     if (a.n_items == 0) return hipSuccess;
-    return fast ? go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, persistent, s)
-                : go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, persistent, s);
+    switch (var) {
+    case SV_FAST: return go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_FAST>(a, persistent, s);
+    case SV_MERGED: return go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_MERGED>(a, persistent, s);
+    default: return go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_GUARDED>(a, persistent, s);
+    }
 }
 
 template <typename T>
-static hipError_t launch_strip_t(StripKind k, int nu, bool f, bool p, const StripLaunch &a, hipStream_t s)
+static hipError_t launch_strip_t(StripKind k, int nu, int f, bool p, const StripLaunch &a, hipStream_t s)
 {
     const bool n1 = nu == 1;
     switch (k) {
@@ -500,15 +588,15 @@ void strip_prepare(int nu, bool fp64)
     StripLaunch a;
     a.n_items = -1;
     for (int k = SK_DOWN_FIRST; k <= SK_SINGLE; ++k)
-        (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, true, true, a, nullptr)
-                    : launch_strip_t<float>((StripKind)k, nu, true, true, a, nullptr));
+        (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, SV_FAST, true, a, nullptr)
+                    : launch_strip_t<float>((StripKind)k, nu, SV_FAST, true, a, nullptr));
 }
 
-hipError_t launch_strip(StripKind k, int nu, bool fp64, bool fast, bool persistent, const StripLaunch &a,
+hipError_t launch_strip(StripKind k, int nu, bool fp64, int variant, bool persistent, const StripLaunch &a,
                         hipStream_t s)
 {
-    return fp64 ? launch_strip_t<double>(k, nu, fast, persistent, a, s)
-                : launch_strip_t<float>(k, nu, fast, persistent, a, s);
+    return fp64 ? launch_strip_t<double>(k, nu, variant, persistent, a, s)
+                : launch_strip_t<float>(k, nu, variant, persistent, a, s);
 }
 
 }  // namespace gdf

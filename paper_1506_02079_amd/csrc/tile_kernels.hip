@@ -3,11 +3,12 @@
 // adjoint assembly, the FP64 refinement step of the mixed-precision solve,
 // and the fixed-order per-slice reductions.
 //
-// All of them walk 64 x 16 pixel tiles (256 threads; thread (tx, ty) handles
-// rows ty, ty + 4, ty + 8, ty + 12 of column tx), so rows are read coalesced;
-// stencil neighbours come from the same or adjacent rows and hit L2.  Partial
-// sums are reduced per tile in FP64 and written to a per-tile slot; a second
-// kernel sums each slice's slots in a fixed order.
+// All of them walk 64 x 16 pixel tiles with 256 threads; each thread handles
+// four consecutive pixels of one tile row (vector loads and stores), so rows
+// are read coalesced; horizontal stencil neighbours come from the adjacent
+// threads by DPP row shifts, vertical ones from the adjacent rows (L2 hits).
+// Partial sums are reduced per tile in FP64 and written to a per-tile slot; a
+// second kernel sums each slice's slots in a fixed order.
 #include "internal.h"
 
 namespace gdf {
@@ -26,33 +27,94 @@ __device__ __forceinline__ int find_slice(const SliceIO *io, int n, long long ti
 
 template <typename TV> __device__ __forceinline__ double ldv(const TV *p, long long i) { return (double)p[i]; }
 
+// Sum over a 256-thread block in a fixed order (butterfly within each wave,
+// then the four wave sums in order), so results do not depend on scheduling.
 __device__ double block_sum(double v, double *red)
 {
-    red[threadIdx.x] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    const double r = red[0];
+    const double r = (red[0] + red[1]) + (red[2] + red[3]);
     __syncthreads();
     return r;
 }
 
-struct TileCtx {
-    int si, x, ty0;
+// ---- quad mapping: thread t of a tile handles the four pixels x .. x + 3 of
+// one row, x = tile_x0 + 4 (t & 15), y = ty0 + (t >> 4).  The 16 threads of a
+// tile row form one DPP row, so horizontal neighbours across threads come from
+// row shifts; the tile's two outer neighbours are loaded.
+
+template <typename T> struct Vec4 { typedef T type __attribute__((ext_vector_type(4))); };
+
+// p[i .. i + 3] as doubles; elements at or past nvalid read as 0
+template <typename TV>
+__device__ __forceinline__ void load4(const TV *p, long long i, int nvalid, double v[4])
+{
+    using V = typename Vec4<TV>::type;
+    if (nvalid >= 4 && (reinterpret_cast<uintptr_t>(p + i) & (sizeof(V) - 1)) == 0) {
+        const V q = *reinterpret_cast<const V *>(p + i);
+        v[0] = (double)q.x;
+        v[1] = (double)q.y;
+        v[2] = (double)q.z;
+        v[3] = (double)q.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = k < nvalid ? (double)p[i + k] : 0.0;
+    }
+}
+
+template <typename TV>
+__device__ __forceinline__ void store4(TV *p, long long i, int nvalid, const double v[4])
+{
+    using V = typename Vec4<TV>::type;
+    if (nvalid >= 4 && (reinterpret_cast<uintptr_t>(p + i) & (sizeof(V) - 1)) == 0) {
+        V q;
+        q.x = (TV)v[0];
+        q.y = (TV)v[1];
+        q.z = (TV)v[2];
+        q.w = (TV)v[3];
+        *reinterpret_cast<V *>(p + i) = q;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nvalid) p[i + k] = (TV)v[k];
+    }
+}
+
+// value of the previous / next thread in the 16-lane DPP row (0 at the row ends)
+__device__ __forceinline__ double row_prev(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x111, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x111, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double row_next(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x101, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x101, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+struct QuadCtx {
+    int si, x, y, nvalid;   // nvalid: pixels of the quad inside the row (<= 0: none)
+    bool row_in;
     SliceIO P;
 };
 
-__device__ __forceinline__ bool tile_ctx(const SliceIO *io, int n, long long n_tiles, TileCtx &c)
+__device__ __forceinline__ bool quad_ctx(const SliceIO *io, int n, long long n_tiles, QuadCtx &c)
 {
     const long long tile = blockIdx.x;
     if (tile >= n_tiles) return false;
     c.si = find_slice(io, n, tile);
     c.P = io[c.si];
     const long long lt = tile - c.P.tile_begin;
-    c.x = (int)(lt % c.P.tiles_x) * kTileW + (threadIdx.x & 63);
-    c.ty0 = (int)(lt / c.P.tiles_x) * kTileH;
+    c.x = (int)(lt % c.P.tiles_x) * 64 + 4 * (threadIdx.x & 15);
+    c.y = (int)(lt / c.P.tiles_x) * 16 + (threadIdx.x >> 4);
+    c.nvalid = min(4, c.P.W - c.x);
+    c.row_in = c.y < c.P.H && c.nvalid > 0;
     return true;
 }
 
@@ -65,7 +127,7 @@ __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *ra
                                                      double tol, int max_cycles, int count_cycle,
                                                      double stall_ratio, SliceState *st, int *active)
 {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int sidx = blockIdx.x;
     if (sidx >= n_slices) return;
     const int b0 = range[2 * sidx], b1 = range[2 * sidx + 1];
@@ -149,41 +211,50 @@ hipError_t launch_resume_flags(int n_slices, const SliceState *state, double tol
 
 // --------------------------------------------------------------- prep ---
 
-// b_u = alpha (g_s - g_o) and partial sums of ||alpha g_s + L g_o||^2 and ||b_u||^2.
+// b_u = alpha (g_s - g_o) and partial sums of ||alpha g_s + L g_o||^2, ||b_u||^2
+// and sum(b_u).  Quad mapping.
 template <typename T, typename TS, typename TO>
 __global__ __launch_bounds__(256) void prep_kernel(const TS *gs, const TO *go, const SliceIO *io,
                                                    int n_slices, long long n_tiles,
                                                    const LevelDesc *levs, double *part_bb,
                                                    double *part_b0, double *part_bs)
 {
-    __shared__ double red[256];
-    TileCtx c;
-    if (!tile_ctx(io, n_slices, n_tiles, c)) return;
+    __shared__ double red[4];
+    QuadCtx c;
+    if (!quad_ctx(io, n_slices, n_tiles, c)) return;
     const SliceIO &P = c.P;
     const LevelDesc &L = levs[P.lev0];
-    const int x = c.x;
+    const int x = c.x, y = c.y, nv = c.row_in ? c.nvalid : 0;
     const double al = P.alpha;
-    double sbb = 0.0, sb0 = 0.0, sbs = 0.0;
-    T *bdst = static_cast<T *>(L.b);
+    const long long go_row = P.off_go + (long long)min(y, P.H - 1) * P.pitch_go;
+    double o[4], on[4], os[4], sv[4];
+    load4(go, go_row + x, nv, o);
+    load4(go, go_row - P.pitch_go + x, (y > 0) ? nv : 0, on);
+    load4(go, go_row + P.pitch_go + x, (y < P.H - 1) ? nv : 0, os);
+    load4(gs, P.off_gs + (long long)min(y, P.H - 1) * P.pitch_gs + x, nv, sv);
+    double ol = row_prev(o[3]), orr = row_next(o[0]);
+    const int g = threadIdx.x & 15;
+    if (nv > 0 && g == 0 && x > 0) ol = (double)go[go_row + x - 1];
+    if (nv > 0 && g == 15 && x + nv < P.W) orr = (double)go[go_row + x + nv];
+    double sbb = 0.0, sb0 = 0.0, sbs = 0.0, bq[4];
 #pragma unroll
-    for (int r0 = 0; r0 < kTileH; r0 += 4) {
-        const int y = c.ty0 + r0 + (threadIdx.x >> 6);
-        if (y >= P.H || x >= P.W) continue;
-        const long long go_row = P.off_go + (long long)y * P.pitch_go;
-        const double o = ldv(go, go_row + x);
-        const double sv = ldv(gs, P.off_gs + (long long)y * P.pitch_gs + x);
+    for (int k = 0; k < 4; ++k) {
+        const double l = k == 0 ? ol : o[k - 1], r = k == 3 ? orr : o[k + 1];
         double lap = 0.0;   // (L g_o)_p over in-slice neighbours
-        if (x > 0) lap += o - ldv(go, go_row + x - 1);
-        if (x < P.W - 1) lap += o - ldv(go, go_row + x + 1);
-        if (y > 0) lap += o - ldv(go, go_row - P.pitch_go + x);
-        if (y < P.H - 1) lap += o - ldv(go, go_row + P.pitch_go + x);
-        const double bf = al * sv + lap;
-        const T bu = (T)(al * (sv - o));
-        bdst[(size_t)y * L.pitch + x] = bu;
-        sbb += bf * bf;
-        sb0 += (double)bu * (double)bu;
-        sbs += (double)bu;
+        if (x + k > 0) lap += o[k] - l;
+        if (x + k < P.W - 1) lap += o[k] - r;
+        if (y > 0) lap += o[k] - on[k];
+        if (y < P.H - 1) lap += o[k] - os[k];
+        const double bf = al * sv[k] + lap;
+        const T bu = (T)(al * (sv[k] - o[k]));
+        bq[k] = (double)bu;
+        if (k < nv) {
+            sbb += bf * bf;
+            sb0 += (double)bu * (double)bu;
+            sbs += (double)bu;
+        }
     }
+    store4(static_cast<T *>(L.b), (long long)min(y, P.H - 1) * L.pitch + x, nv, bq);
     const double tbb = block_sum(sbb, red);
     const double tb0 = block_sum(sb0, red);
     const double tbs = block_sum(sbs, red);
@@ -225,7 +296,8 @@ hipError_t launch_prep(bool fp64, int gs_dtype, const void *gs, int go_dtype, co
 // ----------------------------------------------------------- finalize ---
 
 // f = g_o + u, and partial sums of the FP64 residual ||b_u - A u||^2 of the
-// unrounded g_o + u (A(g_o + u) - (alpha g_s + L g_o) = A u - b_u).
+// unrounded g_o + u (A(g_o + u) - (alpha g_s + L g_o) = A u - b_u).  Quad
+// mapping: one tile row of four-pixel vectors per thread.
 template <typename T, typename TO, typename TF>
 __global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, const SliceIO *io,
                                                        int n_slices, long long n_tiles,
@@ -233,37 +305,46 @@ __global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, cons
                                                        const SliceState *st, const int *only,
                                                        double *part_rr)
 {
-    __shared__ double red[256];
-    TileCtx c;
-    if (!tile_ctx(io, n_slices, n_tiles, c)) return;
+    __shared__ double red[4];
+    QuadCtx c;
+    if (!quad_ctx(io, n_slices, n_tiles, c)) return;
     if (only && !only[c.si]) return;   // uniform per block: keeps this slice's partial sum
     const SliceIO &P = c.P;
     const LevelDesc &L = levs[P.lev0];
-    const int x = c.x;
+    const int x = c.x, y = c.y, nv = c.row_in ? c.nvalid : 0;
     const double sg = P.alpha;
     const T *u = static_cast<const T *>(L.u[st[c.si].cycles & 1]);
     const T *bu = static_cast<const T *>(L.b);
     // full correction = uoff (mean removed on load) + u + shift (constant-mode
     // correction); constants cancel in L, and b is used as stored
     const double shift = st[c.si].shift + st[c.si].uoff;
-    const int pu = L.pitch;
-    double srr = 0.0;
+    const long long pu = L.pitch;
+    const long long p = (long long)min(y, P.H - 1) * pu + x;   // clamped row: loads stay in the slice
+    double uc[4], un[4], us[4], bb[4];
+    load4(u, p, nv, uc);
+    load4(bu, p, nv, bb);
+    load4(u, p - pu, (y > 0) ? nv : 0, un);
+    load4(u, p + pu, (y < P.H - 1) ? nv : 0, us);
+    // horizontal neighbours of the quad's first and last pixel
+    double ul = row_prev(uc[3]), ur = row_next(uc[0]);
+    const int g = threadIdx.x & 15;
+    if (nv > 0 && g == 0 && x > 0) ul = (double)u[p - 1];
+    if (nv > 0 && (g == 15 || nv < 4) && x + nv < P.W) ur = (double)u[p + nv];
+    double srr = 0.0, o[4], fo[4];
+    load4(go, P.off_go + (long long)y * P.pitch_go + x, nv, o);
 #pragma unroll
-    for (int r0 = 0; r0 < kTileH; r0 += 4) {
-        const int y = c.ty0 + r0 + (threadIdx.x >> 6);
-        if (y >= P.H || x >= P.W) continue;
-        const size_t p = (size_t)y * pu + x;
-        const double uc = (double)u[p] + shift;
+    for (int k = 0; k < 4; ++k) {
+        const double l = k == 0 ? ul : uc[k - 1], r = k == 3 ? ur : uc[k + 1];
         double acc = 0.0;
-        if (x > 0) acc += uc - ((double)u[p - 1] + shift);
-        if (x < P.W - 1) acc += uc - ((double)u[p + 1] + shift);
-        if (y > 0) acc += uc - ((double)u[p - pu] + shift);
-        if (y < P.H - 1) acc += uc - ((double)u[p + pu] + shift);
-        const double res = (double)bu[p] - sg * uc - acc;
-        srr += res * res;
-        const double o = ldv(go, P.off_go + (long long)y * P.pitch_go + x);
-        f[P.off_f + (long long)y * P.pitch_f + x] = (TF)(o + uc);
+        if (x + k > 0) acc += uc[k] - l;
+        if (x + k < P.W - 1) acc += uc[k] - r;
+        if (y > 0) acc += uc[k] - un[k];
+        if (y < P.H - 1) acc += uc[k] - us[k];
+        const double res = bb[k] - sg * (uc[k] + shift) - acc;
+        if (k < nv) srr += res * res;
+        fo[k] = o[k] + (uc[k] + shift);
     }
+    store4(f, P.off_f + (long long)y * P.pitch_f + x, nv, fo);
     const double t = block_sum(srr, red);
     if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
 }
@@ -298,26 +379,28 @@ hipError_t launch_finalize(bool fp64, int go_dtype, const void *go, int out_dtyp
 }
 
 // ------------------------------------------------------------ adjoint ---
+//
+// These kernels use the quad mapping (four pixels of one tile row per thread).
 
 template <typename T>
 __global__ __launch_bounds__(256) void prep_adjoint_kernel(const T *gf, const SliceIO *io, int n,
                                                            long long n_tiles, const LevelDesc *levs,
                                                            double *part_bb, double *part_bs)
 {
-    __shared__ double red[256];
-    TileCtx c;
-    if (!tile_ctx(io, n, n_tiles, c)) return;
+    __shared__ double red[4];
+    QuadCtx c;
+    if (!quad_ctx(io, n, n_tiles, c)) return;
     const SliceIO &P = c.P;
     const LevelDesc &L = levs[P.lev0];
-    T *bdst = static_cast<T *>(L.b);
+    const int y = min(c.y, P.H - 1), nv = c.row_in ? c.nvalid : 0;
+    double v[4];
+    load4(gf, P.off_f + (long long)y * P.pitch_f + c.x, nv, v);
+    store4(static_cast<T *>(L.b), (long long)y * L.pitch + c.x, nv, v);
     double sbb = 0.0, sbs = 0.0;
-    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
-        const int y = c.ty0 + r;
-        if (y >= P.H || c.x >= P.W) continue;
-        const T v = gf[P.off_f + (long long)y * P.pitch_f + c.x];
-        bdst[(size_t)y * L.pitch + c.x] = v;
-        sbb += (double)v * (double)v;
-        sbs += (double)v;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {   // elements past nv are 0
+        sbb += v[k] * v[k];
+        sbs += v[k];
     }
     const double t = block_sum(sbb, red);
     const double t2 = block_sum(sbs, red);
@@ -339,30 +422,57 @@ hipError_t launch_prep_adjoint(bool fp64, const void *grad_f, const SliceIO *io_
     return hipGetLastError();
 }
 
+// The quad of level-0 values at row y and its four-neighbour sums: c (the
+// quad), and sum over in-slice neighbours q of (c_k - v_q).
+template <typename TL>
+__device__ __forceinline__ void quad_lap(const TL *v, long long pl, const QuadCtx &q, int nv, double c[4],
+                                         double lap[4])
+{
+    const int x = q.x, y = min(q.y, q.P.H - 1), H = q.P.H, W = q.P.W;
+    const long long p = (long long)y * pl + x;
+    double n[4], s[4];
+    load4(v, p, nv, c);
+    load4(v, p - pl, y > 0 ? nv : 0, n);
+    load4(v, p + pl, y < H - 1 ? nv : 0, s);
+    double l = row_prev(c[3]), r = row_next(c[0]);
+    const int g = threadIdx.x & 15;
+    if (nv > 0 && g == 0 && x > 0) l = (double)v[p - 1];
+    if (nv > 0 && g == 15 && x + nv < W) r = (double)v[p + nv];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double vl = k == 0 ? l : c[k - 1], vr = k == 3 ? r : c[k + 1];
+        double acc = 0.0;
+        if (x + k > 0) acc += c[k] - vl;
+        if (x + k < W - 1) acc += c[k] - vr;
+        if (y > 0) acc += c[k] - n[k];
+        if (y < H - 1) acc += c[k] - s[k];
+        lap[k] = acc;
+    }
+}
+
 // lambda = A^{-1} grad_f (level-0 iterate): grad_gs = alpha lambda,
 // grad_go = L lambda, partials of lambda . (g_s - f).
 template <typename T, typename TL>
-__device__ __forceinline__ void adjoint_tile(const TL *lam, double shift, const T *gs, const T *f,
-                                             T *ggs, T *ggo, const TileCtx &c, int pl, double &sda)
+__device__ __forceinline__ void adjoint_quad(const TL *lam, double shift, const T *gs, const T *f, T *ggs,
+                                             T *ggo, const QuadCtx &q, long long pl, double &sda)
 {
-    const SliceIO &P = c.P;
-    const int x = c.x;
-    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
-        const int y = c.ty0 + r;
-        if (y >= P.H || x >= P.W) continue;
-        const size_t p = (size_t)y * pl + x;
-        const double lraw = (double)lam[p];
-        const double l = lraw + shift;
-        double lap = 0.0;   // L is blind to the constant shift
-        if (x > 0) lap += lraw - (double)lam[p - 1];
-        if (x < P.W - 1) lap += lraw - (double)lam[p + 1];
-        if (y > 0) lap += lraw - (double)lam[p - pl];
-        if (y < P.H - 1) lap += lraw - (double)lam[p + pl];
-        const long long fo = P.off_f + (long long)y * P.pitch_f + x;
-        if (ggs) ggs[fo] = (T)(P.alpha * l);
-        if (ggo) ggo[fo] = (T)lap;
-        sda += l * ((double)gs[P.off_gs + (long long)y * P.pitch_gs + x] - (double)f[fo]);
+    const SliceIO &P = q.P;
+    const int nv = q.row_in ? q.nvalid : 0;
+    const int y = min(q.y, P.H - 1);
+    double lc[4], lap[4], g[4], fv[4], og[4], oo[4];
+    quad_lap(lam, pl, q, nv, lc, lap);   // L is blind to the constant shift
+    const long long fo = P.off_f + (long long)y * P.pitch_f + q.x;
+    load4(gs, P.off_gs + (long long)y * P.pitch_gs + q.x, nv, g);
+    load4(f, fo, nv, fv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double l = lc[k] + shift;
+        og[k] = P.alpha * l;
+        oo[k] = lap[k];
+        if (k < nv) sda += l * (g[k] - fv[k]);
     }
+    if (ggs) store4(ggs, fo, nv, og);
+    if (ggo) store4(ggo, fo, nv, oo);
 }
 
 template <typename T>
@@ -371,19 +481,19 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const T *gs, const T *f, T
                                                       const LevelDesc *levs, const SliceState *st,
                                                       double *const *u64, double *part_da)
 {
-    __shared__ double red[256];
-    TileCtx c;
-    if (!tile_ctx(io, n, n_tiles, c)) return;
+    __shared__ double red[4];
+    QuadCtx c;
+    if (!quad_ctx(io, n, n_tiles, c)) return;
     const SliceIO &P = c.P;
     const LevelDesc &L = levs[P.lev0];
     const int par = st[c.si].cycles & 1;
     double sda = 0.0;
     if (u64) {
-        adjoint_tile<T, double>(u64[par * n + c.si], 0.0, gs, f, ggs, ggo, c, L.pitch, sda);
+        adjoint_quad<T, double>(u64[par * n + c.si], 0.0, gs, f, ggs, ggo, c, L.pitch, sda);
     } else {
         const T *lam = static_cast<const T *>(L.u[par]);
         const double shift = st[c.si].shift + st[c.si].uoff;   // constant parts of lambda
-        adjoint_tile<T, T>(lam, shift, gs, f, ggs, ggo, c, L.pitch, sda);
+        adjoint_quad<T, T>(lam, shift, gs, f, ggs, ggo, c, L.pitch, sda);
     }
     const double t = block_sum(sda, red);
     if (threadIdx.x == 0) part_da[blockIdx.x] = t;
@@ -404,48 +514,76 @@ hipError_t launch_adjoint_assemble(bool fp64, const void *gs, const void *f, voi
 
 // ---------------------------------------------------- mixed refinement ---
 
+// u64_out = u64_in + e (e: the FP32 correction of the last inner solve; the
+// first step starts from zero), then the FP64 residual of u64_out stored as
+// the FP32 right-hand side of the next inner solve, and its squared norm.
 template <typename TS, typename TO>
 __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a)
 {
-    __shared__ double red[256];
-    TileCtx c;
-    if (!tile_ctx(a.io, a.n_slices, a.n_tiles, c)) return;
+    __shared__ double red[4];
+    QuadCtx c;
+    if (!quad_ctx(a.io, a.n_slices, a.n_tiles, c)) return;
     const SliceIO &P = c.P;
     double srr = 0.0;
-    if (a.active[c.si]) {
+    if (a.active[c.si]) {   // uniform per block
         const LevelDesc &L = a.levs[P.lev0];
-        const int pl = L.pitch, x = c.x, H = P.H, W = P.W;
+        const long long pl = L.pitch;
+        const int x = c.x, y = min(c.y, P.H - 1), H = P.H, W = P.W;
+        const int nv = c.row_in ? c.nvalid : 0;
         const double *uin = a.u64[a.in_sel * a.n_slices + c.si];
         double *uout = a.u64[(a.in_sel ^ 1) * a.n_slices + c.si];
         const float *e = static_cast<const float *>(L.u[a.e_sel]);
-        float *rdst = static_cast<float *>(L.b);
-        const TS *gs = static_cast<const TS *>(a.gs);
-        const TO *go = static_cast<const TO *>(a.go);
-        const bool first = a.first;
-        auto val = [&](size_t p) -> double { return first ? 0.0 : uin[p] + (double)e[p]; };
-        for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
-            const int y = c.ty0 + r;
-            if (y >= H || x >= W) continue;
-            const size_t p = (size_t)y * pl + x;
-            const double uc = val(p);
-            double acc = 0.0;
-            if (x > 0) acc += uc - val(p - 1);
-            if (x < W - 1) acc += uc - val(p + 1);
-            if (y > 0) acc += uc - val(p - pl);
-            if (y < H - 1) acc += uc - val(p + pl);
-            double bval;
-            if (a.rhs) {
-                bval = (double)static_cast<const TS *>(a.rhs)[P.off_f + (long long)y * P.pitch_f + x];
-            } else {
-                const double sv = (double)gs[P.off_gs + (long long)y * P.pitch_gs + x];
-                const double o = (double)go[P.off_go + (long long)y * P.pitch_go + x];
-                bval = P.alpha * (sv - o);
+        const long long p = (long long)y * pl + x;
+        // new iterate on the quad and its four neighbour rows / columns
+        double uc[4], un[4], us[4], t0[4], t1[4];
+        double ul = 0.0, ur = 0.0;
+        if (a.first) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) uc[k] = un[k] = us[k] = 0.0;
+        } else {
+            load4(uin, p, nv, uc);
+            load4(e, p, nv, t0);
+            load4(uin, p - pl, y > 0 ? nv : 0, un);
+            load4(e, p - pl, y > 0 ? nv : 0, t1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                uc[k] += t0[k];
+                un[k] += t1[k];
             }
-            const double res = bval - P.alpha * uc - acc;
-            uout[p] = uc;
-            rdst[p] = (float)res;
-            srr += res * res;
+            load4(uin, p + pl, y < H - 1 ? nv : 0, us);
+            load4(e, p + pl, y < H - 1 ? nv : 0, t1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) us[k] += t1[k];
         }
+        ul = row_prev(uc[3]);
+        ur = row_next(uc[0]);
+        const int g = threadIdx.x & 15;
+        if (!a.first && nv > 0 && g == 0 && x > 0) ul = uin[p - 1] + (double)e[p - 1];
+        if (!a.first && nv > 0 && g == 15 && x + nv < W) ur = uin[p + nv] + (double)e[p + nv];
+        double bv[4];
+        if (a.rhs) {
+            load4(static_cast<const TS *>(a.rhs), P.off_f + (long long)y * P.pitch_f + x, nv, bv);
+        } else {
+            double sv[4], o[4];
+            load4(static_cast<const TS *>(a.gs), P.off_gs + (long long)y * P.pitch_gs + x, nv, sv);
+            load4(static_cast<const TO *>(a.go), P.off_go + (long long)y * P.pitch_go + x, nv, o);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) bv[k] = P.alpha * (sv[k] - o[k]);
+        }
+        double res[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double vl = k == 0 ? ul : uc[k - 1], vr = k == 3 ? ur : uc[k + 1];
+            double acc = 0.0;
+            if (x + k > 0) acc += uc[k] - vl;
+            if (x + k < W - 1) acc += uc[k] - vr;
+            if (y > 0) acc += uc[k] - un[k];
+            if (y < H - 1) acc += uc[k] - us[k];
+            res[k] = bv[k] - P.alpha * uc[k] - acc;
+            if (k < nv) srr += res[k] * res[k];
+        }
+        store4(uout, p, nv, uc);
+        store4(static_cast<float *>(L.b), p, nv, res);
     }
     const double t = block_sum(srr, red);
     if (threadIdx.x == 0) a.part_rr[blockIdx.x] = t;
@@ -479,17 +617,18 @@ __global__ __launch_bounds__(256) void finalize64_kernel(const TO *go, TF *f, co
                                                          double *const *u64, const SliceState *st,
                                                          const LevelDesc *levs)
 {
-    TileCtx c;
-    if (!tile_ctx(io, n, n_tiles, c)) return;
+    QuadCtx c;
+    if (!quad_ctx(io, n, n_tiles, c)) return;
     const SliceIO &P = c.P;
     const double *u = u64[(st[c.si].cycles & 1) * n + c.si];   // latest FP64 iterate
-    const int pl = levs[P.lev0].pitch;
-    for (int r = threadIdx.x >> 6; r < kTileH; r += 4) {
-        const int y = c.ty0 + r;
-        if (y >= P.H || c.x >= P.W) continue;
-        const double o = (double)go[P.off_go + (long long)y * P.pitch_go + c.x];
-        f[P.off_f + (long long)y * P.pitch_f + c.x] = (TF)(o + u[(size_t)y * pl + c.x]);
-    }
+    const long long pl = levs[P.lev0].pitch;
+    const int y = min(c.y, P.H - 1), nv = c.row_in ? c.nvalid : 0;
+    double o[4], uv[4];
+    load4(go, P.off_go + (long long)y * P.pitch_go + c.x, nv, o);
+    load4(u, (long long)y * pl + c.x, nv, uv);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] += uv[k];
+    store4(f, P.off_f + (long long)y * P.pitch_f + c.x, nv, o);
 }
 
 hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *f,
