@@ -10,7 +10,7 @@
 //   operator is then diagonally dominant enough for a few red-black sweeps to
 //   solve it) or the grid is a single pixel.
 //   Cycle k (k >= 1): restrict down through the coarse levels (2nu sweeps,
-//   residual, restriction), 6 sweeps on the coarsest level, back up
+//   residual, restriction), 2 sweeps on the coarsest level, back up
 //   (prolongation, 2nu sweeps), then one fused pass on level 0: prolongate,
 //   nu post-sweeps of cycle k, nu pre-sweeps of cycle k + 1, residual (its
 //   norm is the convergence test), restriction.
@@ -65,7 +65,7 @@ constexpr double kStallRatio = 0.6;
 #endif
 // one launch per strip pass (unguarded and guarded items together) or two
 constexpr bool kMergedLaunch = GDF_MERGED_LAUNCH != 0;
-constexpr int kCoarsePasses = 3;   // x 2 sweeps on the coarsest level
+constexpr int kCoarsePasses = 1;   // x 2 sweeps on the coarsest level (sigma >= 2: enough)
 constexpr int kTileW = 64, kTileH = 16;
 constexpr size_t kAlign = 256;
 
@@ -390,7 +390,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.n_partd = tb;
     if (smooth_S > 0) {
         // smoothing partials: [S][tiles][4 waves]
-        const long long nparts = (long long)((W[0] + 63) / 64) * ((H[0] + 15) / 16) * 4;
+        const long long nparts = (long long)((W[0] + 63) / 64) * ((H[0] + 15) / 16) * kSmoothWaves;
         P.ranges_smooth.resize(2 * n);
         for (int s = 0; s < n; ++s) {
             P.ranges_smooth[2 * s] = (int)(s * nparts);
@@ -1301,6 +1301,9 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     for (int d = 0; d <= a.rz; ++d)
         a.wz[d] = sigma_z > 0 ? std::exp(-(double)d * d / (2 * sigma_z * sigma_z)) : 1.0;
     a.alpha = alpha;
+    for (int d = 0; d < 8; ++d) a.wxy_f[d] = (float)a.wxy[d];
+    for (int d = 0; d < 16; ++d) a.wz_f[d] = (float)a.wz[d];
+    a.alpha_f = (float)alpha;
     void *gs_used = g_smooth ? g_smooth : (mixed ? (void *)(ws + P.off_gscopy) : nullptr);
     a.gs_out = gs_used;
     a.levs = R.desc;

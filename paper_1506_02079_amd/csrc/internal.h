@@ -207,6 +207,8 @@ hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *
 
 // ---- smoothing ------------------------------------------------------------
 
+constexpr int kSmoothWaves = 8;   // waves per smoothing workgroup (one partial-sum slot each)
+
 struct SmoothArgs {
     const uint8_t *stack;
     long long pitch_row, pitch_slice;
@@ -215,6 +217,9 @@ struct SmoothArgs {
     double wxy[8];        // in-plane taps (0..rxy)
     double wz[16];        // cross-slice taps (0..rz)
     double alpha;
+    float wxy_f[8];       // the same taps rounded to FP32 (FP32 kernel: kept in scalar registers)
+    float wz_f[16];
+    float alpha_f;
     void *gs_out;         // optional smoothed stack (contiguous [S][H][W])
     const LevelDesc *levs;  // level-0 descriptor of slice z at index z * lev_stride (b written there)
     int lev_stride;

@@ -25,7 +25,9 @@ constexpr int kSTX = 64, kSTY = 16, kMaxRxy = 7;
 constexpr int kRawW = 80;                 // bytes per raw row: x in [X0 - 8, X0 + 72)
 constexpr int kRawDw = kRawW / 4;         // 20 dwords per raw row
 constexpr int kRawHMax = kSTY + 2 * kMaxRxy;
-constexpr int kPrefetch = (kRawHMax * kRawDw + 255) / 256;   // dwords per thread
+constexpr int kSThreads = 64 * kSmoothWaves;               // threads per workgroup
+constexpr int kSRows = kSTY / kSmoothWaves;                 // output rows per thread
+constexpr int kPrefetch = (kRawHMax * kRawDw + kSThreads - 1) / kSThreads;   // dwords per thread
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
@@ -51,7 +53,7 @@ __device__ __forceinline__ uint32_t load_raw_dword(const uint8_t *src, long long
 // RT: compile-time in-plane tap radius (>= the true radius; taps beyond it
 // carry zero weight), RZ: cross-slice tap radius.
 template <typename T, int RZ, int RT>
-__global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
+__global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
 {
     constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
     constexpr int NRAW = RZ + 2;       // LDS ring of raw tiles: slices zo .. zi + 1
@@ -70,22 +72,30 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
     const bool aligned = ((a.pitch_row & 3) == 0) && ((a.pitch_slice & 3) == 0) &&
                          ((reinterpret_cast<uintptr_t>(a.stack) & 3) == 0);
     const int x = X0 + tx;
-    const int yb = wv * 4;             // this thread's 4 output rows (tile-local)
+    const int yb = wv * kSRows;        // this thread's output rows (tile-local)
 
+    // taps are uniform: for FP32 they come from FP32 copies, so they stay in
+    // scalar registers (a conversion would place them in vector registers)
     T wxy[RT + 1];
 #pragma unroll
-    for (int d = 0; d <= RT; ++d) wxy[d] = d <= R ? (T)a.wxy[d] : T(0);
+    for (int d = 0; d <= RT; ++d) {
+        if constexpr (sizeof(T) == 4) wxy[d] = d <= R ? a.wxy_f[d] : 0.f;
+        else wxy[d] = d <= R ? a.wxy[d] : 0.0;
+    }
     T wz[RZ + 1];
 #pragma unroll
-    for (int d = 0; d <= RZ; ++d) wz[d] = (T)a.wz[d];
+    for (int d = 0; d <= RZ; ++d) {
+        if constexpr (sizeof(T) == 4) wz[d] = a.wz_f[d];
+        else wz[d] = a.wz[d];
+    }
 
     // in-plane renormalisation 1 / (sum_x w * sum_y w) per output pixel
     T wsx = T(0);
     for (int d = -R; d <= R; ++d)
         if (x + d >= 0 && x + d < W) wsx += wxy[d < 0 ? -d : d];
-    T inv_xy[4];
+    T inv_xy[kSRows];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < kSRows; ++i) {
         const int y = Y0 + yb + i;
         T wsy = T(0);
         for (int d = -R; d <= R; ++d)
@@ -93,20 +103,22 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
         inv_xy[i] = T(1) / (wsx * wsy);
     }
 
-    T ring[NZ][4];
+    T ring[NZ][kSRows];
 #pragma unroll
     for (int k = 0; k < NZ; ++k)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ring[k][i] = T(0);
+        for (int i = 0; i < kSRows; ++i) ring[k][i] = T(0);
 
-    const T alT = (T)a.alpha;
-    const long long nparts = (long long)a.tiles_x * a.tiles_y * 4;
+    T alT;
+    if constexpr (sizeof(T) == 4) alT = a.alpha_f;
+    else alT = a.alpha;
+    const long long nparts = (long long)a.tiles_x * a.tiles_y * kSmoothWaves;
 
     uint32_t pf[kPrefetch];   // raw tile of the next input slice, in flight
     auto issue = [&](int zi) {
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
-            const int e = tid + q * 256;
+            const int e = tid + q * kSThreads;
             pf[q] = 0u;
             if (zi < S && e < n_dw) {
                 const int r = e / kRawDw, c = e - r * kRawDw;
@@ -118,7 +130,7 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
     auto commit = [&](int slot) {
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
-            const int e = tid + q * 256;
+            const int e = tid + q * kSThreads;
             if (e < n_dw) ring_raw[slot][e] = pf[q];
         }
     };
@@ -141,7 +153,7 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
                 issue(zi + 1);       // next raw tile: its latency is hidden by this step
                 // ------------- x blur of every raw row, 4 consecutive outputs per work item
                 if (zi < S) {
-                    for (int wi = tid; wi < rawH * 16; wi += 256) {
+                    for (int wi = tid; wi < rawH * 16; wi += kSThreads) {
                         const int r = wi >> 4, seg = (wi & 15) * 4;
                         const uint32_t *rowp = &ring_raw[islot][r * kRawDw + (seg >> 2)];
                         T v[20];   // v[j] = pixel X0 + seg - 8 + j
@@ -163,11 +175,11 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
                 __syncthreads();
                 // ------------- y blur into the register ring
                 if (zi < S) {
-                    T col[4 + 2 * RT];   // col[j]: x-blurred raw row yb + RH - RT + j
+                    T col[kSRows + 2 * RT];   // col[j]: x-blurred raw row yb + RH - RT + j
 #pragma unroll
-                    for (int j = 0; j < 4 + 2 * RT; ++j) col[j] = hb[(yb + RH - RT + j) * kSTX + tx];
+                    for (int j = 0; j < kSRows + 2 * RT; ++j) col[j] = hb[(yb + RH - RT + j) * kSTX + tx];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < kSRows; ++i) {
                         T acc = wxy[0] * col[i + RT];
 #pragma unroll
                         for (int d = 1; d <= RT; ++d) acc += wxy[d] * (col[i + RT - d] + col[i + RT + d]);
@@ -175,7 +187,7 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
                     }
                 } else {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) ring[k][i] = T(0);
+                    for (int i = 0; i < kSRows; ++i) ring[k][i] = T(0);
                 }
                 // ------------- output slice zo = zi - RZ
                 const int zo = zi - RZ;
@@ -190,16 +202,16 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
                     T *bdst = static_cast<T *>(L.b);
                     T sbb = T(0), sb0 = T(0), sbs = T(0);
                     // original slice around this thread's column
-                    float oc[6], ol[4], orr[4];
+                    float oc[kSRows + 2], ol[kSRows], orr[kSRows];
 #pragma unroll
-                    for (int j = 0; j < 6; ++j) oc[j] = raw_at(oslot, yb + RH - 1 + j, tx + 8);
+                    for (int j = 0; j < kSRows + 2; ++j) oc[j] = raw_at(oslot, yb + RH - 1 + j, tx + 8);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < kSRows; ++i) {
                         ol[i] = raw_at(oslot, yb + RH + i, tx + 7);
                         orr[i] = raw_at(oslot, yb + RH + i, tx + 9);
                     }
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
+                    for (int i = 0; i < kSRows; ++i) {
                         // register slot of zo is k - RZ (mod NZ): static for each k
                         T acc = wz[0] * ring[((k - RZ) % NZ + NZ) % NZ][i];
 #pragma unroll
@@ -227,7 +239,7 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
                     const double tbb = (double)wave_sum<T>(sbb), tb0 = (double)wave_sum<T>(sb0),
                                  tbs = (double)wave_sum<T>(sbs);
                     if ((tid & 63) == 0) {
-                        const long long pi = (long long)zo * nparts + tile * 4 + wv;
+                        const long long pi = (long long)zo * nparts + tile * kSmoothWaves + wv;
                         a.part_bb[pi] = tbb;
                         a.part_b0[pi] = tb0;
                         a.part_bs[pi] = tbs;
@@ -245,7 +257,7 @@ __global__ __launch_bounds__(256) void smooth_kernel(SmoothArgs a)
 template <typename T, int RZ, int RT>
 hipError_t smooth_launch(const SmoothArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((smooth_kernel<T, RZ, RT>), dim3(a.tiles_x * a.tiles_y), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((smooth_kernel<T, RZ, RT>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s, a);
     return hipGetLastError();
 }
 
