@@ -389,8 +389,8 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.n_tiles = tb;
     P.n_partd = tb;
     if (smooth_S > 0) {
-        // smoothing partials: [S][tiles][4 waves]
-        const long long nparts = (long long)((W[0] + 63) / 64) * ((H[0] + 15) / 16) * kSmoothWaves;
+        // smoothing partials: [S][tiles]
+        const long long nparts = (long long)((W[0] + 63) / 64) * ((H[0] + 15) / 16);   // one per tile
         P.ranges_smooth.resize(2 * n);
         for (int s = 0; s < n; ++s) {
             P.ranges_smooth[2 * s] = (int)(s * nparts);
@@ -1306,8 +1306,22 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     a.alpha_f = (float)alpha;
     void *gs_used = g_smooth ? g_smooth : (mixed ? (void *)(ws + P.off_gscopy) : nullptr);
     a.gs_out = gs_used;
-    a.levs = R.desc;
-    a.lev_stride = P.g[0].nlev;   // uniform stack: descriptors are [slice][level]
+    // a uniform stack: every slice has the same arena block, so the level-0
+    // right-hand sides are equally spaced
+    a.b0 = ws + P.off_arena + P.g[0].off_b[0];
+    a.b_slice_stride = S > 1 ? (long long)((P.g[1].off_b[0] - P.g[0].off_b[0]) / P.esz) : 0;
+    for (int z = 1; z < S; ++z)
+        if ((long long)(P.g[z].off_b[0] - P.g[0].off_b[0]) != a.b_slice_stride * z * P.esz)
+            return set_err(GDF_EDEVICE, "internal: non-uniform arena layout of a stack");
+    a.b_pitch = P.g[0].pitch[0];
+    for (int lo = 0; lo <= 12; ++lo)
+        for (int hi = 0; hi <= 12; ++hi) {
+            double w = 0.0;
+            for (int d = -lo; d <= hi; ++d)
+                if (d >= -a.rz && d <= a.rz) w += a.wz[d < 0 ? -d : d];
+            a.inv_wz[lo][hi] = 1.0 / w;
+            a.inv_wz_f[lo][hi] = (float)(1.0 / w);
+        }
     a.part_bb = R.partd;
     a.part_b0 = R.partd2;
     a.part_bs = R.partd3;
@@ -1317,9 +1331,7 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
         ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0)), s, false);
         HIP_TRY(launch_smooth(P.fp64, a, s));
     }
-    if ((r = R.finish(R.r_smooth, nullptr, R.partd, FIN_BB, 0))) return r;
-    if ((r = R.finish(R.r_smooth, nullptr, R.partd2, FIN_INIT, 0))) return r;
-    if ((r = R.finish(R.r_smooth, nullptr, R.partd3, FIN_MEAN, 0))) return r;
+    HIP_TRY(launch_finish_rhs(P.n, R.r_smooth, R.partd, R.partd2, R.partd3, R.st, s));
 
     SolveIO x;
     x.gs_dtype = P.fp64 ? GDF_F64 : GDF_F32;
@@ -1564,15 +1576,12 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
     SolveIO x{gs_dtype, go_dtype, gs, go, f};
 
     auto body = [&]() -> gdf_status {
-        gdf_status q;
         {
             ProfScope ps(PC_PREP, 0.0, s, R.capturing);
             HIP_TRY(launch_prep(P.fp64, gs_dtype, gs, go_dtype, go, R.io, n, P.n_tiles, R.desc, R.partd,
                                 R.partd2, R.partd3, s));
         }
-        if ((q = R.finish(R.r_tiles, nullptr, R.partd, FIN_BB, 0))) return q;
-        if ((q = R.finish(R.r_tiles, nullptr, R.partd2, FIN_INIT, 0))) return q;
-        if ((q = R.finish(R.r_tiles, nullptr, R.partd3, FIN_MEAN, 0))) return q;
+        HIP_TRY(launch_finish_rhs(n, R.r_tiles, R.partd, R.partd2, R.partd3, R.st, s));
         return solve_body(R, x);
     };
 
@@ -1709,9 +1718,7 @@ static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, cons
         ProfScope ps(PC_PREP, 0.0, s, false);
         HIP_TRY(launch_prep_adjoint(P.fp64, grad_f, R.io, n, P.n_tiles, R.desc, R.partd, R.partd3, s));
     }
-    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_BB, 0))) return r;
-    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_INIT, 0))) return r;
-    if ((r = R.finish(R.r_tiles, nullptr, R.partd3, FIN_MEAN, 0))) return r;
+    HIP_TRY(launch_finish_rhs(n, R.r_tiles, R.partd, R.partd, R.partd3, R.st, s));
     if (P.mixed) {
         if ((r = mixed_iterate(R, dtype, nullptr, GDF_F32, nullptr, grad_f))) return r;
     } else {

@@ -130,6 +130,10 @@ hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_
                          int count_cycle, double stall_ratio, SliceState *state, int *active,
                          hipStream_t s);
 
+// FIN_BB, FIN_INIT and FIN_MEAN of one right-hand side in one launch.
+hipError_t launch_finish_rhs(int n_slices, const int *range, const double *pbb, const double *pb0,
+                             const double *pbs, SliceState *state, hipStream_t s);
+
 // After the exact residual of the output (FIN_FINAL): slices whose FP64
 // relative residual still exceeds tol, with cycles left and finite state,
 // get active = only = 1 (resume iterating, re-form f); others get 0.
@@ -221,8 +225,13 @@ struct SmoothArgs {
     float wz_f[16];
     float alpha_f;
     void *gs_out;         // optional smoothed stack (contiguous [S][H][W])
-    const LevelDesc *levs;  // level-0 descriptor of slice z at index z * lev_stride (b written there)
-    int lev_stride;
+    void *b0;                 // level-0 right-hand side of slice 0 (b_u is written there)
+    long long b_slice_stride; // elements between consecutive slices' level-0 right-hand sides
+    int b_pitch;              // its row pitch (elements)
+    // 1 / (sum of the z taps inside the stack) for an output slice with lo
+    // taps below it and hi above it inside the stack: inv_wz[lo][hi], lo, hi <= rz
+    double inv_wz[13][13];
+    float inv_wz_f[13][13];
     double *part_bb;      // [S][tiles] partial ||alpha g_s + L g_o||^2
     double *part_b0;      // [S][tiles] partial ||b_u||^2
     double *part_bs;      // [S][tiles] partial sum(b_u)

@@ -13,7 +13,7 @@
 // slice at output time, with no second read from HBM).  Blurred planes go into
 // a register ring of 2 rz + 1 planes; the z blur of an output slice is a
 // weighted sum over that ring.  The output is written straight into the
-// right-hand side of the solve, b_u = alpha (I1 - I0), together with per-wave
+// right-hand side of the solve, b_u = alpha (I1 - I0), together with per-tile
 // partial sums of ||alpha I1 + L I0||^2 (the norm of Eq. (1)'s right-hand
 // side), ||b_u||^2 and sum(b_u).  The smoothed stack is written only when asked.
 #pragma once
@@ -29,7 +29,23 @@ constexpr int kSThreads = 64 * kSmoothWaves;               // threads per workgr
 constexpr int kSRows = kSTY / kSmoothWaves;                 // output rows per thread
 constexpr int kPrefetch = (kRawHMax * kRawDw + kSThreads - 1) / kSThreads;   // dwords per thread
 
-template <typename T> __device__ __forceinline__ T wave_sum(T v)
+// Sum over the 64 lanes of a wave with DPP (pair and quad swaps, row shifts,
+// row broadcasts); the total ends in lane 63 and is returned to every lane.
+template <int CTRL, int ROW_MASK, int BANK_MASK> __device__ __forceinline__ float dpp_add(float v)
+{
+    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, false));
+}
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = dpp_add<0xB1, 0xF, 0xF>(v);    // quad_perm [1,0,3,2]
+    v = dpp_add<0x4E, 0xF, 0xF>(v);    // quad_perm [2,3,0,1]
+    v = dpp_add<0x114, 0xF, 0xE>(v);   // row_shr:4 into lanes 4..15 of each row
+    v = dpp_add<0x118, 0xF, 0xC>(v);   // row_shr:8 into lanes 8..15
+    v = dpp_add<0x142, 0xA, 0xF>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_add<0x143, 0xC, 0xF>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -56,10 +72,11 @@ template <typename T, int RZ, int RT>
 __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
 {
     constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
-    constexpr int NRAW = RZ + 2;       // LDS ring of raw tiles: slices zo .. zi + 1
+    constexpr int NRAW = RZ + 3;       // LDS ring of raw tiles: slices zo .. zi + 1
     constexpr int RH = RT > 0 ? RT : 1;   // raw halo rows (>= 1 for the Laplacian of I0)
     __shared__ uint32_t ring_raw[NRAW][kRawHMax * kRawDw];
-    __shared__ T hb[kRawHMax * kSTX];  // x-blurred rows of the current input slice
+    __shared__ T hb[2][kRawHMax * kSTX];   // x-blurred rows of the last two input slices
+    __shared__ double red_s[2][kSmoothWaves][3];   // per-wave partial sums, by output slice parity
 
     const int tid = threadIdx.x;
     const int tx = tid & 63, wv = tid >> 6;
@@ -112,7 +129,7 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     T alT;
     if constexpr (sizeof(T) == 4) alT = a.alpha_f;
     else alT = a.alpha;
-    const long long nparts = (long long)a.tiles_x * a.tiles_y * kSmoothWaves;
+    const long long nparts = (long long)a.tiles_x * a.tiles_y;   // one partial per tile
 
     uint32_t pf[kPrefetch];   // raw tile of the next input slice, in flight
     auto issue = [&](int zi) {
@@ -127,11 +144,11 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
             }
         }
     };
-    auto commit = [&](int slot) {
+    auto commit = [&](int zi) {
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
             const int e = tid + q * kSThreads;
-            if (e < n_dw) ring_raw[slot][e] = pf[q];
+            if (e < n_dw) ring_raw[zi % NRAW][e] = pf[q];
         }
     };
     // raw byte at tile-local raw row r (row 0 = Y0 - RH) and byte column c (x = X0 - 8 + c)
@@ -144,15 +161,20 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     commit(0);
     __syncthreads();
 
-    for (int zb = 0; zb < S + RZ; zb += NZ) {
+    // Step zi (software-pipelined, one barrier per step): x blur of input slice
+    // zi into hb[zi & 1]; y blur of slice zi - 1 (x-blurred in the previous
+    // step) into register ring slot (zi - 1) mod NZ; z blur and output of slice
+    // zo = zi - 1 - RZ; the raw tile of slice zi + 1 enters the LDS ring.
+    for (int zb = 0; zb < S + RZ + 1; zb += NZ) {
 #pragma unroll
         for (int k = 0; k < NZ; ++k) {
-            const int zi = zb + k;   // input slice of this step (register ring slot k)
-            if (zi < S + RZ) {       // uniform across the block
+            const int zi = zb + k;
+            if (zi < S + RZ + 1) {   // uniform across the block
                 const int islot = zi % NRAW;
                 issue(zi + 1);       // next raw tile: its latency is hidden by this step
                 // ------------- x blur of every raw row, 4 consecutive outputs per work item
                 if (zi < S) {
+                    T *hbz = hb[zi & 1];
                     for (int wi = tid; wi < rawH * 16; wi += kSThreads) {
                         const int r = wi >> 4, seg = (wi & 15) * 4;
                         const uint32_t *rowp = &ring_raw[islot][r * kRawDw + (seg >> 2)];
@@ -163,43 +185,47 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
 #pragma unroll
                             for (int i = 0; i < 4; ++i) v[4 * q + i] = (T)((w >> (8 * i)) & 0xffu);
                         }
+                        typedef T T4 __attribute__((ext_vector_type(4)));
+                        T4 out4;
 #pragma unroll
                         for (int o = 0; o < 4; ++o) {
                             T acc = wxy[0] * v[8 + o];
 #pragma unroll
                             for (int d = 1; d <= RT; ++d) acc += wxy[d] * (v[8 + o - d] + v[8 + o + d]);
-                            hb[r * kSTX + seg + o] = acc;
+                            out4[o] = acc;
                         }
+                        // one vector store per item (strided scalar stores would conflict on banks)
+                        *reinterpret_cast<T4 *>(&hbz[r * kSTX + seg]) = out4;
                     }
                 }
-                __syncthreads();
-                // ------------- y blur into the register ring
-                if (zi < S) {
+                // ------------- y blur of slice zi - 1 into the register ring
+                const int ks = (k + NZ - 1) % NZ;   // its ring slot (static once unrolled)
+                const int zy = zi - 1;
+                if (zy >= 0 && zy < S) {
+                    const T *hby = hb[zy & 1];
                     T col[kSRows + 2 * RT];   // col[j]: x-blurred raw row yb + RH - RT + j
 #pragma unroll
-                    for (int j = 0; j < kSRows + 2 * RT; ++j) col[j] = hb[(yb + RH - RT + j) * kSTX + tx];
+                    for (int j = 0; j < kSRows + 2 * RT; ++j) col[j] = hby[(yb + RH - RT + j) * kSTX + tx];
 #pragma unroll
                     for (int i = 0; i < kSRows; ++i) {
                         T acc = wxy[0] * col[i + RT];
 #pragma unroll
                         for (int d = 1; d <= RT; ++d) acc += wxy[d] * (col[i + RT - d] + col[i + RT + d]);
-                        ring[k][i] = acc * inv_xy[i];
+                        ring[ks][i] = acc * inv_xy[i];
                     }
                 } else {
 #pragma unroll
-                    for (int i = 0; i < kSRows; ++i) ring[k][i] = T(0);
+                    for (int i = 0; i < kSRows; ++i) ring[ks][i] = T(0);
                 }
-                // ------------- output slice zo = zi - RZ
-                const int zo = zi - RZ;
+                // ------------- output slice zo = zi - 1 - RZ
+                const int zo = zi - 1 - RZ;
                 if (zo >= 0) {
-                    T wsz = T(0);
-#pragma unroll
-                    for (int d = -RZ; d <= RZ; ++d)
-                        if (zo + d >= 0 && zo + d < S) wsz += wz[d < 0 ? -d : d];
-                    const T iz = T(1) / wsz;
+                    const int zlo = min(RZ, zo), zhi = min(RZ, S - 1 - zo);   // in-stack taps
+                    T iz;
+                    if constexpr (sizeof(T) == 4) iz = a.inv_wz_f[zlo][zhi];
+                    else iz = a.inv_wz[zlo][zhi];
                     const int oslot = zo % NRAW;
-                    const LevelDesc &L = a.levs[(long long)zo * a.lev_stride];
-                    T *bdst = static_cast<T *>(L.b);
+                    T *bdst = static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride;
                     T sbb = T(0), sb0 = T(0), sbs = T(0);
                     // original slice around this thread's column
                     float oc[kSRows + 2], ol[kSRows], orr[kSRows];
@@ -212,12 +238,12 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                     }
 #pragma unroll
                     for (int i = 0; i < kSRows; ++i) {
-                        // register slot of zo is k - RZ (mod NZ): static for each k
-                        T acc = wz[0] * ring[((k - RZ) % NZ + NZ) % NZ][i];
+                        // register slot of zo is k - 1 - RZ (mod NZ): static for each k
+                        T acc = wz[0] * ring[((k - 1 - RZ) % NZ + NZ) % NZ][i];
 #pragma unroll
                         for (int d = 1; d <= RZ; ++d)
-                            acc += wz[d] * (ring[((k - RZ - d) % NZ + NZ) % NZ][i] +
-                                            ring[((k - RZ + d) % NZ + NZ) % NZ][i]);
+                            acc += wz[d] * (ring[((k - 1 - RZ - d) % NZ + NZ) % NZ][i] +
+                                            ring[((k - 1 - RZ + d) % NZ + NZ) % NZ][i]);
                         const int y = Y0 + yb + i;
                         if (y < H && x < W) {
                             const T g = acc * iz;
@@ -229,24 +255,38 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                             if (y < H - 1) lap += o - oc[i + 2];
                             const T bu = alT * (g - (T)o);
                             const T bf = alT * g + (T)lap;
-                            bdst[(size_t)y * L.pitch + x] = bu;
+                            bdst[(size_t)y * a.b_pitch + x] = bu;
                             if (a.gs_out) static_cast<T *>(a.gs_out)[((long long)zo * H + y) * W + x] = g;
                             sbb += bf * bf;
                             sb0 += bu * bu;
                             sbs += bu;
                         }
                     }
-                    const double tbb = (double)wave_sum<T>(sbb), tb0 = (double)wave_sum<T>(sb0),
-                                 tbs = (double)wave_sum<T>(sbs);
+                    const double tbb = (double)wave_sum(sbb), tb0 = (double)wave_sum(sb0),
+                                 tbs = (double)wave_sum(sbs);
                     if ((tid & 63) == 0) {
-                        const long long pi = (long long)zo * nparts + tile * kSmoothWaves + wv;
-                        a.part_bb[pi] = tbb;
-                        a.part_b0[pi] = tb0;
-                        a.part_bs[pi] = tbs;
+                        red_s[zo & 1][wv][0] = tbb;
+                        red_s[zo & 1][wv][1] = tb0;
+                        red_s[zo & 1][wv][2] = tbs;
                     }
                 }
-                commit((zi + 1) % NRAW);   // no reader of that slot in this phase
+                commit(zi + 1);      // no reader of that slot in this phase
                 __syncthreads();
+                if (zo >= 0 && tid == 0) {
+                    // one partial per tile and slice: the waves' sums in a fixed order
+                    // (the next write to this buffer half comes two barriers later)
+                    double sb = 0.0, s0 = 0.0, ss = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kSmoothWaves; ++w) {
+                        sb += red_s[zo & 1][w][0];
+                        s0 += red_s[zo & 1][w][1];
+                        ss += red_s[zo & 1][w][2];
+                    }
+                    const long long pi = (long long)zo * nparts + tile;
+                    a.part_bb[pi] = sb;
+                    a.part_b0[pi] = s0;
+                    a.part_bs[pi] = ss;
+                }
             }
         }
     }

@@ -178,6 +178,38 @@ __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *ra
     }
 }
 
+// The three sums after right-hand-side formation in one launch: ||b||^2,
+// rel_init = sqrt(||b_u||^2 / ||b||^2), and the mean of b_u (bmean, uoff).
+__global__ __launch_bounds__(256) void finish_rhs_kernel(int n_slices, const int *range, const double *pbb,
+                                                         const double *pb0, const double *pbs, SliceState *st)
+{
+    __shared__ double red[4];
+    const int sidx = blockIdx.x;
+    if (sidx >= n_slices) return;
+    const int b0 = range[2 * sidx], b1 = range[2 * sidx + 1];
+    double v = 0.0, w = 0.0, x = 0.0;
+    for (int i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
+        v += pbb[i];
+        w += pb0[i];
+        x += pbs[i];
+    }
+    const double sbb = block_sum(v, red), sb0 = block_sum(w, red), sbs = block_sum(x, red);
+    if (threadIdx.x != 0) return;
+    SliceState &S = st[sidx];
+    S.bb = sbb;
+    S.rel_init = sbb > 0.0 ? sqrt(sb0 / sbb) : sqrt(sb0);
+    S.bmean = sbs / S.npx;
+    S.uoff = S.bmean / S.alpha;
+}
+
+hipError_t launch_finish_rhs(int n_slices, const int *range, const double *pbb, const double *pb0,
+                             const double *pbs, SliceState *state, hipStream_t s)
+{
+    if (n_slices <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finish_rhs_kernel, dim3(n_slices), dim3(256), 0, s, n_slices, range, pbb, pb0, pbs, state);
+    return hipGetLastError();
+}
+
 hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_f,
                          const double *partials_d, int mode, double tol, int max_cycles,
                          int count_cycle, double stall_ratio, SliceState *state, int *active,
