@@ -89,9 +89,13 @@ typedef struct {
     int tile_rows;     /* rows per strip work item (even, >= 16); 0 = tuned default */
     int inner_cycles;  /* MIXED: FP32 V-cycles per refinement step (default 3) */
     int launch_mode;   /* gdf_launch_mode for the multigrid passes (default GDF_LAUNCH_GRID) */
-    int autotune;      /* 1: pick tile_rows, nu and launch_mode by timing candidate solves
-                          of this very call (see "Autotuning" below); 0: off */
-    int reserved[7];
+    int autotune;      /* 1: pick nu, fine_sweeps, tile_rows and launch_mode by timing
+                          candidate solves of this very call (see "Autotuning" below) */
+    int fine_sweeps;   /* red-black sweeps in each fused finest-level pass (the post-sweeps
+                          of one cycle plus the pre-sweeps of the next): 2 nu .. 2 nu + 2;
+                          0 = 2 nu.  Extra sweeps lower the residual at each check and can
+                          save a whole V-cycle. */
+    int reserved[6];
 } gdf_solve_opts;
 
 typedef enum {
@@ -200,9 +204,10 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *desc_host, int dty
  * first times complete solves of its own arguments under candidate settings
  * and then runs once more with the fastest, whose outputs and report it
  * returns.  Tuned, in this order, each among the values left at 0 by the
- * caller: nu (2, 1: sweeps per smoothing step, i.e. how many red-black sweeps
- * each pass over HBM fuses), tile_rows (heuristic, 32, 64, 128, 256 rows per
- * work item) and launch_mode (grid, persistent).  The choice is cached per
+ * caller: nu (2, 1: sweeps per smoothing step), fine_sweeps (2 nu, 2 nu + 1,
+ * 2 nu + 2: how many red-black sweeps the fused finest pass applies per pass
+ * over HBM), tile_rows (heuristic, 32, 64, 128, 256 rows per work item) and
+ * launch_mode (grid, persistent).  The choice is cached per
  * batch signature (entry point, sizes, alphas, tol, precision, dtypes, fixed
  * options) until gdf_release.  The workspace size functions return the
  * largest size over the candidates when opts.autotune = 1.  Candidate runs

@@ -60,11 +60,6 @@ constexpr double kSigmaStop = 2.0;
 // An FP32 V-cycle that shrinks the residual by less than this factor (the
 // usual factor is 0.05 - 0.3) means the iterate has reached FP32's floor.
 constexpr double kStallRatio = 0.6;
-#ifndef GDF_MERGED_LAUNCH
-#define GDF_MERGED_LAUNCH 1
-#endif
-// one launch per strip pass (unguarded and guarded items together) or two
-constexpr bool kMergedLaunch = GDF_MERGED_LAUNCH != 0;
 constexpr int kCoarsePasses = 1;   // x 2 sweeps on the coarsest level (sigma >= 2: enough)
 constexpr int kTileW = 64, kTileH = 16;
 constexpr size_t kAlign = 256;
@@ -82,6 +77,7 @@ template <typename T> void key_push(std::vector<unsigned long long> &k, const T 
 
 struct Opts {
     int prec, max_vc, nu, out_dtype, use_graph, tile_rows, inner, launch, autotune;
+    int fsw;   // sweeps of the fused finest pass
 };
 
 gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
@@ -114,6 +110,9 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
     r.autotune = o->autotune;
     if (r.autotune != 0 && r.autotune != 1)
         return set_err(GDF_EINVAL, "opts.autotune must be 0 or 1 (got %d)", r.autotune);
+    r.fsw = o->fine_sweeps ? o->fine_sweeps : 2 * r.nu;
+    if (r.fsw < 2 * r.nu || r.fsw > 2 * r.nu + 2)
+        return set_err(GDF_EINVAL, "opts.fine_sweeps must be 0 or in [2 nu, 2 nu + 2] (got %d)", o->fine_sweeps);
     return GDF_OK;
 }
 
@@ -238,18 +237,33 @@ int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
     List L;
     L.kind = kind;
     L.level = level;
-    L.G = strip_halo(kind, P.o.nu);
+    L.G = strip_halo(kind, P.o.nu, P.o.fsw);
     L.VW = kStripCols - 2 * L.G;
     L.TH = choose_rows(P, slices, level, L.VW);
     L.off = (int)P.items.size();
     std::vector<Item> fast, guarded;
     int pidx = 0;
+    // Row bands: a thin band at the top and at the bottom of a slice (just
+    // deep enough for the halo: these items run the guarded code), and bands
+    // of TH rows in between, whose items are clear of the top and bottom edges.
+    // Band starts are even (the kernel's row parity and restriction pairs).
+    const int E = (L.G + 2) & ~1;   // >= G + 1
+    std::vector<std::pair<int, int>> bands;
     for (int s : slices) {
         const SliceGeom &g = P.g[s];
         const int H = g.h[level], W = g.w[level];
         L.slice_px.emplace_back(s, (double)H * W);
-        for (int y0 = 0; y0 < H; y0 += L.TH) {
-            const int y1 = std::min(y0 + L.TH, H);
+        bands.clear();
+        const int lo = E, hi = (H - E) & ~1;   // interior rows [lo, hi)
+        if (hi - lo >= L.TH) {
+            bands.emplace_back(0, lo);
+            for (int y0 = lo; y0 < hi; y0 += L.TH) bands.emplace_back(y0, std::min(y0 + L.TH, hi));
+            bands.emplace_back(hi, H);
+        } else {
+            for (int y0 = 0; y0 < H; y0 += L.TH) bands.emplace_back(y0, std::min(y0 + L.TH, H));
+        }
+        for (const auto &band : bands) {
+            const int y0 = band.first, y1 = band.second;
             const bool yin = y0 - L.G >= 1 && y1 + L.G <= H - 1;
             for (int x0 = 0; x0 < W; x0 += L.VW) {
                 const bool interior = yin && x0 - L.G >= 1 && x0 - L.G + kStripCols - 1 <= W - 2;
@@ -493,7 +507,7 @@ gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vecto
 {
     std::vector<unsigned long long> key;
     for (int v : {n, smooth_S, need_gs ? 1 : 0, o.prec, o.max_vc, o.nu, o.out_dtype, o.use_graph, o.tile_rows,
-                  o.inner, o.launch})
+                  o.inner, o.launch, o.fsw})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
         key_push(key, H[i]);
@@ -583,6 +597,27 @@ struct ProfScope {
 
 // ------------------------------------------------------------------ driver
 
+// Page-locked host buffer for the per-cycle convergence flags (a direct copy,
+// no staging through a bounce buffer), one per thread, grown as needed and
+// kept until the process ends.
+hipError_t pinned_flags(int n, int *&out)
+{
+    thread_local int *buf = nullptr;
+    thread_local int cap = 0;
+    if (cap < n) {
+        int *nb = nullptr;
+        const int want = std::max(n, 1024);
+        const hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&nb), sizeof(int) * (size_t)want,
+                                           hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        if (buf) (void)hipHostFree(buf);
+        buf = nb;
+        cap = want;
+    }
+    out = buf;
+    return hipSuccess;
+}
+
 struct Run {
     const Plan &P;
     char *ws;
@@ -648,21 +683,10 @@ struct Run {
         a.partials = partials;
         const bool timed = g_prof_on && (!g_prof_fine_only || cls == PC_FINE);
         ProfScope ps(cls, timed ? pass_bytes(li, per_px) : 0.0, s, capturing);
-        const bool pers = P.o.launch == GDF_LAUNCH_PERSISTENT;
         a.items = items + L.off;
-        if (kMergedLaunch) {
-            a.n_items = L.count;
-            a.n_fast = L.n_fast;
-            HIP_TRY(launch_strip(kind, P.o.nu, fp64, SV_MERGED, pers, a, s));
-            return GDF_OK;
-        }
-        a.n_items = L.n_fast;
+        a.n_items = L.count;
         a.n_fast = L.n_fast;
-        HIP_TRY(launch_strip(kind, P.o.nu, fp64, SV_FAST, pers, a, s));
-        a.items = items + L.off + L.n_fast;
-        a.n_items = L.count - L.n_fast;
-        a.n_fast = 0;
-        HIP_TRY(launch_strip(kind, P.o.nu, fp64, SV_GUARDED, pers, a, s));
+        HIP_TRY(launch_strip(kind, P.o.nu, P.o.fsw, fp64, P.o.launch == GDF_LAUNCH_PERSISTENT, a, s));
         return GDF_OK;
     }
 
@@ -718,8 +742,9 @@ struct Run {
 
     gdf_status read_active(bool &any)
     {
-        std::vector<int> h(P.n);
-        HIP_TRY(hipMemcpyAsync(h.data(), active, sizeof(int) * P.n, hipMemcpyDeviceToHost, s));
+        int *h = nullptr;
+        HIP_TRY(pinned_flags(P.n, h));
+        HIP_TRY(hipMemcpyAsync(h, active, sizeof(int) * P.n, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         any = false;
         for (int i = 0; i < P.n; ++i) {
@@ -966,7 +991,7 @@ gdf_status solve_body(Run &R, const SolveIO &x)
 // cached per batch signature (sizes, screening weights, tolerances, precision
 // and dtypes; not the data or the pointers) until gdf_release.
 
-struct Tuned { int nu, tile_rows, launch; };
+struct Tuned { int nu, fine_sweeps, tile_rows, launch; };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::vector<unsigned long long>, Tuned>> g_tuned;
 thread_local gdf_solve_opts g_last_tuned;
@@ -975,6 +1000,10 @@ thread_local bool g_last_tuned_ok = false;
 std::vector<int> tune_nus(const gdf_solve_opts &b)
 {
     return b.nu ? std::vector<int>{b.nu} : std::vector<int>{2, 1};
+}
+std::vector<int> tune_fine_sweeps(const gdf_solve_opts &b, int nu)
+{
+    return b.fine_sweeps ? std::vector<int>{b.fine_sweeps} : std::vector<int>{0, 2 * nu + 1, 2 * nu + 2};
 }
 std::vector<int> tune_tiles(const gdf_solve_opts &b)
 {
@@ -1008,15 +1037,17 @@ size_t tuned_workspace(const std::vector<unsigned long long> &key, const gdf_sol
     }
     size_t m = 0;
     for (int nu : tune_nus(base))
-        for (int tr : tune_tiles(base)) {
-            gdf_solve_opts c = base;
-            c.autotune = 0;
-            c.nu = nu;
-            c.tile_rows = tr;
-            const size_t b = size_of(&c);
-            if (b == 0) return 0;
-            m = std::max(m, b);
-        }
+        for (int fs : tune_fine_sweeps(base, nu))
+            for (int tr : tune_tiles(base)) {
+                gdf_solve_opts c = base;
+                c.autotune = 0;
+                c.nu = nu;
+                c.fine_sweeps = fs;
+                c.tile_rows = tr;
+                const size_t b = size_of(&c);
+                if (b == 0) return 0;
+                m = std::max(m, b);
+            }
     std::lock_guard<std::mutex> lk(g_wsz_mu);
     if (g_wsz.size() >= 64) g_wsz.erase(g_wsz.begin());
     g_wsz.emplace_back(key, m);
@@ -1028,7 +1059,7 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
 {
     gdf_solve_opts best = base;
     best.autotune = 0;
-    Tuned t{0, 0, 0};
+    Tuned t{0, 0, 0, 0};
     bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1050,6 +1081,7 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
         const std::vector<int> nus = tune_nus(base), tiles = tune_tiles(base), ls = tune_launches(base);
         gdf_solve_opts cur = best;
         cur.nu = nus[0];
+        cur.fine_sweeps = base.fine_sweeps;
         cur.tile_rows = tiles[0];
         cur.launch_mode = ls[0];
         double tcur = timeit(cur);
@@ -1062,15 +1094,17 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
             }
         };
         try_field(&gdf_solve_opts::nu, nus);
+        try_field(&gdf_solve_opts::fine_sweeps, tune_fine_sweeps(base, cur.nu));
         try_field(&gdf_solve_opts::tile_rows, tiles);
         try_field(&gdf_solve_opts::launch_mode, ls);
         if (!(tcur < inf)) return call(&best);   // no candidate ran cleanly: report the plain call
-        t = Tuned{cur.nu, cur.tile_rows, cur.launch_mode};
+        t = Tuned{cur.nu, cur.fine_sweeps, cur.tile_rows, cur.launch_mode};
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tuned.size() >= 64) g_tuned.erase(g_tuned.begin());
         g_tuned.emplace_back(key, t);
     }
     best.nu = t.nu;
+    best.fine_sweeps = t.fine_sweeps;
     best.tile_rows = t.tile_rows;
     best.launch_mode = t.launch;
     g_last_tuned = best;
@@ -1215,7 +1249,7 @@ size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
     if (b.autotune != 1) return fuse_workspace_plain(S, H, W, opts);
     std::vector<unsigned long long> key;
     key_push(key, 0);
-    for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.tile_rows,
+    for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows,
                   b.launch_mode})
         key_push(key, v);
     return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
@@ -1241,7 +1275,7 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
         return r;
     std::vector<unsigned long long> key;
     key_push(key, 0);
-    for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu,
+    for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps,
                   b.tile_rows, b.launch_mode, g_smooth ? 1 : 0})
         key_push(key, v);
     for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
@@ -1424,7 +1458,7 @@ size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_
     if (n < 1 || !d) return 0;
     std::vector<unsigned long long> key;
     key_push(key, 1);
-    for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.tile_rows,
+    for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows,
                   b.launch_mode})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
@@ -1464,6 +1498,7 @@ static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const v
     m.precision = mo.prec;
     m.max_vcycles = mo.max_vc;
     m.nu = mo.nu;
+    m.fine_sweeps = mo.fsw;
     m.out_dtype = mo.out_dtype;
     m.tile_rows = mo.tile_rows;
     m.inner_cycles = mo.inner;
@@ -1532,7 +1567,7 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
     std::vector<unsigned long long> key;
     key_push(key, 1);
     for (int v : {n, bc, gs_dtype, go_dtype, b.precision, b.max_vcycles, b.out_dtype, b.use_graph,
-                  b.inner_cycles, b.nu, b.tile_rows, b.launch_mode})
+                  b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows, b.launch_mode})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {
@@ -1605,6 +1640,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         key_push(key, o.tile_rows);
         key_push(key, o.inner);
         key_push(key, o.launch);
+        key_push(key, o.fsw);
         for (int i = 0; i < n; ++i) {
             key_push(key, d[i].H);
             key_push(key, d[i].W);
@@ -1618,7 +1654,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         }
         hipGraphExec_t ex = graph_lookup(key);
         if (!ex) {
-            if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.nu, P.fp64);
+            if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.nu, o.fsw, P.fp64);
             R.capturing = true;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             gdf_status q = body();
@@ -1669,7 +1705,7 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
     std::vector<unsigned long long> key;
     key_push(key, 2);
-    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.tile_rows, b.launch_mode})
+    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows, b.launch_mode})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {

@@ -49,7 +49,7 @@ struct StripLaunch {
     const LevelDesc *levs;
     const Item *items;
     int n_items;
-    int n_fast;              // SV_MERGED: items [0, n_fast) run the unguarded variant
+    int n_fast;              // items [0, n_fast) run the unguarded variant
     int in_sel, out_sel;     // which u buffer is read / written
     const int *cycles;       // if non-null: read buffer (cycles[slice] & 1), write the other
     int cycles_stride;       // ints between consecutive slices' counters
@@ -72,23 +72,22 @@ enum StripKind {
 
 // Halo (G) of a strip kind: stages after the load, plus one for prolongation,
 // rounded up to even.  Valid output width per strip is 128 - 2G.
-int strip_halo(StripKind k, int nu);
+int strip_halo(StripKind k, int nu, int fsw);
 
-// Kernel variants of a strip pass.  SV_FAST: every item stays clear of the
-// slice's edges (rows y0 - G .. y1 + G in [1, H - 2], columns x0 - G .. x0 - G
-// + 127 in [1, W - 2]), so the code without row guards and edge masks runs.
-// SV_GUARDED: any item.  SV_MERGED: one launch, unguarded code for the first
-// n_fast items and guarded code for the others.
-enum StripVariant { SV_GUARDED = 0, SV_FAST = 1, SV_MERGED = 2 };
-
-// Enqueue one strip pass.  fp64 selects double precision.  persistent: the
-// grid is capped at the workgroups resident on the device at once and each
-// wave loops over the list's items; otherwise one wave per item.
-hipError_t launch_strip(StripKind k, int nu, bool fp64, int variant, bool persistent, const StripLaunch &a,
+// Enqueue one strip pass (one launch).  Items [0, a.n_fast) stay clear of
+// the slice's edges (rows y0 - G .. y1 + G in [1, H - 2], columns x0 - G ..
+// x0 - G + 127 in [1, W - 2]) and run the code without row guards and edge
+// masks; the others run the guarded code.  nu: sweeps per smoothing step of
+// the coarse passes and the first pass; fsw: sweeps of the fused finest pass
+// (SK_FINE).  fp64 selects double precision.  persistent: the grid is capped
+// at the workgroups resident on the device at once and each wave loops over
+// the list's items; otherwise one wave per item.
+hipError_t launch_strip(StripKind k, int nu, int fsw, bool fp64, bool persistent, const StripLaunch &a,
                         hipStream_t s);
-// Resolves the persistent grid sizes of every strip kernel variant for nu and
-// the precision (device queries; call before a stream capture begins).
-void strip_prepare(int nu, bool fp64);
+
+// Resolves the persistent grid sizes of every strip kernel variant for nu,
+// fsw and the precision (device queries; call before a stream capture begins).
+void strip_prepare(int nu, int fsw, bool fp64);
 
 // ---- per-slice reductions and flags ------------------------------------
 

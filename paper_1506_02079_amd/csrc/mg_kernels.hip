@@ -136,7 +136,7 @@ __device__ __forceinline__ int xcd_logical_block()
 // length of the load queue for a register ring of rs rows (a divisor of rs, so
 // that queue slots are compile-time constants in the unrolled ring loop)
 #ifndef GDF_QUEUE_MAX
-#define GDF_QUEUE_MAX 6
+#define GDF_QUEUE_MAX 4
 #endif
 constexpr int queue_len(int rs)
 {
@@ -478,35 +478,47 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 
 // Each wave takes work items w, w + P, w + 2P, ... (P = waves in the grid).
 // With a grid covering the list every wave runs one item; a persistent grid
-// (capped at the waves the chip holds at once) loops over the list.
-// VAR: SV_GUARDED / SV_FAST run one variant on every item; SV_MERGED runs the
-// unguarded variant on items [0, n_fast) and the guarded one on the rest, in
-// one launch.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
+// (capped at the waves the chip holds at once) loops over the list.  Items
+// [0, n_fast) run the unguarded variant, the others the guarded one.
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
     const int stride = gridDim.x * kWavesPerBlock;
     for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
          id += stride) {
-        if (VAR == SV_FAST || (VAR == SV_MERGED && id < a.n_fast))
+        if (id < a.n_fast)
             strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, id);
         else
             strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, id);
     }
 }
 
-int strip_halo(StripKind k, int nu)
+// Half-sweeps of the fused finest pass for fsw red-black sweeps.
+template <bool PROLONG, int RMODE> static int halo_by_sweeps(int sw)
+{
+    switch (sw) {
+    case 1: return StripShape<PROLONG, 2, RMODE>::G;
+    case 2: return StripShape<PROLONG, 4, RMODE>::G;
+    case 3: return StripShape<PROLONG, 6, RMODE>::G;
+    case 4: return StripShape<PROLONG, 8, RMODE>::G;
+    case 5: return StripShape<PROLONG, 10, RMODE>::G;
+    case 6: return StripShape<PROLONG, 12, RMODE>::G;
+    default: return -1;
+    }
+}
+
+int strip_halo(StripKind k, int nu, int fsw)
 {
     switch (k) {
-    case SK_DOWN_FIRST: return nu == 1 ? StripShape<false, 2, RES_BOTH>::G : StripShape<false, 4, RES_BOTH>::G;
-    case SK_FINE: return nu == 1 ? StripShape<true, 4, RES_BOTH>::G : StripShape<true, 8, RES_BOTH>::G;
-    case SK_DOWN: return nu == 1 ? StripShape<false, 2, RES_RESTRICT>::G : StripShape<false, 4, RES_RESTRICT>::G;
-    case SK_UP: return nu == 1 ? StripShape<true, 2, RES_NONE>::G : StripShape<true, 4, RES_NONE>::G;
+    case SK_DOWN_FIRST: return halo_by_sweeps<false, RES_BOTH>(nu);
+    case SK_FINE: return halo_by_sweeps<true, RES_BOTH>(fsw);
+    case SK_DOWN: return halo_by_sweeps<false, RES_RESTRICT>(nu);
+    case SK_UP: return halo_by_sweeps<true, RES_NONE>(nu);
     case SK_COARSE_ZERO:
     case SK_COARSE: return StripShape<false, 4, RES_NONE>::G;
     case SK_SINGLE_ZERO:
     case SK_SINGLE: return StripShape<false, 4, RES_NORM>::G;
-    default: return 0;
+    default: return -1;
     }
 }
 
@@ -523,80 +535,76 @@ static int resident_blocks(const void *kernel)
 
 // Persistent grid size of one kernel instantiation, queried once (a query that
 // fails is retried on the next call).  One device type per process.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
 static int persistent_cap()
 {
     static std::atomic<int> cap{0};
     int c = cap.load(std::memory_order_relaxed);
     if (c == 0) {
-        c = resident_blocks(reinterpret_cast<const void *>(&strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, VAR>));
+        c = resident_blocks(reinterpret_cast<const void *>(&strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN>));
         if (c > 0) cap.store(c, std::memory_order_relaxed);
     }
     return c;
 }
 
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
-static hipError_t go_variant(const StripLaunch &a, bool persistent, hipStream_t s)
-{
-    const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
-    int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
-    if (persistent) {
-        const int cap = persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, VAR>();
-        if (cap >= 8 && grid > cap) grid = cap;
-    }
-    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN, VAR>), dim3(grid), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-// n_items < 0: only resolve the persistent grid sizes (no launch)
+// n_items < 0: only resolve the persistent grid size (no launch)
 template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
-static hipError_t go(const StripLaunch &a, int var, bool persistent, hipStream_t s)
+static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s)
 {
     if (a.n_items < 0) {
-        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_FAST>();
-        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_GUARDED>();
-        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_MERGED>();
+        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN>();
         return hipSuccess;
     }
     if (a.n_items == 0) return hipSuccess;
-    switch (var) {
-    case SV_FAST: return go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_FAST>(a, persistent, s);
-    case SV_MERGED: return go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_MERGED>(a, persistent, s);
-    default: return go_variant<T, PROLONG, ZERO, NHS, RMODE, GEN, SV_GUARDED>(a, persistent, s);
+    const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+    int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
+    if (persistent) {
+        const int cap = persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN>();
+        if (cap >= 8 && grid > cap) grid = cap;
     }
+    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN>), dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t launch_strip_t(StripKind k, int nu, int f, bool p, const StripLaunch &a, hipStream_t s)
+static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const StripLaunch &a, hipStream_t s)
 {
     const bool n1 = nu == 1;
     switch (k) {
-    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, f, p, s) : go<T, false, true, 4, RES_BOTH>(a, f, p, s);
-    case SK_FINE: return n1 ? go<T, true, false, 4, RES_BOTH>(a, f, p, s) : go<T, true, false, 8, RES_BOTH>(a, f, p, s);
-    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, f, p, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, f, p, s);
-    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, f, p, s) : go<T, true, false, 4, RES_NONE, true>(a, f, p, s);
-    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, f, p, s);
-    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, f, p, s);
-    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, f, p, s);
-    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, f, p, s);
+    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, p, s) : go<T, false, true, 4, RES_BOTH>(a, p, s);
+    case SK_FINE:
+        switch (fsw) {
+        case 2: return go<T, true, false, 4, RES_BOTH>(a, p, s);
+        case 3: return go<T, true, false, 6, RES_BOTH>(a, p, s);
+        case 4: return go<T, true, false, 8, RES_BOTH>(a, p, s);
+        case 5: return go<T, true, false, 10, RES_BOTH>(a, p, s);
+        case 6: return go<T, true, false, 12, RES_BOTH>(a, p, s);
+        default: return hipErrorInvalidValue;
+        }
+    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, p, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, p, s);
+    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, p, s) : go<T, true, false, 4, RES_NONE, true>(a, p, s);
+    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, p, s);
+    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, p, s);
+    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, p, s);
+    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, p, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-void strip_prepare(int nu, bool fp64)
+void strip_prepare(int nu, int fsw, bool fp64)
 {
     StripLaunch a;
     a.n_items = -1;
     for (int k = SK_DOWN_FIRST; k <= SK_SINGLE; ++k)
-        (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, SV_FAST, true, a, nullptr)
-                    : launch_strip_t<float>((StripKind)k, nu, SV_FAST, true, a, nullptr));
+        (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, fsw, true, a, nullptr)
+                    : launch_strip_t<float>((StripKind)k, nu, fsw, true, a, nullptr));
 }
 
-hipError_t launch_strip(StripKind k, int nu, bool fp64, int variant, bool persistent, const StripLaunch &a,
+hipError_t launch_strip(StripKind k, int nu, int fsw, bool fp64, bool persistent, const StripLaunch &a,
                         hipStream_t s)
 {
-    return fp64 ? launch_strip_t<double>(k, nu, variant, persistent, a, s)
-                : launch_strip_t<float>(k, nu, variant, persistent, a, s);
+    return fp64 ? launch_strip_t<double>(k, nu, fsw, persistent, a, s)
+                : launch_strip_t<float>(k, nu, fsw, persistent, a, s);
 }
 
 }  // namespace gdf

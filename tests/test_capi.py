@@ -61,6 +61,9 @@ def _fuse(**kw):
     (dict(opts=gdf.make_opts(tile_rows=7)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(out_dtype=0 + 9)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(launch_mode=3)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(nu=2, fine_sweeps=3)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(nu=2, fine_sweeps=7)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(nu=1, fine_sweeps=5)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),
     (dict(wsb=16), gdf.GDF_ENOMEM),

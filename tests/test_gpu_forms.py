@@ -204,10 +204,10 @@ def test_autotuned_uneven_batch_graph():
     t = gdf.autotune_last()
     print("tuned", t, flush=True)
     assert t["nu"] in (1, 2) and t["tile_rows"] in (0, 32, 64, 128, 256) and t["launch_mode"] in (1, 2)
+    assert t["fine_sweeps"] in (0, 2 * t["nu"] + 1, 2 * t["nu"] + 2)
     assert all(r["rel_residual"] <= 1e-6 and r["status"] == gdf.GDF_OK for r in rep1)
     # cached choice: the same settings given explicitly reproduce the result
-    f2, rep2 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, nu=t["nu"],
-                                tile_rows=t["tile_rows"], launch_mode=t["launch_mode"])
+    f2, rep2 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, **t)
     for a, b in zip(f1, f2):
         assert torch.equal(a, b)
     i = min(range(len(desc)), key=lambda k: desc[k][0] * desc[k][1])
@@ -232,3 +232,19 @@ def test_fp32_floor_slice_escalates_to_refinement():
         assert rep[0]["vcycles"] < 40
         fr = oracle.solve(s, o.astype(np.float64), a, tol=1e-12)
         assert np.abs(f[0].cpu().numpy() - fr).max() <= 1e-3
+
+
+@pytest.mark.parametrize("nu,fine_sweeps", [(2, 5), (2, 6), (1, 3), (1, 4)])
+def test_fused_pass_sweep_counts(nu, fine_sweeps):
+    # more sweeps in the fused finest pass: same solution, fewer or equal cycles
+    stack = synth.make_stack(5, 333, 270, seed=61, ramp=True)
+    st = torch.from_numpy(stack).to(DEV)
+    f0, r0 = gdf.fuse_stack(st, 0.01, tol=1e-6, nu=nu)
+    f1, r1, gsm = gdf.fuse_stack(st, 0.01, tol=1e-6, nu=nu, fine_sweeps=fine_sweeps, return_smooth=True)
+    print(nu, fine_sweeps, [r["vcycles"] for r in r0], [r["vcycles"] for r in r1], flush=True)
+    assert all(r["rel_residual"] <= 1e-6 and r["status"] == gdf.GDF_OK for r in r1)
+    assert sum(r["vcycles"] for r in r1) <= sum(r["vcycles"] for r in r0)
+    g = gsm.cpu().numpy().astype(np.float64)
+    for j in (0, 4):
+        fr = oracle.solve(g[j], stack[j].astype(np.float64), 0.01, tol=1e-11)
+        assert np.abs(f1[j].cpu().numpy() - fr).max() <= 1e-3
