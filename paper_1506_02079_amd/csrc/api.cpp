@@ -192,7 +192,8 @@ const char *kProfNames[PC_COUNT] = {"smooth", "vcycle_fine", "restrict_first", "
 struct Plan {
     Opts o;
     bool fp64;       // hierarchy element type
-    int esz;
+    int esz;         // bytes per level-0 element
+    int csz;         // bytes per coarse-level element
     int n;
     std::vector<SliceGeom> g;
     std::vector<int> desc_base;
@@ -216,6 +217,9 @@ struct Plan {
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
 
+#ifndef GDF_ROWS_PER_ITEM_DIV
+#define GDF_ROWS_PER_ITEM_DIV 6144
+#endif
 int choose_rows(const Plan &P, const std::vector<int> &slices, int level, int VW)
 {
     if (level == 0 && P.o.tile_rows) return P.o.tile_rows;
@@ -224,7 +228,7 @@ int choose_rows(const Plan &P, const std::vector<int> &slices, int level, int VW
         const SliceGeom &g = P.g[s];
         rows += (long long)g.h[level] * ((g.w[level] + VW - 1) / VW);
     }
-    long long th = rows / 6144;
+    long long th = rows / GDF_ROWS_PER_ITEM_DIV;
     th = std::max<long long>(16, std::min<long long>(512, th));
     int p = 16;
     while (p * 2 <= th) p *= 2;
@@ -301,6 +305,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.mixed = o.prec == GDF_PREC_MIXED;
     P.fp64 = o.prec == GDF_PREC_FP64;
     P.esz = P.fp64 ? 8 : 4;
+    P.csz = P.fp64 ? 8 : 2;   // coarse levels of an FP32 hierarchy are stored as bfloat16
     P.g.resize(n);
     P.desc_base.resize(n);
     int nd = 0;
@@ -319,7 +324,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     for (int s = 0; s < n; ++s) {
         SliceGeom &g = P.g[s];
         for (int l = 0; l < g.nlev; ++l) {
-            const size_t bytes = align_up((size_t)g.h[l] * g.pitch[l] * P.esz);
+            const size_t bytes = align_up((size_t)g.h[l] * g.pitch[l] * (l == 0 ? P.esz : P.csz));
             g.off_u[l][0] = off; off += bytes;
             g.off_u[l][1] = off; off += bytes;
             g.off_b[l] = off; off += bytes;
@@ -704,7 +709,7 @@ struct Run {
     // one multigrid coarse-grid correction (levels >= 1), hierarchy precision fp64
     gdf_status coarse(bool fp64)
     {
-        const double e = fp64 ? 8.0 : 4.0;
+        const double e = fp64 ? 8.0 : 2.0;   // coarse-level element bytes
         gdf_status r;
         for (int l = 1; l <= P.max_level; ++l) {
             if ((r = strip(P.list_down[l], SK_DOWN, 0, 0, nullptr, fp64, PC_COARSE, 2.25 * e))) return r;
@@ -719,10 +724,11 @@ struct Run {
 
     gdf_status first_pass(bool fp64)
     {
-        const double e = fp64 ? 8.0 : 4.0;
+        const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
         const int nF = P.list_first >= 0 ? P.lists[P.list_first].count : 0;
-        if ((r = strip(P.list_first, SK_DOWN_FIRST, 0, 0, partf, fp64, PC_FIRST, 2.25 * e))) return r;
+        // read b, write u, write the coarse right-hand side (a quarter per pixel)
+        if ((r = strip(P.list_first, SK_DOWN_FIRST, 0, 0, partf, fp64, PC_FIRST, 2 * e + 0.25 * ce))) return r;
         if ((r = strip(P.list_single, SK_SINGLE_ZERO, 0, 0, partf + nF, fp64, PC_COARSE, 2 * e))) return r;
         return GDF_OK;
     }
@@ -731,11 +737,14 @@ struct Run {
     // count (plain solve); otherwise from k (the inner solves of the mixed mode)
     gdf_status cycle(int k, bool fp64, bool slice_par = true)
     {
-        const double e = fp64 ? 8.0 : 4.0;
+        const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
         if ((r = coarse(fp64))) return r;
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
-        if ((r = strip(P.list_fine, SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE, 3.5 * e, slice_par))) return r;
+        // read u and b, write u; read the coarse correction and write the coarse
+        // right-hand side (a quarter per pixel each)
+        if ((r = strip(P.list_fine, SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE, 3 * e + 0.5 * ce, slice_par)))
+            return r;
         if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e, slice_par))) return r;
         return GDF_OK;
     }

@@ -27,6 +27,7 @@
 #include "internal.h"
 
 #include <atomic>
+#include <type_traits>
 
 namespace gdf {
 
@@ -62,9 +63,6 @@ __device__ __forceinline__ double wave_shl1(double v)
 // not stall on LDS/scalar traffic.
 #define GDF_GLOBAL __attribute__((address_space(1)))
 
-// native two-element vector (loads/stores through a global-address-space
-// pointer as one vector access)
-template <typename T> struct Vec2 { typedef T type __attribute__((ext_vector_type(2))); };
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -121,6 +119,47 @@ __device__ __forceinline__ X ld_at(const GDF_GLOBAL void *base, unsigned byte_of
     return *reinterpret_cast<const GDF_GLOBAL X *>(reinterpret_cast<const GDF_GLOBAL char *>(base) + byte_off);
 }
 
+// Storage of a level's arrays: the arithmetic type itself, or bfloat16 (raw
+// 16-bit patterns, `unsigned short`) on the coarse levels of an FP32
+// hierarchy.  Coarse levels only carry corrections, whose relative accuracy
+// (2^-8 here) stays far below the cycle's convergence factor, so the cycle
+// converges as with FP32 coarse levels while moving half the bytes there.
+// Pair: two adjacent elements as one memory access.
+template <typename S> struct Stor;
+template <> struct Stor<float> {
+    typedef float Pair __attribute__((ext_vector_type(2)));
+    __device__ static float lo(Pair p) { return p.x; }
+    __device__ static float hi(Pair p) { return p.y; }
+    __device__ static float get(float s) { return s; }
+    __device__ static float put(float v) { return v; }
+    __device__ static Pair pair(float a, float b) { Pair p; p.x = a; p.y = b; return p; }
+};
+template <> struct Stor<double> {
+    typedef double Pair __attribute__((ext_vector_type(2)));
+    __device__ static double lo(Pair p) { return p.x; }
+    __device__ static double hi(Pair p) { return p.y; }
+    __device__ static double get(double s) { return s; }
+    __device__ static double put(double v) { return v; }
+    __device__ static Pair pair(double a, double b) { Pair p; p.x = a; p.y = b; return p; }
+};
+template <> struct Stor<unsigned short> {   // bfloat16
+    typedef unsigned int Pair;
+    __device__ static float lo(Pair p) { return __uint_as_float(p << 16); }
+    __device__ static float hi(Pair p) { return __uint_as_float(p & 0xFFFF0000u); }
+    __device__ static float get(unsigned short s) { return __uint_as_float((unsigned)s << 16); }
+    // round to nearest even (infinities and NaNs stay infinities and NaNs)
+    __device__ static unsigned short put(float v)
+    {
+        const unsigned u = __float_as_uint(v);
+        return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+    __device__ static Pair pair(float a, float b) { return (unsigned)put(a) | ((unsigned)put(b) << 16); }
+};
+
+// storage of a level-0 pass (own arrays, coarse arrays) and of a coarse pass
+template <typename T> struct LevelStor { typedef T Fine; typedef T Coarse; };
+template <> struct LevelStor<float> { typedef float Fine; typedef unsigned short Coarse; };
+
 // Map hardware block ids to logical blocks so that consecutive logical blocks
 // (neighbouring strips, which share halo rows/columns) run on the same XCD and
 // hit the same L2.  Hardware dispatch places block b on XCD b % 8; the grid
@@ -162,13 +201,17 @@ template <bool PROLONG, int NHS, int RMODE> struct StripShape {
 // and no row inside the cone ever reads one (the cones are nested), so the
 // owned rows come out exactly as in the guarded variant.  Interior rows also
 // fix the vertical coefficients.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+// SO: storage of this level's arrays; SC: storage of the next coarser level's
+// (prolongation source, restriction target).  Arithmetic is in T.
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
 __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 {
     using Sh = StripShape<PROLONG, NHS, RMODE>;
     constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS, Q = Sh::Q;
     static_assert((RS & 1) == 0 && RS % Q == 0, "ring slots and queue slots must be static");
-    using V2 = typename Vec2<T>::type;
+    using PO = typename Stor<SO>::Pair;
+    using SOt = Stor<SO>;
+    using SCt = Stor<SC>;
 
     const int lane = threadIdx.x & (kWave - 1);
     const Item it = uniform_item(a.items[item_id]);
@@ -188,7 +231,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     const bool in0 = cx0 >= 0 && cx0 < W;
     const bool in1 = cx0 + 1 >= 0 && cx0 + 1 < W;
     const int cxl = min(max(cx0, 0), (W - 1) & ~1);  // clamped, even: safe vector address
-    const unsigned cxb = (unsigned)cxl * (unsigned)sizeof(T);   // byte offset of the lane's pair
+    const unsigned cxb = (unsigned)cxl * (unsigned)sizeof(SO);   // byte offset of the lane's pair
     const bool own = in0 && cx0 >= it.x0 && cx0 < it.x0 + VW;
     const T m0 = in0 ? T(1) : T(0), m1 = in1 ? T(1) : T(0);
     // neighbour-inside masks (zero for columns outside the slice)
@@ -233,7 +276,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         return RowC{T(1), T(1), T(1), gi00, gi10};
     };
 
-    const GDF_GLOBAL T *__restrict__ bsrc = (const GDF_GLOBAL T *)L.b;
+    const GDF_GLOBAL SO *__restrict__ bsrc = (const GDF_GLOBAL SO *)L.b;
     const double *bshift_p = L.bshift;
     // level 0: the slice's mean right-hand side is removed on load, so the
     // iterate is the zero-mean part of the correction (smaller values, smaller
@@ -245,27 +288,27 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         in_sel = uniform(a.cycles[(size_t)L.slice * a.cycles_stride]) & 1;
         out_sel = in_sel ^ 1;
     }
-    const GDF_GLOBAL T *__restrict__ usrc = (const GDF_GLOBAL T *)(in_sel ? L.u[1] : L.u[0]);
-    GDF_GLOBAL T *__restrict__ udst = (GDF_GLOBAL T *)(out_sel ? L.u[1] : L.u[0]);
+    const GDF_GLOBAL SO *__restrict__ usrc = (const GDF_GLOBAL SO *)(in_sel ? L.u[1] : L.u[0]);
+    GDF_GLOBAL SO *__restrict__ udst = (GDF_GLOBAL SO *)(out_sel ? L.u[1] : L.u[0]);
 
     // ---- prolongation state (coarse column lc = cx0 / 2)
     const int lc = cx0 >> 1;
     const bool cin = PROLONG && lc >= 0 && lc < Wc;
     const int lcl = PROLONG ? min(max(lc, 0), Wc - 1) : 0;
     const bool ledge = lc == 0, redge = PROLONG && lc == Wc - 1;
-    const GDF_GLOBAL T *__restrict__ ecp = (const GDF_GLOBAL T *)L.ec;
+    const GDF_GLOBAL SC *__restrict__ ecp = (const GDF_GLOBAL SC *)L.ec;
     // raw coarse value (clamped row and column: always a valid address)
     // (uniform row base + 32-bit lane offset: scalar-base addressing, no
     // per-lane 64-bit address arithmetic)
-    const unsigned lclb = (unsigned)lcl * (unsigned)sizeof(T);
-    auto ld_coarse = [ecp, lclb, Hc, pitch_c](int m) -> T {
+    const unsigned lclb = (unsigned)lcl * (unsigned)sizeof(SC);
+    auto ld_coarse = [ecp, lclb, Hc, pitch_c](int m) -> SC {   // raw storage value
         m = min(max(m, 0), Hc - 1);
-        return ld_at<T>(ecp + (size_t)m * pitch_c, lclb);
+        return ld_at<SC>(ecp + (size_t)m * pitch_c, lclb);
     };
 
     // ---- restriction state: a coarse cell's right-hand side is the sum of its
     // children's residuals (children outside the slice contribute zero)
-    GDF_GLOBAL T *__restrict__ bcp = (GDF_GLOBAL T *)L.bc;
+    GDF_GLOBAL SC *__restrict__ bcp = (GDF_GLOBAL SC *)L.bc;
     T rpair = T(0);
 
     const int y0 = it.y0, y1 = it.y1;
@@ -289,18 +332,18 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     // even) is loaded, so no load result is dead on arrival (a dead half of a
     // vector load would make the compiler wait for the load to land before
     // reusing its register).
-    V2 qb[Q], qu[Q];
-    T qus[Q];           // unguarded: the black column only
-    T qe0[Q], qe1[Q];   // coarse rows m and m -/+ 1 of the row (prolongation)
-    auto issue_row = [&](int tq, int par, V2 &vb, V2 &vu, T &vus, T &ve0, T &ve1) {
+    PO qb[Q], qu[Q];    // raw storage values
+    SO qus[Q];          // unguarded: the black column only
+    SC qe0[Q], qe1[Q];  // coarse rows m and m -/+ 1 of the row (prolongation)
+    auto issue_row = [&](int tq, int par, PO &vb, PO &vu, SO &vus, SC &ve0, SC &ve1) {
         // past the last loaded row the queue re-reads that row (cache hits);
         // outside the slice the row is clamped (the commit zeroes it)
         const int yq = ybase + min(tq, NL - 1);
         const size_t rowo = (size_t)min(max(yq, 0), H - 1) * pitch;   // uniform
-        vb = ld_at<V2>(bsrc + rowo, cxb);
+        vb = ld_at<PO>(bsrc + rowo, cxb);
         if (!ZERO) {
-            if (FAST) vus = ld_at<T>(usrc + rowo, cxb + (1 - par) * (unsigned)sizeof(T));
-            else vu = ld_at<V2>(usrc + rowo, cxb);
+            if (FAST) vus = ld_at<SO>(usrc + rowo, cxb + (1 - par) * (unsigned)sizeof(SO));
+            else vu = ld_at<PO>(usrc + rowo, cxb);
         }
         if (PROLONG) {
             const int m = yq >> 1;
@@ -330,7 +373,8 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                 if (PROLONG) {
                     // cell-centred bilinear: 3/4 of the parent row plus 1/4 of the
                     // next coarse row towards this fine row, then the same in x
-                    const T e0 = (FAST || cin) ? qe0[qs] : T(0), e1 = (FAST || cin) ? qe1[qs] : T(0);
+                    const T e0 = (FAST || cin) ? (T)SCt::get(qe0[qs]) : T(0);
+                    const T e1 = (FAST || cin) ? (T)SCt::get(qe1[qs]) : T(0);
                     const T V = T(0.75) * e0 + T(0.25) * e1;
                     T VL = wave_shr1(V), VR = wave_shl1(V);
                     if (!FAST) {
@@ -341,26 +385,26 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                     cor1 = T(0.75) * V + T(0.25) * VR;
                 }
                 if (FAST) {
-                    b[k][0] = qb[qs].x - bsh;
-                    b[k][1] = qb[qs].y - bsh;
+                    b[k][0] = (T)SOt::lo(qb[qs]) - bsh;
+                    b[k][1] = (T)SOt::hi(qb[qs]) - bsh;
                     if (!ZERO) {
                         // row parity = k parity (ybase and tb even): black column 1 - (k & 1)
                         if (k & 1) {
-                            u[k][0] = qus[qs] + cor0;
+                            u[k][0] = (T)SOt::get(qus[qs]) + cor0;
                             u[k][1] = T(0);   // red: rewritten by the first half-sweep unread
                         } else {
                             u[k][0] = T(0);
-                            u[k][1] = qus[qs] + cor1;
+                            u[k][1] = (T)SOt::get(qus[qs]) + cor1;
                         }
                     } else {
                         u[k][0] = u[k][1] = T(0);
                     }
                 } else if (y >= 0 && y < H) {
-                    b[k][0] = in0 ? qb[qs].x - bsh : T(0);
-                    b[k][1] = in1 ? qb[qs].y - bsh : T(0);
+                    b[k][0] = in0 ? (T)SOt::lo(qb[qs]) - bsh : T(0);
+                    b[k][1] = in1 ? (T)SOt::hi(qb[qs]) - bsh : T(0);
                     if (!ZERO) {
-                        u[k][0] = in0 ? qu[qs].x + cor0 : T(0);
-                        u[k][1] = in1 ? qu[qs].y + cor1 : T(0);
+                        u[k][0] = in0 ? (T)SOt::lo(qu[qs]) + cor0 : T(0);
+                        u[k][1] = in1 ? (T)SOt::hi(qu[qs]) + cor1 : T(0);
                     } else {
                         u[k][0] = u[k][1] = T(0);
                     }
@@ -404,10 +448,8 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                             }
                         }
                         if (s == NHS && y >= yo0 && y < yo1 && own) {
-                            V2 o;
-                            o.x = u[sl][0];
-                            o.y = u[sl][1];
-                            *reinterpret_cast<GDF_GLOBAL V2 *>(udst + (size_t)y * pitch + cx0) = o;
+                            *reinterpret_cast<GDF_GLOBAL PO *>(udst + (size_t)y * pitch + cx0) =
+                                SOt::pair(u[sl][0], u[sl][1]);
                         }
                     }
                 } else if (RMODE != RES_NONE) {
@@ -451,12 +493,12 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                             const T pr = r0 + rr1;      // zero for columns outside the slice
                             if ((k & 1) == 0) {         // y even: first row of a coarse cell
                                 if (y + 1 >= H) {
-                                    if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = pr;
+                                    if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = SCt::put(pr);
                                 } else {
                                     rpair = pr;
                                 }
                             } else {
-                                if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = rpair + pr;
+                                if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = SCt::put(rpair + pr);
                             }
                         }
                     }
@@ -480,16 +522,16 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 // With a grid covering the list every wave runs one item; a persistent grid
 // (capped at the waves the chip holds at once) loops over the list.  Items
 // [0, n_fast) run the unguarded variant, the others the guarded one.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
     const int stride = gridDim.x * kWavesPerBlock;
     for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
          id += stride) {
         if (id < a.n_fast)
-            strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, id);
         else
-            strip_item<T, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, id);
     }
 }
 
@@ -535,34 +577,39 @@ static int resident_blocks(const void *kernel)
 
 // Persistent grid size of one kernel instantiation, queried once (a query that
 // fails is retried on the next call).  One device type per process.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
 static int persistent_cap()
 {
     static std::atomic<int> cap{0};
     int c = cap.load(std::memory_order_relaxed);
     if (c == 0) {
-        c = resident_blocks(reinterpret_cast<const void *>(&strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN>));
+        c = resident_blocks(
+            reinterpret_cast<const void *>(&strip_kernel<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>));
         if (c > 0) cap.store(c, std::memory_order_relaxed);
     }
     return c;
 }
 
-// n_items < 0: only resolve the persistent grid size (no launch)
+// Passes on level 0 (GEN false) keep their own arrays in T and the coarse ones
+// in LevelStor<T>::Coarse; coarse-level passes (GEN true) keep everything in
+// LevelStor<T>::Coarse.  n_items < 0: only resolve the persistent grid size.
 template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
 static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s)
 {
+    typedef typename LevelStor<T>::Coarse SC;
+    typedef typename std::conditional<GEN, SC, T>::type SO;
     if (a.n_items < 0) {
-        persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN>();
+        persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>();
         return hipSuccess;
     }
     if (a.n_items == 0) return hipSuccess;
     const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
     int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
     if (persistent) {
-        const int cap = persistent_cap<T, PROLONG, ZERO, NHS, RMODE, GEN>();
+        const int cap = persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>();
         if (cap >= 8 && grid > cap) grid = cap;
     }
-    hipLaunchKernelGGL((strip_kernel<T, PROLONG, ZERO, NHS, RMODE, GEN>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((strip_kernel<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
