@@ -117,7 +117,7 @@ typedef struct {
 /* One slice of a batch (host memory).  Offsets and row pitches are in
  * elements of the buffer they index. */
 typedef struct {
-    int H, W;                   /* slice height and width, >= 1 */
+    int H, W;                   /* slice height and width, >= 1; W <= 4194304 */
     double alpha;               /* screening weight of Eq. (1), > 0 */
     long long off_gs, pitch_gs; /* g_s (smoothed slice) */
     long long off_go, pitch_go; /* g_o (original slice) */
@@ -138,7 +138,8 @@ void gdf_release(void);
 /* ------------------------------------------------------------------------ */
 /* fuse_stack: the whole method on a uint8 stack (Section III-A then Eq. (1)).
  *
- * stack_dev      uint8 [S][H][W] at element strides (pitch_slice, pitch_row).
+ * stack_dev      uint8 [S][H][W] at element strides (pitch_slice, pitch_row);
+ *                W <= 4194304.
  * alpha          screening weight, > 0 and finite.
  * bc             gdf_bc; only GDF_BC_NEUMANN runs on the GPU.
  * tol            target relative residual per slice, in (0, 1).

@@ -179,8 +179,8 @@ void build_levels(SliceGeom &g)
 struct List {
     StripKind kind;
     int level;
-    int off, count;            // all items: [off, off + count) = fast part then guarded part
-    int n_fast;
+    int off, count;            // all items: [off, off + count) = interior, column-edge, guarded
+    int n_fast, n_rows_in;
     int G, VW, TH;
     std::vector<std::pair<int, double>> slice_px;   // (slice, pixels at this level)
 };
@@ -217,22 +217,29 @@ struct Plan {
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
 
-#ifndef GDF_ROWS_PER_ITEM_DIV
-#define GDF_ROWS_PER_ITEM_DIV 6144
-#endif
-int choose_rows(const Plan &P, const std::vector<int> &slices, int level, int VW)
+// Rows per work item of a list (TH): 128, halved (down to 16) while the list
+// would have fewer than two items per wave the device holds at once.  Taller
+// items waste less on halo rows; more items keep every SIMD busy to the end of
+// the pass.  (Measured on 64 x 2048^2 stacks and on batches of uneven slices:
+// 128 rows beat 256 and taller on level 0.)
+int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripKind kind, int G, int VW)
 {
     if (level == 0 && P.o.tile_rows) return P.o.tile_rows;
-    long long rows = 0;
-    for (int s : slices) {
-        const SliceGeom &g = P.g[s];
-        rows += (long long)g.h[level] * ((g.w[level] + VW - 1) / VW);
+    int slots = strip_resident_waves(kind, P.o.nu, P.o.fsw, P.fp64);
+    if (slots <= 0) slots = 4096;
+    const int E = (G + 2) & ~1;
+    int th = 128;
+    for (; th > 16; th /= 2) {
+        double items = 0.0;
+        for (int s : slices) {
+            const int H = P.g[s].h[level], W = P.g[s].w[level];
+            const int lo = E, hi = (H - E) & ~1;
+            const int nb = hi - lo >= th ? 2 + (hi - lo + th - 1) / th : (H + th - 1) / th;
+            items += (double)((W + VW - 1) / VW) * nb;
+        }
+        if (items >= 2.0 * slots) break;
     }
-    long long th = rows / GDF_ROWS_PER_ITEM_DIV;
-    th = std::max<long long>(16, std::min<long long>(512, th));
-    int p = 16;
-    while (p * 2 <= th) p *= 2;
-    return p;
+    return th;
 }
 
 int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
@@ -243,9 +250,17 @@ int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
     L.level = level;
     L.G = strip_halo(kind, P.o.nu, P.o.fsw);
     L.VW = kStripCols - 2 * L.G;
-    L.TH = choose_rows(P, slices, level, L.VW);
+    L.TH = choose_rows(P, slices, level, kind, L.G, L.VW);
+    // the rows an item touches must span less than 2^31 bytes (the kernel
+    // addresses them with 32-bit offsets); with W <= kMaxWidth this leaves at
+    // least 16 rows per item
+    int maxp = 0;
+    for (int s : slices) maxp = std::max(maxp, P.g[s].pitch[level]);
+    const long long row_bytes = (long long)maxp * (level == 0 ? P.esz : P.csz);
+    const long long rmax = (0x7FFFFFFFLL / row_bytes - 2 * L.G - 4) & ~1LL;
+    if (L.TH > rmax) L.TH = (int)std::max<long long>(16, rmax);
     L.off = (int)P.items.size();
-    std::vector<Item> fast, guarded;
+    std::vector<Item> fast, edge, guarded;
     int pidx = 0;
     // Row bands: a thin band at the top and at the bottom of a slice (just
     // deep enough for the halo: these items run the guarded code), and bands
@@ -270,14 +285,16 @@ int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
             const int y0 = band.first, y1 = band.second;
             const bool yin = y0 - L.G >= 1 && y1 + L.G <= H - 1;
             for (int x0 = 0; x0 < W; x0 += L.VW) {
-                const bool interior = yin && x0 - L.G >= 1 && x0 - L.G + kStripCols - 1 <= W - 2;
-                (interior ? fast : guarded).push_back(Item{P.desc_base[s] + level, x0, y0, y1, pidx++});
+                const bool xin = x0 - L.G >= 1 && x0 - L.G + kStripCols - 1 <= W - 2;
+                (yin ? (xin ? fast : edge) : guarded).push_back(Item{P.desc_base[s] + level, x0, y0, y1, pidx++});
             }
         }
     }
     P.items.insert(P.items.end(), fast.begin(), fast.end());
+    P.items.insert(P.items.end(), edge.begin(), edge.end());
     P.items.insert(P.items.end(), guarded.begin(), guarded.end());
     L.n_fast = (int)fast.size();
+    L.n_rows_in = (int)(fast.size() + edge.size());
     L.count = (int)P.items.size() - L.off;
     P.lists.push_back(L);
     return (int)P.lists.size() - 1;
@@ -691,6 +708,7 @@ struct Run {
         a.items = items + L.off;
         a.n_items = L.count;
         a.n_fast = L.n_fast;
+        a.n_rows_in = L.n_rows_in;
         HIP_TRY(launch_strip(kind, P.o.nu, P.o.fsw, fp64, P.o.launch == GDF_LAUNCH_PERSISTENT, a, s));
         return GDF_OK;
     }
@@ -1220,6 +1238,7 @@ static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long 
     gdf_status r;
     if ((r = parse_opts(opts, o))) return r;
     if (S < 1 || H < 1 || W < 1) return set_err(GDF_EINVAL, "S, H, W must be >= 1 (got %d, %d, %d)", S, H, W);
+    if (W > kMaxWidth) return set_err(GDF_EINVAL, "W must be <= %d (got %d)", kMaxWidth, W);
     if (!stack || !f) return set_err(GDF_EINVAL, "stack and f must be non-null");
     if (pr < W || ps < (long long)H * pr)
         return set_err(GDF_EINVAL, "pitch_row must be >= W and pitch_slice >= H * pitch_row");
@@ -1419,6 +1438,7 @@ static gdf_status slices_validate(int n, const gdf_slice_desc *d, double tol, in
     for (int i = 0; i < n; ++i) {
         const gdf_slice_desc &s = d[i];
         if (s.H < 1 || s.W < 1) return set_err(GDF_EINVAL, "slice %d: H, W must be >= 1", i);
+        if (s.W > kMaxWidth) return set_err(GDF_EINVAL, "slice %d: W must be <= %d (got %d)", i, kMaxWidth, s.W);
         if (!(s.alpha > 0.0) || !std::isfinite(s.alpha))
             return set_err(GDF_EINVAL, "slice %d: alpha must be finite and > 0 (got %g)", i, s.alpha);
         if (s.off_gs < 0 || s.off_go < 0 || s.off_f < 0)

@@ -13,6 +13,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kStripCols = 128;    // columns covered by one wave (2 per lane)
 constexpr int kWavesPerBlock = 4;  // independent waves per workgroup
 constexpr int kMaxLevels = 16;
+constexpr int kMaxWidth = 1 << 22;  // widest slice (keeps an item's rows within 32-bit offsets)
 
 // One multigrid level of one slice.  Arrays are row-major with row pitch
 // `pitch` (elements, even, >= W + 1 for odd W) so that a lane's two-column
@@ -49,7 +50,8 @@ struct StripLaunch {
     const LevelDesc *levs;
     const Item *items;
     int n_items;
-    int n_fast;              // items [0, n_fast) run the unguarded variant
+    int n_fast;              // items [0, n_fast) run the interior variant
+    int n_rows_in;           // items [n_fast, n_rows_in) the column-edge variant, the rest the guarded one
     int in_sel, out_sel;     // which u buffer is read / written
     const int *cycles;       // if non-null: read buffer (cycles[slice] & 1), write the other
     int cycles_stride;       // ints between consecutive slices' counters
@@ -77,13 +79,18 @@ int strip_halo(StripKind k, int nu, int fsw);
 // Enqueue one strip pass (one launch).  Items [0, a.n_fast) stay clear of
 // the slice's edges (rows y0 - G .. y1 + G in [1, H - 2], columns x0 - G ..
 // x0 - G + 127 in [1, W - 2]) and run the code without row guards and edge
-// masks; the others run the guarded code.  nu: sweeps per smoothing step of
+// masks; items [a.n_fast, a.n_rows_in) have such rows but touch a column edge
+// (no row guards, per-lane masks); the others run the guarded code.  nu: sweeps per smoothing step of
 // the coarse passes and the first pass; fsw: sweeps of the fused finest pass
 // (SK_FINE).  fp64 selects double precision.  persistent: the grid is capped
 // at the workgroups resident on the device at once and each wave loops over
 // the list's items; otherwise one wave per item.
 hipError_t launch_strip(StripKind k, int nu, int fsw, bool fp64, bool persistent, const StripLaunch &a,
                         hipStream_t s);
+
+// Waves of a strip kernel variant that the device holds at once (occupancy x
+// SIMDs); 0 if the runtime cannot tell (no device).
+int strip_resident_waves(StripKind k, int nu, int fsw, bool fp64);
 
 // Resolves the persistent grid sizes of every strip kernel variant for nu,
 // fsw and the precision (device queries; call before a stream capture begins).

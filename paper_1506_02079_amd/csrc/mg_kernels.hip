@@ -58,12 +58,6 @@ __device__ __forceinline__ double wave_shl1(double v)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Descriptor fields are generic pointers; naming the global address space
-// explicitly keeps loads/stores on the global (not flat) path, whose waits do
-// not stall on LDS/scalar traffic.
-#define GDF_GLOBAL __attribute__((address_space(1)))
-
-
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Values every lane of the wave holds alike, moved into scalar registers (the
@@ -111,14 +105,6 @@ __device__ __forceinline__ LevelDesc uniform_level(const LevelDesc &d)
     return r;
 }
 
-// Load from a uniform (scalar) base plus a 32-bit per-lane byte offset, the
-// form of the scalar-base global load (no per-lane 64-bit address math).
-template <typename X>
-__device__ __forceinline__ X ld_at(const GDF_GLOBAL void *base, unsigned byte_off)
-{
-    return *reinterpret_cast<const GDF_GLOBAL X *>(reinterpret_cast<const GDF_GLOBAL char *>(base) + byte_off);
-}
-
 // Storage of a level's arrays: the arithmetic type itself, or bfloat16 (raw
 // 16-bit patterns, `unsigned short`) on the coarse levels of an FP32
 // hierarchy.  Coarse levels only carry corrections, whose relative accuracy
@@ -144,17 +130,79 @@ template <> struct Stor<double> {
 };
 template <> struct Stor<unsigned short> {   // bfloat16
     typedef unsigned int Pair;
+    typedef __bf16 BF2 __attribute__((ext_vector_type(2)));
+    typedef float F2 __attribute__((ext_vector_type(2)));
     __device__ static float lo(Pair p) { return __uint_as_float(p << 16); }
     __device__ static float hi(Pair p) { return __uint_as_float(p & 0xFFFF0000u); }
     __device__ static float get(unsigned short s) { return __uint_as_float((unsigned)s << 16); }
-    // round to nearest even (infinities and NaNs stay infinities and NaNs)
-    __device__ static unsigned short put(float v)
+    // round to nearest even (the hardware conversion)
+    __device__ static unsigned short put(float v) { return __builtin_bit_cast(unsigned short, (__bf16)v); }
+    __device__ static Pair pair(float a, float b)
     {
-        const unsigned u = __float_as_uint(v);
-        return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        F2 f;
+        f.x = a;
+        f.y = b;
+        return __builtin_bit_cast(Pair, __builtin_convertvector(f, BF2));
     }
-    __device__ static Pair pair(float a, float b) { return (unsigned)put(a) | ((unsigned)put(b) << 16); }
 };
+
+// ------------------------------------------------------- buffer access ---
+
+// Raw buffer resource over `bytes` bytes from `base` (no stride or swizzle;
+// dword 3 selects plain dword access on this GPU family).  The address of an
+// access is base + row offset (a scalar) + lane offset; a lane offset at or
+// past `bytes` reads zero and drops a store.  So a lane is masked by its
+// offset and a whole row by a zero-sized resource, without a branch.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+// a lane offset past every window (the host keeps an item's rows below 2^31 bytes)
+constexpr unsigned kNoLane = 0x80000000u;
+
+template <typename X> struct Buf;
+template <> struct Buf<unsigned short> {
+    __device__ static unsigned short ld(Rsrc r, unsigned vo, unsigned so)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0);
+    }
+    __device__ static void st(unsigned short v, Rsrc r, unsigned vo, unsigned so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)vo, (int)so, 0);
+    }
+};
+template <> struct Buf<unsigned> {
+    __device__ static unsigned ld(Rsrc r, unsigned vo, unsigned so)
+    {
+        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
+    }
+    __device__ static void st(unsigned v, Rsrc r, unsigned vo, unsigned so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)vo, (int)so, 0);
+    }
+};
+template <> struct Buf<float> {
+    __device__ static float ld(Rsrc r, unsigned vo, unsigned so) { return __uint_as_float(Buf<unsigned>::ld(r, vo, so)); }
+    __device__ static void st(float v, Rsrc r, unsigned vo, unsigned so) { Buf<unsigned>::st(__float_as_uint(v), r, vo, so); }
+};
+typedef unsigned U2 __attribute__((ext_vector_type(2)));
+typedef unsigned U4 __attribute__((ext_vector_type(4)));
+template <typename X, typename R> struct BufBits {   // 8- and 16-byte values
+    __device__ static X ld(Rsrc r, unsigned vo, unsigned so)
+    {
+        if constexpr (sizeof(X) == 8) return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+        else return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
+    }
+    __device__ static void st(X v, Rsrc r, unsigned vo, unsigned so)
+    {
+        if constexpr (sizeof(X) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, v), r, (int)vo, (int)so, 0);
+        else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(R, v), r, (int)vo, (int)so, 0);
+    }
+};
+template <> struct Buf<double> : BufBits<double, U2> {};
+template <> struct Buf<Stor<float>::Pair> : BufBits<Stor<float>::Pair, U2> {};
+template <> struct Buf<Stor<double>::Pair> : BufBits<Stor<double>::Pair, U4> {};
 
 // storage of a level-0 pass (own arrays, coarse arrays) and of a coarse pass
 template <typename T> struct LevelStor { typedef T Fine; typedef T Coarse; };
@@ -188,30 +236,42 @@ template <bool PROLONG, int NHS, int RMODE> struct StripShape {
     static constexpr int NS = NHS + (RMODE != RES_NONE ? 1 : 0);  // stages after the load
     static constexpr int G = (NS + (PROLONG ? 1 : 0) + 1) & ~1;   // halo, even
     static constexpr int VW = kStripCols - 2 * G;                  // owned columns
-    static constexpr int RS = 2 * NS + 2;                          // register ring rows
+    // register ring rows: at least 2 NS + 2, rounded up so that a full-depth
+    // load queue divides it
+    static constexpr int RS = (2 * NS + 2 + GDF_QUEUE_MAX - 1) / GDF_QUEUE_MAX * GDF_QUEUE_MAX;
     // loads run Q - 1 rows ahead of the row entering the ring, so each wave keeps
     // several rows of HBM reads in flight
     static constexpr int Q = queue_len(RS);
 };
 
-// FAST: the item's rows y0 - G .. y1 + G all lie in [1, H - 2] and its columns
-// x0 - G .. x0 - G + 127 in [1, W - 2] (no slice edge inside).  Then every
-// stage runs on every step with no row guards: a row outside a stage's cone of
-// validity ([y0 - G + s, y1 + G - s) at stage s) gets a finite throwaway value,
-// and no row inside the cone ever reads one (the cones are nested), so the
-// owned rows come out exactly as in the guarded variant.  Interior rows also
-// fix the vertical coefficients.
+// Variants.  VAR 1 (interior): the item's rows y0 - G .. y1 + G all lie in
+// [1, H - 2] and its columns x0 - G .. x0 - G + 127 in [1, W - 2].  VAR 2
+// (column edge): the rows do, but some columns touch or leave the slice.  VAR 0
+// (guarded): anything else (the top and bottom bands of a slice).
+// With interior rows every stage runs on every step with no row guards: a row
+// outside a stage's cone of validity ([y0 - G + s, y1 + G - s) at stage s) gets
+// a finite throwaway value, and no row inside the cone ever reads one (the
+// cones are nested), so the owned rows come out exactly as in the guarded
+// variant.  Inside the cones every row is an interior row (unit vertical
+// couplings) on every level; the b ring holds b times the inverse diagonal, so
+// an update is one fused multiply-add on the neighbour sum.  With interior
+// columns as well (VAR 1) the stencil is the same for every lane (unit
+// couplings, diagonal sigma + 4); at column edges it is per lane (masks and,
+// on coarse levels, the narrower last column).
 // SO: storage of this level's arrays; SC: storage of the next coarser level's
 // (prolongation source, restriction target).  Arithmetic is in T.
-template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool FAST>
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
 __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 {
+    constexpr bool RIN = VAR != 0;   // rows interior: no row guards
+    constexpr bool CIN = VAR == 1;   // columns interior as well: one stencil for all lanes
     using Sh = StripShape<PROLONG, NHS, RMODE>;
     constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS, Q = Sh::Q;
     static_assert((RS & 1) == 0 && RS % Q == 0, "ring slots and queue slots must be static");
     using PO = typename Stor<SO>::Pair;
     using SOt = Stor<SO>;
     using SCt = Stor<SC>;
+    constexpr unsigned ES = sizeof(SO), CS = sizeof(SC);
 
     const int lane = threadIdx.x & (kWave - 1);
     const Item it = uniform_item(a.items[item_id]);
@@ -225,15 +285,19 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     const int H = L.H, W = L.W, pitch = L.pitch;
     const int Hc = L.Hc, Wc = L.Wc, pitch_c = L.pitch_c;
     const T sig = (T)L.sigma;
+    const int y0 = it.y0, y1 = it.y1;
+    const int ybase = y0 - G, yend = y1 + G;
+    const int NL = yend - ybase;
+    const int yo0 = max(y0, 0), yo1 = min(y1, H);   // owned rows inside the slice
 
     // ---- per-lane column geometry
     const int cx0 = it.x0 - G + 2 * lane;   // even; this lane holds columns cx0, cx0 + 1
     const bool in0 = cx0 >= 0 && cx0 < W;
     const bool in1 = cx0 + 1 >= 0 && cx0 + 1 < W;
     const int cxl = min(max(cx0, 0), (W - 1) & ~1);  // clamped, even: safe vector address
-    const unsigned cxb = (unsigned)cxl * (unsigned)sizeof(SO);   // byte offset of the lane's pair
+    const unsigned cxb = (unsigned)cxl * ES;          // byte offset of the lane's pair
     const bool own = in0 && cx0 >= it.x0 && cx0 < it.x0 + VW;
-    const T m0 = in0 ? T(1) : T(0), m1 = in1 ? T(1) : T(0);
+    const unsigned vo_own = own ? (unsigned)cx0 * ES : kNoLane;   // the lane's stores
     // neighbour-inside masks (zero for columns outside the slice)
     const T ml0 = (in0 && cx0 - 1 >= 0) ? T(1) : T(0);
     const T mr0 = (in0 && cx0 + 1 < W) ? T(1) : T(0);
@@ -246,6 +310,8 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         inv0[d] = in0 ? T(1) / (sig + ml0 + mr0 + T(d)) : T(0);
         inv1[d] = in1 ? T(1) / (sig + ml1 + mr1 + T(d)) : T(0);
     }
+    // unit interior stencil (unguarded items): diagonal and its inverse
+    const T dg = sig + T(4), ivs = T(1) / dg;
     // ---- finite-volume coefficients of a coarse level (GEN)
     // columns: relative width wx (only the last column may be narrower); the
     // coupling across a column face is 2 / (wx_left + wx_right) per unit row height
@@ -276,45 +342,69 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         return RowC{T(1), T(1), T(1), gi00, gi10};
     };
 
-    const GDF_GLOBAL SO *__restrict__ bsrc = (const GDF_GLOBAL SO *)L.b;
-    const double *bshift_p = L.bshift;
+    // interior rows, per column j of the lane: inverse diagonal g, its
+    // diagonal d, and on coarse levels the couplings scaled by g (left, right,
+    // vertical); unit and uniform with interior columns
+    const T g0 = CIN ? ivs : (GEN ? gi00 : inv0[2]), g1 = CIN ? ivs : (GEN ? gi10 : inv1[2]);
+    const T d0 = CIN ? dg : (GEN ? sig * wx0 + kl0 + kr0 + T(2) * wx0 : sig + ml0 + mr0 + T(2));
+    const T d1 = CIN ? dg : (GEN ? sig * wx1 + kl1 + kr1 + T(2) * wx1 : sig + ml1 + mr1 + T(2));
+    const T al0 = gi00 * kl0, ar0 = gi00 * kr0, av0 = gi00 * wx0;
+    const T al1 = gi10 * kl1, ar1 = gi10 * kr1, av1 = gi10 * wx1;
+
     // level 0: the slice's mean right-hand side is removed on load, so the
     // iterate is the zero-mean part of the correction (smaller values, smaller
     // FP32 rounding); the mean is added back when f is formed
-    const T bsh = bshift_p ? (T)uniform_d(*bshift_p) : T(0);
+    const T bsh = L.bshift ? (T)uniform_d(*L.bshift) : T(0);
+    const T bshg0 = bsh * g0, bshg1 = bsh * g1;
     // (selects, not a runtime index into the descriptor's array: that would spill it)
     int in_sel = a.in_sel, out_sel = a.out_sel;
     if (a.cycles) {   // per-slice parity: the latest iterate sits in buffer cycles & 1
         in_sel = uniform(a.cycles[(size_t)L.slice * a.cycles_stride]) & 1;
         out_sel = in_sel ^ 1;
     }
-    const GDF_GLOBAL SO *__restrict__ usrc = (const GDF_GLOBAL SO *)(in_sel ? L.u[1] : L.u[0]);
-    GDF_GLOBAL SO *__restrict__ udst = (GDF_GLOBAL SO *)(out_sel ? L.u[1] : L.u[0]);
+
+    // ---- the item's windows: rows [wlo, whi] of this level and [cwlo, cwhi] of
+    // the coarser one hold every access (clamped rows included), so row offsets
+    // within them are 32-bit scalars
+    const int wlo = max(ybase, 0), whi = min(yend - 1, H - 1);
+    const unsigned rowB = (unsigned)pitch * ES;
+    const unsigned winB = (unsigned)(whi - wlo + 1) * rowB;
+    const size_t wofs = (size_t)wlo * pitch;
+    const Rsrc rb = make_rsrc((const SO *)L.b + wofs, winB);
+    const Rsrc ru = make_rsrc((const SO *)(in_sel ? L.u[1] : L.u[0]) + wofs, winB);
+    const Rsrc rw = make_rsrc((SO *)(out_sel ? L.u[1] : L.u[0]) + wofs, winB);
+    const Rsrc rnone = make_rsrc(L.b, 0u);   // drops every store
+    // (row offsets go through readfirstlane: a value the compiler happens to
+    // compute in vector registers would otherwise get a per-lane loop around
+    // each access that takes it)
+    auto row_off = [=](int y) -> unsigned {   // y clamped into the slice
+        return (unsigned)uniform((RIN ? y - wlo : min(max(y, 0), H - 1) - wlo) * (int)rowB);
+    };
+    auto win_off = [=](int y) -> unsigned {   // y clamped into the window
+        return (unsigned)uniform((min(max(y, wlo), whi) - wlo) * (int)rowB);
+    };
+    const int cwlo = max((wlo >> 1) - 1, 0), cwhi = min((whi >> 1) + 1, Hc - 1);
+    const unsigned crowB = (unsigned)pitch_c * CS;
+    const unsigned cwinB = (unsigned)max(cwhi - cwlo + 1, 0) * crowB;
+    const size_t cofs = (size_t)max(cwlo, 0) * pitch_c;
+    auto crow_off = [=](int m) -> unsigned {   // m clamped into the coarse slice
+        return (unsigned)uniform((min(max(m, 0), Hc - 1) - cwlo) * (int)crowB);
+    };
 
     // ---- prolongation state (coarse column lc = cx0 / 2)
     const int lc = cx0 >> 1;
     const bool cin = PROLONG && lc >= 0 && lc < Wc;
     const int lcl = PROLONG ? min(max(lc, 0), Wc - 1) : 0;
     const bool ledge = lc == 0, redge = PROLONG && lc == Wc - 1;
-    const GDF_GLOBAL SC *__restrict__ ecp = (const GDF_GLOBAL SC *)L.ec;
-    // raw coarse value (clamped row and column: always a valid address)
-    // (uniform row base + 32-bit lane offset: scalar-base addressing, no
-    // per-lane 64-bit address arithmetic)
-    const unsigned lclb = (unsigned)lcl * (unsigned)sizeof(SC);
-    auto ld_coarse = [ecp, lclb, Hc, pitch_c](int m) -> SC {   // raw storage value
-        m = min(max(m, 0), Hc - 1);
-        return ld_at<SC>(ecp + (size_t)m * pitch_c, lclb);
-    };
+    const unsigned lclb = (CIN || cin) ? (unsigned)lcl * CS : kNoLane;   // outside: reads zero
+    const Rsrc re = PROLONG ? make_rsrc((const SC *)L.ec + cofs, cwinB) : rnone;
 
     // ---- restriction state: a coarse cell's right-hand side is the sum of its
     // children's residuals (children outside the slice contribute zero)
-    GDF_GLOBAL SC *__restrict__ bcp = (GDF_GLOBAL SC *)L.bc;
+    const Rsrc rc = (RMODE & RES_RESTRICT) ? make_rsrc((SC *)L.bc + cofs, cwinB) : rnone;
+    const unsigned vo_rc = own ? (unsigned)lc * CS : kNoLane;
     T rpair = T(0);
-
-    const int y0 = it.y0, y1 = it.y1;
-    const int ybase = y0 - G, yend = y1 + G;
-    const int NL = yend - ybase;
-    const int yo0 = max(y0, 0), yo1 = min(y1, H);   // owned rows inside the slice
+    const float ownw = own ? 1.f : 0.f;
 
     T u[RS][2], b[RS][2];
 #pragma unroll
@@ -339,20 +429,24 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         // past the last loaded row the queue re-reads that row (cache hits);
         // outside the slice the row is clamped (the commit zeroes it)
         const int yq = ybase + min(tq, NL - 1);
-        const size_t rowo = (size_t)min(max(yq, 0), H - 1) * pitch;   // uniform
-        vb = ld_at<PO>(bsrc + rowo, cxb);
+        const unsigned so = row_off(yq);
+        vb = Buf<PO>::ld(rb, cxb, so);
         if (!ZERO) {
-            if (FAST) vus = ld_at<SO>(usrc + rowo, cxb + (1 - par) * (unsigned)sizeof(SO));
-            else vu = ld_at<PO>(usrc + rowo, cxb);
+            if (RIN) vus = Buf<SO>::ld(ru, par ? cxb : cxb + ES, so);
+            else vu = Buf<PO>::ld(ru, cxb, so);
         }
         if (PROLONG) {
             const int m = yq >> 1;
-            ve0 = ld_coarse(m);
-            ve1 = ld_coarse((yq & 1) ? m + 1 : m - 1);
+            ve0 = Buf<SC>::ld(re, lclb, crow_off(m));
+            ve1 = Buf<SC>::ld(re, lclb, crow_off((yq & 1) ? m + 1 : m - 1));
         }
     };
 #pragma unroll
     for (int q = 0; q < Q - 1; ++q) issue_row(q, q & 1, qb[q], qu[q], qus[q], qe0[q], qe1[q]);
+    // Wait for the first rows here, once per item: with loads still in flight
+    // on entry, the wait at the head of the ring loop (which merges the entry
+    // with the loop's own back edge) would become a full drain on every trip.
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
 
     const int T_end = NL + 2 * NS;
     for (int tb = 0; tb < T_end; tb += RS) {
@@ -373,43 +467,49 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                 if (PROLONG) {
                     // cell-centred bilinear: 3/4 of the parent row plus 1/4 of the
                     // next coarse row towards this fine row, then the same in x
-                    const T e0 = (FAST || cin) ? (T)SCt::get(qe0[qs]) : T(0);
-                    const T e1 = (FAST || cin) ? (T)SCt::get(qe1[qs]) : T(0);
+                    // (lanes whose coarse column lies outside read zero)
+                    const T e0 = (T)SCt::get(qe0[qs]);
+                    const T e1 = (T)SCt::get(qe1[qs]);
                     const T V = T(0.75) * e0 + T(0.25) * e1;
                     T VL = wave_shr1(V), VR = wave_shl1(V);
-                    if (!FAST) {
+                    if (!CIN) {
                         VL = ledge ? V : VL;
                         VR = redge ? V : VR;
                     }
                     cor0 = T(0.75) * V + T(0.25) * VL;
                     cor1 = T(0.75) * V + T(0.25) * VR;
                 }
-                if (FAST) {
-                    b[k][0] = (T)SOt::lo(qb[qs]) - bsh;
-                    b[k][1] = (T)SOt::hi(qb[qs]) - bsh;
+                if (RIN) {
+                    b[k][0] = fma((T)SOt::lo(qb[qs]), g0, -bshg0);
+                    b[k][1] = fma((T)SOt::hi(qb[qs]), g1, -bshg1);
+                    // a column outside the slice (its g is zero) may hold any bits
+                    if (!CIN) {
+                        b[k][0] = in0 ? b[k][0] : T(0);
+                        b[k][1] = in1 ? b[k][1] : T(0);
+                    }
                     if (!ZERO) {
                         // row parity = k parity (ybase and tb even): black column 1 - (k & 1)
                         if (k & 1) {
-                            u[k][0] = (T)SOt::get(qus[qs]) + cor0;
+                            const T v = (T)SOt::get(qus[qs]) + cor0;
+                            u[k][0] = (CIN || in0) ? v : T(0);
                             u[k][1] = T(0);   // red: rewritten by the first half-sweep unread
                         } else {
+                            const T v = (T)SOt::get(qus[qs]) + cor1;
                             u[k][0] = T(0);
-                            u[k][1] = (T)SOt::get(qus[qs]) + cor1;
+                            u[k][1] = (CIN || in1) ? v : T(0);
                         }
                     } else {
                         u[k][0] = u[k][1] = T(0);
                     }
-                } else if (y >= 0 && y < H) {
-                    b[k][0] = in0 ? (T)SOt::lo(qb[qs]) - bsh : T(0);
-                    b[k][1] = in1 ? (T)SOt::hi(qb[qs]) - bsh : T(0);
-                    if (!ZERO) {
-                        u[k][0] = in0 ? (T)SOt::lo(qu[qs]) + cor0 : T(0);
-                        u[k][1] = in1 ? (T)SOt::hi(qu[qs]) + cor1 : T(0);
-                    } else {
-                        u[k][0] = u[k][1] = T(0);
-                    }
                 } else {
-                    u[k][0] = u[k][1] = b[k][0] = b[k][1] = T(0);
+                    // zero outside the slice (selects, not a branch: a branch here
+                    // splits the ring into per-path copies that wait for every load)
+                    const bool rin = y >= 0 && y < H;   // uniform
+                    const bool v0 = rin && in0, v1 = rin && in1;
+                    b[k][0] = v0 ? (T)SOt::lo(qb[qs]) - bsh : T(0);
+                    b[k][1] = v1 ? (T)SOt::hi(qb[qs]) - bsh : T(0);
+                    u[k][0] = (!ZERO && v0) ? (T)SOt::lo(qu[qs]) + cor0 : T(0);
+                    u[k][1] = (!ZERO && v1) ? (T)SOt::hi(qu[qs]) + cor1 : T(0);
                 }
             }
             // ------------------------------------------------ stages 1..NS
@@ -419,48 +519,99 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                 const int su = (sl + RS - 1) % RS;   // row y-1
                 const int sd = (sl + 1) % RS;        // row y+1
                 const int y = ybase + t - 2 * s;
+                const bool owned_row = y >= yo0 && y < yo1;   // uniform
                 if (s <= NHS) {
-                    const int lo = max(ybase + s, 0), hi = min(yend - s, H);
-                    if (FAST || (y >= lo && y < hi)) {
-                        const int c = (s - 1) & 1;         // 0: red, 1: black
-                        const int j = (k & 1) ^ c;         // column of that colour (y parity = k parity)
-                        if (!GEN) {
-                            const int dy = FAST ? 2 : (y > 0) + (y < H - 1);
+                    const int c = (s - 1) & 1;         // 0: red, 1: black
+                    const int j = (k & 1) ^ c;         // column of that colour (y parity = k parity)
+                    if (RIN) {
+                        // b ring scaled by the inverse diagonal g; neighbours outside
+                        // the slice hold zero
+                        if (!GEN || CIN) {   // unit couplings
                             if (j == 0) {
-                                const T iv = dy == 2 ? inv0[2] : (dy == 1 ? inv0[1] : inv0[0]);
                                 const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
-                                u[sl][0] = (b[sl][0] + nb) * iv;
+                                u[sl][0] = fma(nb, g0, b[sl][0]);
                             } else {
-                                const T iv = dy == 2 ? inv1[2] : (dy == 1 ? inv1[1] : inv1[0]);
-                                const T nb = u[sl][0] + wave_shl1(u[sl][0]) + u[su][1] + u[sd][1];
-                                u[sl][1] = (b[sl][1] + nb) * iv;
+                                const T nb = wave_shl1(u[sl][0]) + u[sl][0] + u[su][1] + u[sd][1];
+                                u[sl][1] = fma(nb, g1, b[sl][1]);
                             }
-                        } else {
-                            const RowC rc = FAST ? RowC{T(1), T(1), T(1), gi00, gi10} : row_coef(y);
+                        } else {             // coarse level at a column edge: per-lane couplings
                             if (j == 0) {
-                                const T h = fma(kl0, wave_shr1(u[sl][1]), kr0 * u[sl][1]);
-                                const T v = fma(rc.ku, u[su][0], rc.kd * u[sd][0]);
-                                u[sl][0] = (b[sl][0] + fma(rc.wy, h, wx0 * v)) * rc.i0;
+                                const T v = fma(av0, u[su][0] + u[sd][0], b[sl][0]);
+                                u[sl][0] = fma(al0, wave_shr1(u[sl][1]), fma(ar0, u[sl][1], v));
                             } else {
-                                const T h = fma(kl1, u[sl][0], kr1 * wave_shl1(u[sl][0]));
-                                const T v = fma(rc.ku, u[su][1], rc.kd * u[sd][1]);
-                                u[sl][1] = (b[sl][1] + fma(rc.wy, h, wx1 * v)) * rc.i1;
+                                const T v = fma(av1, u[su][1] + u[sd][1], b[sl][1]);
+                                u[sl][1] = fma(ar1, wave_shl1(u[sl][0]), fma(al1, u[sl][0], v));
                             }
                         }
-                        if (s == NHS && y >= yo0 && y < yo1 && own) {
-                            *reinterpret_cast<GDF_GLOBAL PO *>(udst + (size_t)y * pitch + cx0) =
-                                SOt::pair(u[sl][0], u[sl][1]);
+                        if (s == NHS)
+                            Buf<PO>::st(SOt::pair(u[sl][0], u[sl][1]), owned_row ? rw : rnone, vo_own, win_off(y));
+                    } else {
+                        const int lo = max(ybase + s, 0), hi = min(yend - s, H);
+                        if (y >= lo && y < hi) {
+                            if (!GEN) {
+                                const int dy = (y > 0) + (y < H - 1);
+                                if (j == 0) {
+                                    const T iv = dy == 2 ? inv0[2] : (dy == 1 ? inv0[1] : inv0[0]);
+                                    const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
+                                    u[sl][0] = (b[sl][0] + nb) * iv;
+                                } else {
+                                    const T iv = dy == 2 ? inv1[2] : (dy == 1 ? inv1[1] : inv1[0]);
+                                    const T nb = wave_shl1(u[sl][0]) + u[sl][0] + u[su][1] + u[sd][1];
+                                    u[sl][1] = (b[sl][1] + nb) * iv;
+                                }
+                            } else {
+                                const RowC rc = row_coef(y);
+                                if (j == 0) {
+                                    const T h = fma(kl0, wave_shr1(u[sl][1]), kr0 * u[sl][1]);
+                                    const T v = fma(rc.ku, u[su][0], rc.kd * u[sd][0]);
+                                    u[sl][0] = (b[sl][0] + fma(rc.wy, h, wx0 * v)) * rc.i0;
+                                } else {
+                                    const T h = fma(kl1, u[sl][0], kr1 * wave_shl1(u[sl][0]));
+                                    const T v = fma(rc.ku, u[su][1], rc.kd * u[sd][1]);
+                                    u[sl][1] = (b[sl][1] + fma(rc.wy, h, wx1 * v)) * rc.i1;
+                                }
+                            }
+                            if (s == NHS && owned_row)
+                                Buf<PO>::st(SOt::pair(u[sl][0], u[sl][1]), rw, vo_own, win_off(y));
                         }
                     }
                 } else if (RMODE != RES_NONE) {
-                    if (y >= yo0 && y < yo1) {
-                        const T uc0 = u[sl][0], uc1 = u[sl][1];
+                    // r = b - sigma u - sum_q k_q (u - u_q): neighbour differences are
+                    // (nearly) exact, so the residual stays accurate in FP32
+                    const T uc0 = u[sl][0], uc1 = u[sl][1];
+                    T r0 = T(0), rr1 = T(0);
+                    if (CIN) {
+                        // every row, owned or not (masked below): no branch
+                        const T dd = uc0 - uc1;
+                        T acc0 = (uc0 - wave_shr1(uc1)) + dd;
+                        T acc1 = (uc1 - wave_shl1(uc0)) - dd;
+                        acc0 += uc0 - u[su][0];
+                        acc1 += uc1 - u[su][1];
+                        acc0 += uc0 - u[sd][0];
+                        acc1 += uc1 - u[sd][1];
+                        // b = (sigma + 4) x the ring's scaled value, exact inside the fma
+                        r0 = fma(dg, b[sl][0], -fma(sig, uc0, acc0));
+                        rr1 = fma(dg, b[sl][1], -fma(sig, uc1, acc1));
+                    } else if (RIN) {
+                        // column edge: masked couplings (kl, kr are zero across the
+                        // slice edge; wx is 1 but for a narrower last coarse column)
+                        const T dd = uc0 - uc1;
+                        const T h0 = fma(kr0, dd, kl0 * (uc0 - wave_shr1(uc1)));
+                        const T h1 = fma(kl1, -dd, kr1 * (uc1 - wave_shl1(uc0)));
+                        const T v0 = (uc0 - u[su][0]) + (uc0 - u[sd][0]);
+                        const T v1 = (uc1 - u[su][1]) + (uc1 - u[sd][1]);
+                        const T sw0 = GEN ? sig * wx0 : sig, sw1 = GEN ? sig * wx1 : sig;
+                        const T acc0 = GEN ? fma(wx0, v0, h0) : v0 + h0;
+                        const T acc1 = GEN ? fma(wx1, v1, h1) : v1 + h1;
+                        // b = d x the ring's scaled value, exact inside the fma
+                        r0 = fma(d0, b[sl][0], -fma(sw0, uc0, acc0));
+                        rr1 = fma(d1, b[sl][1], -fma(sw1, uc1, acc1));
+                        r0 = in0 ? r0 : T(0);
+                        rr1 = in1 ? rr1 : T(0);
+                    } else if (owned_row) {
                         const T l0 = wave_shr1(uc1), r1 = wave_shl1(uc0);
-                        // r = b - sigma u - sum_q k_q (u - u_q): neighbour differences are
-                        // (nearly) exact, so the residual stays accurate in FP32
-                        T r0, rr1;
                         if (!GEN) {
-                            const T mu = (FAST || y > 0) ? T(1) : T(0), md = (FAST || y < H - 1) ? T(1) : T(0);
+                            const T mu = y > 0 ? T(1) : T(0), md = y < H - 1 ? T(1) : T(0);
                             T acc0 = ml0 * (uc0 - l0);
                             acc0 = fma(mr0, uc0 - uc1, acc0);
                             acc0 = fma(mu, uc0 - u[su][0], acc0);
@@ -472,7 +623,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                             r0 = fma(-sig, uc0, b[sl][0]) - acc0;
                             rr1 = fma(-sig, uc1, b[sl][1]) - acc1;
                         } else {
-                            const RowC rc = FAST ? RowC{T(1), T(1), T(1), gi00, gi10} : row_coef(y);
+                            const RowC rc = row_coef(y);
                             const T wy = rc.wy, ku = rc.ku, kd = rc.kd;
                             const T h0 = fma(kl0, uc0 - l0, kr0 * (uc0 - uc1));
                             const T v0 = fma(ku, uc0 - u[su][0], kd * (uc0 - u[sd][0]));
@@ -481,24 +632,25 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                             r0 = fma(-sig * wx0 * wy, uc0, b[sl][0]) - fma(wy, h0, wx0 * v0);
                             rr1 = fma(-sig * wx1 * wy, uc1, b[sl][1]) - fma(wy, h1, wx1 * v1);
                         }
+                    }
+                    if (RIN || owned_row) {
                         if (RMODE & RES_NORM) {
-                            if (own) {
-                                const float f0 = (float)r0, f1 = (float)rr1;
-                                nacc = fmaf(f0, f0, nacc);
-                                nacc = fmaf(f1, f1, nacc);
-                                sacc += f0 + f1;   // zero for columns outside the slice
-                            }
+                            // owned lanes of owned rows (zero for columns outside the slice)
+                            const float w = owned_row ? ownw : 0.f;
+                            const float f0 = (float)r0, f1 = (float)rr1;
+                            nacc = fmaf(w, fmaf(f0, f0, f1 * f1), nacc);
+                            sacc = fmaf(w, f0 + f1, sacc);
                         }
                         if (RMODE & RES_RESTRICT) {
                             const T pr = r0 + rr1;      // zero for columns outside the slice
                             if ((k & 1) == 0) {         // y even: first row of a coarse cell
-                                if (y + 1 >= H) {
-                                    if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = SCt::put(pr);
-                                } else {
+                                if (!RIN && y + 1 >= H)
+                                    Buf<SC>::st(SCt::put(pr), rc, vo_rc, crow_off(y >> 1));
+                                else
                                     rpair = pr;
-                                }
-                            } else {
-                                if (own) bcp[(size_t)(y >> 1) * pitch_c + lc] = SCt::put(rpair + pr);
+                            } else {                    // owned rows come in pairs (y0, y1 even)
+                                Buf<SC>::st(SCt::put(rpair + pr), owned_row ? rc : rnone, vo_rc,
+                                            crow_off(min(max(y, wlo), whi) >> 1));
                             }
                         }
                     }
@@ -521,7 +673,8 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 // Each wave takes work items w, w + P, w + 2P, ... (P = waves in the grid).
 // With a grid covering the list every wave runs one item; a persistent grid
 // (capped at the waves the chip holds at once) loops over the list.  Items
-// [0, n_fast) run the unguarded variant, the others the guarded one.
+// [0, n_fast) run the interior variant, [n_fast, n_rows_in) the column-edge
+// one and the rest the guarded one.
 template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
@@ -529,9 +682,11 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
     for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
          id += stride) {
         if (id < a.n_fast)
-            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, true>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 1>(a, id);
+        else if (id < a.n_rows_in)
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 2>(a, id);
         else
-            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, false>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 0>(a, id);
     }
 }
 
@@ -592,12 +747,17 @@ static int persistent_cap()
 
 // Passes on level 0 (GEN false) keep their own arrays in T and the coarse ones
 // in LevelStor<T>::Coarse; coarse-level passes (GEN true) keep everything in
-// LevelStor<T>::Coarse.  n_items < 0: only resolve the persistent grid size.
+// LevelStor<T>::Coarse.  waves non-null: only store the waves resident at once
+// (0 if unknown); n_items < 0: only resolve the persistent grid size.
 template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
-static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s)
+static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s, int *waves)
 {
     typedef typename LevelStor<T>::Coarse SC;
     typedef typename std::conditional<GEN, SC, T>::type SO;
+    if (waves) {
+        *waves = persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>() * kWavesPerBlock;
+        return hipSuccess;
+    }
     if (a.n_items < 0) {
         persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>();
         return hipSuccess;
@@ -614,28 +774,43 @@ static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s)
 }
 
 template <typename T>
-static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const StripLaunch &a, hipStream_t s)
+static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const StripLaunch &a, hipStream_t s,
+                                 int *w = nullptr)
 {
     const bool n1 = nu == 1;
     switch (k) {
-    case SK_DOWN_FIRST: return n1 ? go<T, false, true, 2, RES_BOTH>(a, p, s) : go<T, false, true, 4, RES_BOTH>(a, p, s);
+    case SK_DOWN_FIRST:
+        return n1 ? go<T, false, true, 2, RES_BOTH>(a, p, s, w) : go<T, false, true, 4, RES_BOTH>(a, p, s, w);
     case SK_FINE:
         switch (fsw) {
-        case 2: return go<T, true, false, 4, RES_BOTH>(a, p, s);
-        case 3: return go<T, true, false, 6, RES_BOTH>(a, p, s);
-        case 4: return go<T, true, false, 8, RES_BOTH>(a, p, s);
-        case 5: return go<T, true, false, 10, RES_BOTH>(a, p, s);
-        case 6: return go<T, true, false, 12, RES_BOTH>(a, p, s);
+        case 2: return go<T, true, false, 4, RES_BOTH>(a, p, s, w);
+        case 3: return go<T, true, false, 6, RES_BOTH>(a, p, s, w);
+        case 4: return go<T, true, false, 8, RES_BOTH>(a, p, s, w);
+        case 5: return go<T, true, false, 10, RES_BOTH>(a, p, s, w);
+        case 6: return go<T, true, false, 12, RES_BOTH>(a, p, s, w);
         default: return hipErrorInvalidValue;
         }
-    case SK_DOWN: return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, p, s) : go<T, false, true, 4, RES_RESTRICT, true>(a, p, s);
-    case SK_UP: return n1 ? go<T, true, false, 2, RES_NONE, true>(a, p, s) : go<T, true, false, 4, RES_NONE, true>(a, p, s);
-    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, p, s);
-    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, p, s);
-    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, p, s);
-    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, p, s);
+    case SK_DOWN:
+        return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, p, s, w)
+                  : go<T, false, true, 4, RES_RESTRICT, true>(a, p, s, w);
+    case SK_UP:
+        return n1 ? go<T, true, false, 2, RES_NONE, true>(a, p, s, w) : go<T, true, false, 4, RES_NONE, true>(a, p, s, w);
+    case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, p, s, w);
+    case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, p, s, w);
+    case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, p, s, w);
+    case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, p, s, w);
     default: return hipErrorInvalidValue;
     }
+}
+
+int strip_resident_waves(StripKind k, int nu, int fsw, bool fp64)
+{
+    StripLaunch a;
+    a.n_items = -1;
+    int w = 0;
+    const hipError_t e = fp64 ? launch_strip_t<double>(k, nu, fsw, true, a, nullptr, &w)
+                              : launch_strip_t<float>(k, nu, fsw, true, a, nullptr, &w);
+    return e == hipSuccess ? w : 0;
 }
 
 void strip_prepare(int nu, int fsw, bool fp64)
