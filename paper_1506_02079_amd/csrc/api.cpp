@@ -203,16 +203,17 @@ struct Plan {
     int list_first = -1, list_fine = -1, list_single = -1;
     int list_down[kMaxLevels], list_up[kMaxLevels], list_coarse[kMaxLevels];
     int max_level = 0;
-    std::vector<int> ranges_first, ranges_cycle, ranges_tiles, ranges_smooth;
+    std::vector<int> ranges_first, ranges_cycle, ranges_tiles, ranges_ftiles, ranges_smooth;
     int n_norm;
     std::vector<SliceIO> io;
     long long n_tiles = 0;
+    long long n_ftiles = 0;    // blocks of the row-marching output pass
     long long n_partd = 0;
     bool mixed = false;
     bool need_gs_copy = false;   // fuse_stack MIXED without g_smooth output
     // layout (bytes from the workspace base)
     size_t off_tables, tables_bytes;
-    size_t off_state, off_active, off_only, off_desc, off_items, off_r_first, off_r_cycle, off_r_tiles,
+    size_t off_state, off_active, off_only, off_desc, off_items, off_r_first, off_r_cycle, off_r_tiles, off_r_ftiles,
         off_r_smooth, off_io, off_u64tab;
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
@@ -407,7 +408,8 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     // tiles for the per-pixel kernels
     P.io.resize(n);
     P.ranges_tiles.resize(2 * n);
-    long long tb = 0;
+    P.ranges_ftiles.resize(2 * n);
+    long long tb = 0, fb = 0;
     for (int s = 0; s < n; ++s) {
         SliceIO &io = P.io[s];
         std::memset(&io, 0, sizeof io);
@@ -421,8 +423,14 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
         P.ranges_tiles[2 * s] = (int)tb;
         tb += nt;
         P.ranges_tiles[2 * s + 1] = (int)tb;
+        io.ftiles_x = (W[s] + kFinCols - 1) / kFinCols;
+        io.ftile_begin = fb;
+        P.ranges_ftiles[2 * s] = (int)fb;
+        fb += (long long)io.ftiles_x * ((H[s] + kFinRows - 1) / kFinRows);
+        P.ranges_ftiles[2 * s + 1] = (int)fb;
     }
     P.n_tiles = tb;
+    P.n_ftiles = fb;
     P.n_partd = tb;
     if (smooth_S > 0) {
         // smoothing partials: [S][tiles]
@@ -448,6 +456,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.off_r_first = take(sizeof(int) * 2 * n);
     P.off_r_cycle = take(sizeof(int) * 2 * n);
     P.off_r_tiles = take(sizeof(int) * 2 * n);
+    P.off_r_ftiles = take(sizeof(int) * 2 * n);
     P.off_r_smooth = take(sizeof(int) * 2 * n);
     P.off_io = take(sizeof(SliceIO) * n);
     P.off_u64tab = take(sizeof(double *) * 2 * n);
@@ -501,6 +510,7 @@ std::vector<char> bind_tables(const Plan &P, char *ws, const std::vector<SliceIO
     std::memcpy(img.data() + P.off_r_first, P.ranges_first.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_cycle, P.ranges_cycle.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_tiles, P.ranges_tiles.data(), sizeof(int) * 2 * P.n);
+    std::memcpy(img.data() + P.off_r_ftiles, P.ranges_ftiles.data(), sizeof(int) * 2 * P.n);
     if (!P.ranges_smooth.empty())
         std::memcpy(img.data() + P.off_r_smooth, P.ranges_smooth.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_io, io.data(), sizeof(SliceIO) * P.n);
@@ -650,7 +660,7 @@ struct Run {
     int *only;      // slices to re-finalize after a resume
     LevelDesc *desc;
     Item *items;
-    int *r_first, *r_cycle, *r_tiles, *r_smooth;
+    int *r_first, *r_cycle, *r_tiles, *r_ftiles, *r_smooth;
     SliceIO *io;
     double **u64tab;
     float2 *partf;
@@ -670,6 +680,7 @@ struct Run {
         r_first = reinterpret_cast<int *>(ws + P.off_r_first);
         r_cycle = reinterpret_cast<int *>(ws + P.off_r_cycle);
         r_tiles = reinterpret_cast<int *>(ws + P.off_r_tiles);
+        r_ftiles = reinterpret_cast<int *>(ws + P.off_r_ftiles);
         r_smooth = reinterpret_cast<int *>(ws + P.off_r_smooth);
         io = reinterpret_cast<SliceIO *>(ws + P.off_io);
         u64tab = reinterpret_cast<double **>(ws + P.off_u64tab);
@@ -903,7 +914,17 @@ struct SolveIO {
     int gs_dtype, go_dtype;
     const void *gs, *go;
     void *f;
+    bool rows_ok;   // widths and g_o / f offsets fit the row-marching output pass
 };
+
+// Every width a multiple of 4 and every g_o / f row start on a four-element
+// boundary (the row-marching output pass moves four elements per lane).
+static bool fin_rows_ok(const std::vector<SliceIO> &io)
+{
+    for (const SliceIO &v : io)
+        if ((v.W & 3) || (v.off_go & 3) || (v.pitch_go & 3) || (v.off_f & 3) || (v.pitch_f & 3)) return false;
+    return true;
+}
 
 // FP64 iterative refinement around FP32 V-cycles.  The FP64 iterate u64 starts
 // at zero; each step solves A e = r (r the FP64 residual, stored as FP32 in the
@@ -973,6 +994,10 @@ gdf_status solve_body(Run &R, const SolveIO &x)
     const double f_b = P.o.out_dtype == GDF_F64 ? 8.0 : 4.0;
     double all_px = 0.0;
     for (int i = 0; i < P.n; ++i) all_px += (double)P.g[i].H * P.g[i].W;
+    // the row-marching output pass reads g_o and writes f four elements at a time
+    const size_t go_e = x.go_dtype == GDF_U8 ? 1 : (x.go_dtype == GDF_F32 ? 4 : 8);
+    const bool rows = x.rows_ok && (reinterpret_cast<uintptr_t>(x.go) % (4 * go_e)) == 0 &&
+                      (reinterpret_cast<uintptr_t>(x.f) % (size_t)(4 * f_b)) == 0;
     if (!P.mixed) {
         // rounds after the first resume slices whose exact residual missed tol
         // (decided on the host, or on the device inside a captured graph, which
@@ -982,10 +1007,11 @@ gdf_status solve_body(Run &R, const SolveIO &x)
             {
                 // (later rounds touch only the resumed slices: not counted)
                 ProfScope ps(PC_FINALIZE, round ? 0.0 : all_px * (2.0 * P.esz + go_b + f_b), R.s, R.capturing);
-                HIP_TRY(launch_finalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n, P.n_tiles,
-                                        R.desc, R.st, round ? R.only : nullptr, R.partd, R.s));
+                HIP_TRY(launch_finalize(P.fp64, rows, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n,
+                                        rows ? P.n_ftiles : P.n_tiles, R.desc, R.st, round ? R.only : nullptr,
+                                        R.partd, R.s));
             }
-            if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_FINAL, 0))) return r;
+            if ((r = R.finish(rows ? R.r_ftiles : R.r_tiles, nullptr, R.partd, FIN_FINAL, 0))) return r;
             if (R.capturing) {
                 if (round == 2) break;
                 HIP_TRY(launch_resume_flags(P.n, R.st, R.tol, R.max_cycles, R.active, R.only, R.s));
@@ -1401,6 +1427,7 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     x.go_dtype = GDF_U8;
     x.go = stack;
     x.f = f;
+    x.rows_ok = fin_rows_ok(io);
     if ((r = solve_body(R, x))) return r;
     std::vector<SliceState> h;
     const gdf_status st = collect(P, ws, s, report, tol, mixed ? o.inner : 1, &h);
@@ -1632,12 +1659,13 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
     char *ws = static_cast<char *>(workspace);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if ((r = upload_tables(P, ws, slice_io(P, d), s))) return r;
+    const std::vector<SliceIO> io = slice_io(P, d);
+    if ((r = upload_tables(P, ws, io, s))) return r;
     Run R(P, ws, s);
     R.tol = tol;
     R.max_cycles = o.max_vc;
     R.stall_ratio = o.prec == GDF_PREC_FP32 ? kStallRatio : 0.0;
-    SolveIO x{gs_dtype, go_dtype, gs, go, f};
+    SolveIO x{gs_dtype, go_dtype, gs, go, f, fin_rows_ok(io)};
 
     auto body = [&]() -> gdf_status {
         {

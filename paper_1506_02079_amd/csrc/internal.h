@@ -13,7 +13,21 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kStripCols = 128;    // columns covered by one wave (2 per lane)
 constexpr int kWavesPerBlock = 4;  // independent waves per workgroup
 constexpr int kMaxLevels = 16;
-constexpr int kMaxWidth = 1 << 22;  // widest slice (keeps an item's rows within 32-bit offsets)
+constexpr int kMaxWidth = 1 << 22;
+
+#ifdef __HIPCC__
+// Logical tile of this workgroup in a 1-D grid of nb workgroups.  The hardware
+// hands workgroup b to XCD b % 8; remapping gives each XCD a contiguous range of
+// tiles, so tiles that share halo rows and columns run on the same XCD at about
+// the same time and meet in its L2.  A tail of fewer than 8 groups keeps its
+// order.
+__device__ __forceinline__ long long xcd_tile(long long b, long long nb)
+{
+    const long long nb8 = nb >> 3;
+    if (b >= nb8 * 8) return b;
+    return (b & 7) * nb8 + (b >> 3);
+}
+#endif  // widest slice (keeps an item's rows within 32-bit offsets)
 
 // One multigrid level of one slice.  Arrays are row-major with row pitch
 // `pitch` (elements, even, >= W + 1 for odd W) so that a lane's two-column
@@ -157,6 +171,9 @@ struct SliceIO {        // per-slice user-buffer view (element offsets/pitches)
     int lev0;           // LevelDesc index of the slice's finest level
     int tiles_x;        // 64-wide tiles per row (for the simple 2D kernels)
     long long tile_begin;  // first tile index of this slice
+    int ftiles_x;       // blocks per row of the row-marching output pass
+    int pad_;
+    long long ftile_begin;  // first such block of this slice
 };
 
 // b_u = alpha (g_s - g_o) into level 0 b, and FP64 partials of
@@ -169,7 +186,11 @@ hipError_t launch_prep(bool fp64, int gs_dtype, const void *gs, int go_dtype, co
 // f = g_o + u (out dtype), FP64 partials of ||b_u - A u||^2 per tile.  The
 // level-0 iterate of slice s is buffer (state[s].cycles & 1).
 // With `only` non-null, tiles of slices with only[s] == 0 are skipped.
-hipError_t launch_finalize(bool fp64, int go_dtype, const void *go, int out_dtype, void *f,
+// rows: the row-marching kernel over blocks of kFinCols x kFinRows (n_tiles
+// of those; every width a multiple of 4 and the g_o and f rows aligned to four
+// elements), else the quad kernel over 64 x 16 tiles.
+constexpr int kFinCols = 256, kFinRows = 64;
+hipError_t launch_finalize(bool fp64, bool rows, int go_dtype, const void *go, int out_dtype, void *f,
                            const SliceIO *io_dev, int n_slices, long long n_tiles,
                            const LevelDesc *levs, const SliceState *state, const int *only,
                            double *part_rr, hipStream_t s);

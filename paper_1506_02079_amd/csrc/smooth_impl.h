@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
 
     const int tid = threadIdx.x;
     const int tx = tid & 63, wv = tid >> 6;
-    const int tile = blockIdx.x;
+    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD
     const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
     const int X0 = tile_x * kSTX, Y0 = tile_y * kSTY;
     const int S = a.S, H = a.H, W = a.W, R = a.rxy;

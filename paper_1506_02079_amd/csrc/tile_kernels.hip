@@ -99,6 +99,7 @@ __device__ __forceinline__ double row_next(double v)
 }
 
 struct QuadCtx {
+    long long tile;         // logical tile index (also the slot of its partial sums)
     int si, x, y, nvalid;   // nvalid: pixels of the quad inside the row (<= 0: none)
     bool row_in;
     SliceIO P;
@@ -106,7 +107,8 @@ struct QuadCtx {
 
 __device__ __forceinline__ bool quad_ctx(const SliceIO *io, int n, long long n_tiles, QuadCtx &c)
 {
-    const long long tile = blockIdx.x;
+    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+    c.tile = tile;
     if (tile >= n_tiles) return false;
     c.si = find_slice(io, n, tile);
     c.P = io[c.si];
@@ -291,9 +293,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const TS *gs, const TO *go, c
     const double tb0 = block_sum(sb0, red);
     const double tbs = block_sum(sbs, red);
     if (threadIdx.x == 0) {
-        part_bb[blockIdx.x] = tbb;
-        part_b0[blockIdx.x] = tb0;
-        part_bs[blockIdx.x] = tbs;
+        part_bb[c.tile] = tbb;
+        part_b0[c.tile] = tb0;
+        part_bs[c.tile] = tbs;
     }
 }
 
@@ -331,7 +333,7 @@ hipError_t launch_prep(bool fp64, int gs_dtype, const void *gs, int go_dtype, co
 // unrounded g_o + u (A(g_o + u) - (alpha g_s + L g_o) = A u - b_u).  Quad
 // mapping: one tile row of four-pixel vectors per thread.
 template <typename T, typename TO, typename TF>
-__global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, const SliceIO *io,
+__global__ __launch_bounds__(256) void finalize_quad_kernel(const TO *go, TF *f, const SliceIO *io,
                                                        int n_slices, long long n_tiles,
                                                        const LevelDesc *levs,
                                                        const SliceState *st, const int *only,
@@ -378,36 +380,202 @@ __global__ __launch_bounds__(256) void finalize_kernel(const TO *go, TF *f, cons
     }
     store4(f, P.off_f + (long long)y * P.pitch_f + x, nv, fo);
     const double t = block_sum(srr, red);
-    if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
+    if (threadIdx.x == 0) part_rr[c.tile] = t;
+}
+
+// Row-marching output pass (the common case: widths are multiples of four
+// and the g_o and f rows start on four-element boundaries).  One wave owns a block of kFinCols columns (four
+// per lane) by kFinRows rows and walks down it holding the iterate's rows
+// y - 1, y, y + 1, so every row is read once; the loads of the next rows are
+// in flight kFinQ - 1 rows ahead.  The wave's two outer horizontal neighbours
+// come from one extra element per row; the others cross lanes by DPP.
+constexpr int kFinQ = 4;   // rows of loads in flight
+
+__device__ __forceinline__ int find_fslice(const SliceIO *io, int n, long long t)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (io[mid].ftile_begin <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// lane i receives lane i - 1's / i + 1's value (0 at the wave's ends)
+__device__ __forceinline__ double wave_prev(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_next(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename V> __device__ __forceinline__ void v4_to_d(const V &q, double v[4])
+{
+    v[0] = (double)q.x;
+    v[1] = (double)q.y;
+    v[2] = (double)q.z;
+    v[3] = (double)q.w;
+}
+
+#define GDF_GLOBAL __attribute__((address_space(1)))
+
+template <typename T, typename TO, typename TF>
+__global__ __launch_bounds__(64) void finalize_kernel(const TO *go_, TF *f_, const SliceIO *io, int n_slices,
+                                                      long long n_ft, const LevelDesc *levs,
+                                                      const SliceState *st, const int *only, double *part_rr)
+{
+    using VT = typename Vec4<T>::type;
+    using VO = typename Vec4<TO>::type;
+    using VF = typename Vec4<TF>::type;
+    constexpr int Q = kFinQ;
+    const long long ft = xcd_tile(blockIdx.x, gridDim.x);
+    if (ft >= n_ft) return;
+    const int si = find_fslice(io, n_slices, ft);
+    if (only && !only[si]) return;   // uniform per wave: keeps this slice's partial sum
+    // the slice's fields as wave-uniform scalars (stores to f cannot alias them)
+    const int H = __builtin_amdgcn_readfirstlane(io[si].H), W = __builtin_amdgcn_readfirstlane(io[si].W);
+    const int ftx = __builtin_amdgcn_readfirstlane(io[si].ftiles_x);
+    const long long lt = ft - io[si].ftile_begin;
+    const long long off_go = io[si].off_go, pitch_go = io[si].pitch_go;
+    const long long off_f = io[si].off_f, pitch_f = io[si].pitch_f;
+    const double sg = io[si].alpha;
+    const LevelDesc &L = levs[io[si].lev0];
+    const long long pu = L.pitch;
+    const GDF_GLOBAL T *u = (const GDF_GLOBAL T *)L.u[st[si].cycles & 1];
+    const GDF_GLOBAL T *bu = (const GDF_GLOBAL T *)L.b;
+    const GDF_GLOBAL TO *go = (const GDF_GLOBAL TO *)go_;
+    GDF_GLOBAL TF *f = (GDF_GLOBAL TF *)f_;
+    // full correction = uoff (mean removed on load) + u + shift (constant-mode
+    // correction); constants cancel in L, and b is used as stored
+    const double shift = st[si].shift + st[si].uoff;
+
+    const int lane = threadIdx.x;
+    const int X0 = (int)(lt % ftx) * kFinCols, Y0 = (int)(lt / ftx) * kFinRows;
+    const int Y1 = min(Y0 + kFinRows, H);
+    const int x = X0 + 4 * lane;
+    const bool in = x < W;          // the lane's quad lies in the slice (W is a multiple of 4)
+    const int xl = min(x, W - 4);   // a valid quad for every lane
+    // the wave's outer neighbour columns (lane 0: left, lane 63: right), clamped
+    const int xe = min(max(lane == 0 ? X0 - 1 : X0 + kFinCols, 0), W - 1);
+    // horizontal neighbour masks of the quad's first and last pixel
+    const double ml = x > 0 ? 1.0 : 0.0, mr = x + 3 < W - 1 ? 1.0 : 0.0;
+    // arena rows are multiples of 64 elements: a lane's quad never leaves its row
+    auto urow = [&](int y) { return u + (long long)min(max(y, 0), H - 1) * pu; };
+
+    double un[4], uc[4], us[4];
+    v4_to_d(*reinterpret_cast<const GDF_GLOBAL VT *>(urow(Y0 - 1) + xl), un);   // (row -1: masked below)
+    v4_to_d(*reinterpret_cast<const GDF_GLOBAL VT *>(urow(Y0) + xl), uc);
+    double ue = (double)urow(Y0)[xe];
+
+    // queue: u of row y + 1 (and its outer element), b and g_o of row y; past
+    // the block's last row the queue re-reads that row (cache hits, unused)
+    VT qu[Q], qb[Q];
+    VO qo[Q];
+    T qe[Q];
+    auto issue = [&](int t, int slot) {
+        const int y = min(Y0 + t, Y1 - 1);
+        qu[slot] = *reinterpret_cast<const GDF_GLOBAL VT *>(urow(y + 1) + xl);
+        qe[slot] = urow(y + 1)[xe];
+        qb[slot] = *reinterpret_cast<const GDF_GLOBAL VT *>(bu + (long long)y * pu + xl);
+        qo[slot] = *reinterpret_cast<const GDF_GLOBAL VO *>(go + off_go + (long long)y * pitch_go + xl);
+    };
+#pragma unroll
+    for (int q = 0; q < Q - 1; ++q) issue(q, q);
+    // one full wait here, so the wait at the head of the row loop (which merges
+    // the entry with the back edge) stays partial
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0)
+
+    double srr = 0.0;
+    const int n_rows = Y1 - Y0;
+    for (int tb = 0; tb < n_rows; tb += Q) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+            const int t = tb + k;
+            issue(t + Q - 1, (k + Q - 1) % Q);
+            const int y = Y0 + t;
+            const double mu = y > 0 ? 1.0 : 0.0, md = y < H - 1 ? 1.0 : 0.0;   // uniform
+            const double wrow = (t < n_rows && in) ? 1.0 : 0.0;
+            double bb[4], o[4];
+            v4_to_d(qu[k], us);
+            v4_to_d(qb[k], bb);
+            v4_to_d(qo[k], o);
+            const double ue_next = (double)qe[k];
+            double ul = wave_prev(uc[3]), ur = wave_next(uc[0]);
+            ul = lane == 0 ? ue : ul;
+            ur = lane == 63 ? ue : ur;
+            VF fv;
+            double rr = 0.0;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const double l = m == 0 ? ul : uc[m - 1], r = m == 3 ? ur : uc[m + 1];
+                const double kl = m == 0 ? ml : 1.0, kr = m == 3 ? mr : 1.0;
+                double acc = kl * (uc[m] - l);
+                acc = fma(kr, uc[m] - r, acc);
+                acc = fma(mu, uc[m] - un[m], acc);
+                acc = fma(md, uc[m] - us[m], acc);
+                const double res = bb[m] - sg * (uc[m] + shift) - acc;
+                rr = fma(res, res, rr);
+                fv[m] = (TF)(o[m] + (uc[m] + shift));
+            }
+            srr = fma(wrow, rr, srr);
+            if (t < n_rows && in)
+                *reinterpret_cast<GDF_GLOBAL VF *>(f + off_f + (long long)y * pitch_f + x) = fv;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                un[m] = uc[m];
+                uc[m] = us[m];
+            }
+            ue = ue_next;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) srr += __shfl_xor(srr, off);
+    if (lane == 0) part_rr[ft] = srr;
 }
 
 template <typename T, typename TO>
-static hipError_t fin_go(int out_dtype, const void *go, void *f, const SliceIO *io, int n,
+static hipError_t fin_go(bool rows, int out_dtype, const void *go, void *f, const SliceIO *io, int n,
                          long long nt, const LevelDesc *levs, const SliceState *st, const int *only,
                          double *prr, hipStream_t s)
 {
-    const dim3 g((unsigned)nt), blk(256);
-    if (out_dtype == 2)
-        hipLaunchKernelGGL((finalize_kernel<T, TO, double>), g, blk, 0, s, (const TO *)go, (double *)f, io, n, nt, levs, st, only, prr);
-    else
-        hipLaunchKernelGGL((finalize_kernel<T, TO, float>), g, blk, 0, s, (const TO *)go, (float *)f, io, n, nt, levs, st, only, prr);
+    if (rows) {
+        const dim3 g((unsigned)nt), blk(64);
+        if (out_dtype == 2)
+            hipLaunchKernelGGL((finalize_kernel<T, TO, double>), g, blk, 0, s, (const TO *)go, (double *)f, io, n, nt, levs, st, only, prr);
+        else
+            hipLaunchKernelGGL((finalize_kernel<T, TO, float>), g, blk, 0, s, (const TO *)go, (float *)f, io, n, nt, levs, st, only, prr);
+    } else {
+        const dim3 g((unsigned)nt), blk(256);
+        if (out_dtype == 2)
+            hipLaunchKernelGGL((finalize_quad_kernel<T, TO, double>), g, blk, 0, s, (const TO *)go, (double *)f, io, n, nt, levs, st, only, prr);
+        else
+            hipLaunchKernelGGL((finalize_quad_kernel<T, TO, float>), g, blk, 0, s, (const TO *)go, (float *)f, io, n, nt, levs, st, only, prr);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(bool fp64, int go_dtype, const void *go, int out_dtype, void *f,
+hipError_t launch_finalize(bool fp64, bool rows, int go_dtype, const void *go, int out_dtype, void *f,
                            const SliceIO *io_dev, int n, long long n_tiles,
                            const LevelDesc *levs, const SliceState *st, const int *only,
                            double *part_rr, hipStream_t s)
 {
     if (n_tiles <= 0) return hipSuccess;
     if (fp64) {
-        if (go_dtype == 0) return fin_go<double, uint8_t>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
-        if (go_dtype == 1) return fin_go<double, float>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
-        return fin_go<double, double>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+        if (go_dtype == 0) return fin_go<double, uint8_t>(rows, out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+        if (go_dtype == 1) return fin_go<double, float>(rows, out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+        return fin_go<double, double>(rows, out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
     }
-    if (go_dtype == 0) return fin_go<float, uint8_t>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
-    if (go_dtype == 1) return fin_go<float, float>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
-    return fin_go<float, double>(out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+    if (go_dtype == 0) return fin_go<float, uint8_t>(rows, out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+    if (go_dtype == 1) return fin_go<float, float>(rows, out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
+    return fin_go<float, double>(rows, out_dtype, go, f, io_dev, n, n_tiles, levs, st, only, part_rr, s);
 }
 
 // ------------------------------------------------------------ adjoint ---
@@ -437,8 +605,8 @@ __global__ __launch_bounds__(256) void prep_adjoint_kernel(const T *gf, const Sl
     const double t = block_sum(sbb, red);
     const double t2 = block_sum(sbs, red);
     if (threadIdx.x == 0) {
-        part_bb[blockIdx.x] = t;
-        part_bs[blockIdx.x] = t2;
+        part_bb[c.tile] = t;
+        part_bs[c.tile] = t2;
     }
 }
 
@@ -528,7 +696,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const T *gs, const T *f, T
         adjoint_quad<T, T>(lam, shift, gs, f, ggs, ggo, c, L.pitch, sda);
     }
     const double t = block_sum(sda, red);
-    if (threadIdx.x == 0) part_da[blockIdx.x] = t;
+    if (threadIdx.x == 0) part_da[c.tile] = t;
 }
 
 hipError_t launch_adjoint_assemble(bool fp64, const void *gs, const void *f, void *ggs, void *ggo,
@@ -618,7 +786,7 @@ __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a)
         store4(static_cast<float *>(L.b), p, nv, res);
     }
     const double t = block_sum(srr, red);
-    if (threadIdx.x == 0) a.part_rr[blockIdx.x] = t;
+    if (threadIdx.x == 0) a.part_rr[c.tile] = t;
 }
 
 hipError_t launch_refine(const RefineArgs &a, hipStream_t s)

@@ -234,6 +234,30 @@ def test_fp32_floor_slice_escalates_to_refinement():
         assert np.abs(f[0].cpu().numpy() - fr).max() <= 1e-3
 
 
+def test_output_pass_row_and_quad_agree():
+    # widths that are multiples of 4 with aligned outputs take the row-marching
+    # output pass; a leading 3 x 3 slice shifts every later output off the
+    # four-element grid and sends the whole call through the quad pass
+    shapes = [(200, 260), (96, 512), (37, 4)]
+    al = [0.01, 0.003, 0.05]
+    pairs = [synth.batch_slice(H, W, 70 + i) for i, (H, W) in enumerate(shapes)]
+    tg = [torch.from_numpy(s).to(DEV) for _, s in pairs]
+    to = [torch.from_numpy(o).to(DEV) for o, _ in pairs]
+    print("row vs quad output pass", shapes, flush=True)
+    f1, r1 = gdf.solve_slices(tg, to, al, tol=1e-6)
+    o3, s3 = synth.batch_slice(3, 3, 79)
+    f2, r2 = gdf.solve_slices([torch.from_numpy(s3).to(DEV)] + tg, [torch.from_numpy(o3).to(DEV)] + to,
+                              [0.02] + al, tol=1e-6)
+    for i in range(len(shapes)):
+        assert torch.equal(f1[i], f2[i + 1])
+        assert r1[i]["vcycles"] == r2[i + 1]["vcycles"]
+        assert abs(r1[i]["rel_residual"] - r2[i + 1]["rel_residual"]) <= 1e-9 * r1[i]["rel_residual"]
+        assert r1[i]["rel_residual"] <= 1e-6 and r1[i]["status"] == gdf.GDF_OK
+        o, s = pairs[i]
+        fr = oracle.solve(s, o.astype(np.float64), al[i], tol=1e-11)
+        assert np.abs(f1[i].cpu().numpy() - fr).max() <= 1e-3
+
+
 @pytest.mark.parametrize("nu,fine_sweeps", [(2, 5), (2, 6), (1, 3), (1, 4)])
 def test_fused_pass_sweep_counts(nu, fine_sweeps):
     # more sweeps in the fused finest pass: same solution, fewer or equal cycles
