@@ -203,7 +203,7 @@ struct Plan {
     int list_first = -1, list_fine = -1, list_single = -1;
     int list_down[kMaxLevels], list_up[kMaxLevels], list_coarse[kMaxLevels];
     int max_level = 0;
-    std::vector<int> ranges_first, ranges_cycle, ranges_tiles, ranges_ftiles, ranges_smooth;
+    std::vector<int> ranges_cycle, ranges_tiles, ranges_ftiles, ranges_smooth;
     int n_norm;
     std::vector<SliceIO> io;
     long long n_tiles = 0;
@@ -213,7 +213,7 @@ struct Plan {
     bool need_gs_copy = false;   // fuse_stack MIXED without g_smooth output
     // layout (bytes from the workspace base)
     size_t off_tables, tables_bytes;
-    size_t off_state, off_active, off_only, off_desc, off_items, off_r_first, off_r_cycle, off_r_tiles, off_r_ftiles,
+    size_t off_state, off_active, off_only, off_desc, off_items, off_r_cycle, off_r_tiles, off_r_ftiles,
         off_r_smooth, off_io, off_u64tab;
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
@@ -382,7 +382,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     for (int l = 0; l < kMaxLevels; ++l) P.list_down[l] = P.list_up[l] = P.list_coarse[l] = -1;
     std::vector<int> mid0, single0;
     for (int s = 0; s < n; ++s) (P.g[s].nlev > 1 ? mid0 : single0).push_back(s);
-    P.list_first = add_list(P, SK_DOWN_FIRST, 0, mid0);
+    P.list_first = add_list(P, SK_FIRST_RESTRICT, 0, mid0);
     P.list_fine = add_list(P, SK_FINE, 0, mid0);
     P.list_single = add_list(P, SK_SINGLE, 0, single0);
     for (int l = 1; l <= P.max_level; ++l) {
@@ -395,14 +395,10 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
         P.list_up[l] = add_list(P, SK_UP, l, mid);
         P.list_coarse[l] = add_list(P, SK_COARSE, l, coarsest);
     }
-    const int nF = P.list_first >= 0 ? P.lists[P.list_first].count : 0;
     const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
     const int nS = P.list_single >= 0 ? P.lists[P.list_single].count : 0;
-    P.n_norm = std::max(nF, nC) + nS;
-    P.ranges_first.assign(2 * n, -1);
+    P.n_norm = nC + nS;   // norm partials: fused finest pass, then single-level slices
     P.ranges_cycle.assign(2 * n, -1);
-    list_ranges(P, P.list_first, 0, P.ranges_first);
-    list_ranges(P, P.list_single, nF, P.ranges_first);
     list_ranges(P, P.list_fine, 0, P.ranges_cycle);
     list_ranges(P, P.list_single, nC, P.ranges_cycle);
     // tiles for the per-pixel kernels
@@ -453,7 +449,6 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.off_only = take(sizeof(int) * n);
     P.off_desc = take(sizeof(LevelDesc) * P.descs.size());
     P.off_items = take(sizeof(Item) * std::max<size_t>(1, P.items.size()));
-    P.off_r_first = take(sizeof(int) * 2 * n);
     P.off_r_cycle = take(sizeof(int) * 2 * n);
     P.off_r_tiles = take(sizeof(int) * 2 * n);
     P.off_r_ftiles = take(sizeof(int) * 2 * n);
@@ -507,7 +502,6 @@ std::vector<char> bind_tables(const Plan &P, char *ws, const std::vector<SliceIO
     }
     std::memcpy(img.data() + P.off_desc, descs.data(), sizeof(LevelDesc) * descs.size());
     if (!P.items.empty()) std::memcpy(img.data() + P.off_items, P.items.data(), sizeof(Item) * P.items.size());
-    std::memcpy(img.data() + P.off_r_first, P.ranges_first.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_cycle, P.ranges_cycle.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_tiles, P.ranges_tiles.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_r_ftiles, P.ranges_ftiles.data(), sizeof(int) * 2 * P.n);
@@ -660,7 +654,7 @@ struct Run {
     int *only;      // slices to re-finalize after a resume
     LevelDesc *desc;
     Item *items;
-    int *r_first, *r_cycle, *r_tiles, *r_ftiles, *r_smooth;
+    int *r_cycle, *r_tiles, *r_ftiles, *r_smooth;
     SliceIO *io;
     double **u64tab;
     float2 *partf;
@@ -677,7 +671,6 @@ struct Run {
         only = reinterpret_cast<int *>(ws + P.off_only);
         desc = reinterpret_cast<LevelDesc *>(ws + P.off_desc);
         items = reinterpret_cast<Item *>(ws + P.off_items);
-        r_first = reinterpret_cast<int *>(ws + P.off_r_first);
         r_cycle = reinterpret_cast<int *>(ws + P.off_r_cycle);
         r_tiles = reinterpret_cast<int *>(ws + P.off_r_tiles);
         r_ftiles = reinterpret_cast<int *>(ws + P.off_r_ftiles);
@@ -755,24 +748,26 @@ struct Run {
     {
         const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
-        const int nF = P.list_first >= 0 ? P.lists[P.list_first].count : 0;
-        // read b, write u, write the coarse right-hand side (a quarter per pixel)
-        if ((r = strip(P.list_first, SK_DOWN_FIRST, 0, 0, partf, fp64, PC_FIRST, 2 * e + 0.25 * ce))) return r;
-        if ((r = strip(P.list_single, SK_SINGLE_ZERO, 0, 0, partf + nF, fp64, PC_COARSE, 2 * e))) return r;
+        const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
+        // read b, write the coarse right-hand side (a quarter per pixel)
+        if ((r = strip(P.list_first, SK_FIRST_RESTRICT, 0, 0, partf, fp64, PC_FIRST, e + 0.25 * ce))) return r;
+        if ((r = strip(P.list_single, SK_SINGLE_ZERO, 0, 0, partf + nC, fp64, PC_COARSE, 2 * e))) return r;
         return GDF_OK;
     }
 
     // slice_par: F/S passes take each slice's buffer parity from its cycle
     // count (plain solve); otherwise from k (the inner solves of the mixed mode)
-    gdf_status cycle(int k, bool fp64, bool slice_par = true)
+    // zero: the finest iterate is zero (first cycle after a restricting first pass)
+    gdf_status cycle(int k, bool fp64, bool slice_par = true, bool zero = false)
     {
         const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
         if ((r = coarse(fp64))) return r;
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
-        // read u and b, write u; read the coarse correction and write the coarse
-        // right-hand side (a quarter per pixel each)
-        if ((r = strip(P.list_fine, SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE, 3 * e + 0.5 * ce, slice_par)))
+        // read u (unless zero) and b, write u; read the coarse correction and
+        // write the coarse right-hand side (a quarter per pixel each)
+        if ((r = strip(P.list_fine, zero ? SK_FINE_ZERO : SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE,
+                       (zero ? 2 : 3) * e + 0.5 * ce, slice_par)))
             return r;
         if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e, slice_par))) return r;
         return GDF_OK;
@@ -800,12 +795,12 @@ struct Run {
     {
         gdf_status r;
         if (first) {
-            if ((r = first_pass(fp64))) return r;
-            if ((r = finish(r_first, partf, nullptr, FIN_CHECK, 0))) return r;
+            if ((r = first_pass(fp64))) return r;   // (no iterate to check yet)
         }
+        const bool z = first;   // first cycle from a zero iterate
         if (capturing) {
             for (int k = 1; k <= (captured ? captured : max_cycles); ++k) {
-                if ((r = cycle(k, fp64))) return r;
+                if ((r = cycle(k, fp64, true, z && k == 1))) return r;
                 if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
             }
             return GDF_OK;
@@ -814,7 +809,7 @@ struct Run {
         for (int k = 1; k <= max_cycles; ++k) {
             if ((r = read_active(any))) return r;
             if (!any) break;
-            if ((r = cycle(k, fp64))) return r;
+            if ((r = cycle(k, fp64, true, z && k == 1))) return r;
             if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
         }
         return GDF_OK;
@@ -969,7 +964,7 @@ gdf_status mixed_iterate(Run &R, int gs_dtype, const void *gs, int go_dtype, con
         }
         if ((r = R.first_pass(false))) return r;
         for (int c = 1; c <= P.o.inner; ++c)
-            if ((r = R.cycle(c, false, false))) return r;
+            if ((r = R.cycle(c, false, false, c == 1))) return r;
         ra.first = 0;
         ra.in_sel = (k - 1) & 1;
         ra.e_sel = P.o.inner & 1;

@@ -75,7 +75,7 @@ struct StripLaunch {
 
 // Strip kernel variants (template instances live in mg_kernels.hip).
 enum StripKind {
-    SK_DOWN_FIRST,   // zero start, 2nu sweeps, residual -> norm + restrict (finest, first pass)
+    SK_FIRST_RESTRICT,  // finest, first pass of a solve from zero: restrict b (no sweeps)
     SK_FINE,         // prolongate, 4nu sweeps, residual -> norm + restrict (finest, fused up+down)
     SK_DOWN,         // zero start, 2nu sweeps, restrict (coarse levels, down leg)
     SK_UP,           // prolongate, 2nu sweeps (coarse levels, up leg)
@@ -83,6 +83,7 @@ enum StripKind {
     SK_COARSE,       // 2 sweeps (coarsest level)
     SK_SINGLE_ZERO,  // zero start, 2 sweeps, residual -> norm (single-level slices)
     SK_SINGLE,       // 2 sweeps, residual -> norm
+    SK_FINE_ZERO,    // as SK_FINE from a zero iterate (the first cycle after SK_FIRST_RESTRICT)
     SK_COUNT
 };
 

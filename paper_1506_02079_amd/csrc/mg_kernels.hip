@@ -225,23 +225,28 @@ __device__ __forceinline__ int xcd_logical_block()
 #ifndef GDF_QUEUE_MAX
 #define GDF_QUEUE_MAX 4
 #endif
-constexpr int queue_len(int rs)
+#ifndef GDF_QUEUE_ZERO
+#define GDF_QUEUE_ZERO 4
+#endif
+constexpr int queue_len(int rs, int qmax)
 {
-    for (int q = GDF_QUEUE_MAX; q >= 2; --q)
+    for (int q = qmax; q >= 2; --q)
         if (rs % q == 0) return q;
     return 1;
 }
 
-template <bool PROLONG, int NHS, int RMODE> struct StripShape {
+// QM: the deepest load queue wanted (passes that start from zero load only b
+// and afford a deeper one)
+template <bool PROLONG, int NHS, int RMODE, int QM = GDF_QUEUE_MAX> struct StripShape {
     static constexpr int NS = NHS + (RMODE != RES_NONE ? 1 : 0);  // stages after the load
     static constexpr int G = (NS + (PROLONG ? 1 : 0) + 1) & ~1;   // halo, even
     static constexpr int VW = kStripCols - 2 * G;                  // owned columns
     // register ring rows: at least 2 NS + 2, rounded up so that a full-depth
     // load queue divides it
-    static constexpr int RS = (2 * NS + 2 + GDF_QUEUE_MAX - 1) / GDF_QUEUE_MAX * GDF_QUEUE_MAX;
+    static constexpr int RS = (2 * NS + 2 + QM - 1) / QM * QM;
     // loads run Q - 1 rows ahead of the row entering the ring, so each wave keeps
     // several rows of HBM reads in flight
-    static constexpr int Q = queue_len(RS);
+    static constexpr int Q = queue_len(RS, QM);
 };
 
 // Variants.  VAR 1 (interior): the item's rows y0 - G .. y1 + G all lie in
@@ -265,7 +270,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 {
     constexpr bool RIN = VAR != 0;   // rows interior: no row guards
     constexpr bool CIN = VAR == 1;   // columns interior as well: one stencil for all lanes
-    using Sh = StripShape<PROLONG, NHS, RMODE>;
+    using Sh = StripShape<PROLONG, NHS, RMODE, ZERO ? GDF_QUEUE_ZERO : GDF_QUEUE_MAX>;
     constexpr int NS = Sh::NS, G = Sh::G, VW = Sh::VW, RS = Sh::RS, Q = Sh::Q;
     static_assert((RS & 1) == 0 && RS % Q == 0, "ring slots and queue slots must be static");
     using PO = typename Stor<SO>::Pair;
@@ -487,14 +492,15 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                         b[k][0] = in0 ? b[k][0] : T(0);
                         b[k][1] = in1 ? b[k][1] : T(0);
                     }
-                    if (!ZERO) {
-                        // row parity = k parity (ybase and tb even): black column 1 - (k & 1)
+                    if (!ZERO || PROLONG) {
+                        // row parity = k parity (ybase and tb even): black column 1 - (k & 1);
+                        // from a zero iterate (ZERO) the prolonged correction alone
                         if (k & 1) {
-                            const T v = (T)SOt::get(qus[qs]) + cor0;
+                            const T v = (ZERO ? T(0) : (T)SOt::get(qus[qs])) + cor0;
                             u[k][0] = (CIN || in0) ? v : T(0);
                             u[k][1] = T(0);   // red: rewritten by the first half-sweep unread
                         } else {
-                            const T v = (T)SOt::get(qus[qs]) + cor1;
+                            const T v = (ZERO ? T(0) : (T)SOt::get(qus[qs])) + cor1;
                             u[k][0] = T(0);
                             u[k][1] = (CIN || in1) ? v : T(0);
                         }
@@ -508,8 +514,8 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                     const bool v0 = rin && in0, v1 = rin && in1;
                     b[k][0] = v0 ? (T)SOt::lo(qb[qs]) - bsh : T(0);
                     b[k][1] = v1 ? (T)SOt::hi(qb[qs]) - bsh : T(0);
-                    u[k][0] = (!ZERO && v0) ? (T)SOt::lo(qu[qs]) + cor0 : T(0);
-                    u[k][1] = (!ZERO && v1) ? (T)SOt::hi(qu[qs]) + cor1 : T(0);
+                    u[k][0] = v0 ? (ZERO ? T(0) : (T)SOt::lo(qu[qs])) + cor0 : T(0);
+                    u[k][1] = v1 ? (ZERO ? T(0) : (T)SOt::hi(qu[qs])) + cor1 : T(0);
                 }
             }
             // ------------------------------------------------ stages 1..NS
@@ -707,7 +713,8 @@ template <bool PROLONG, int RMODE> static int halo_by_sweeps(int sw)
 int strip_halo(StripKind k, int nu, int fsw)
 {
     switch (k) {
-    case SK_DOWN_FIRST: return halo_by_sweeps<false, RES_BOTH>(nu);
+    case SK_FIRST_RESTRICT: return StripShape<false, 0, RES_RESTRICT>::G;
+    case SK_FINE_ZERO:
     case SK_FINE: return halo_by_sweeps<true, RES_BOTH>(fsw);
     case SK_DOWN: return halo_by_sweeps<false, RES_RESTRICT>(nu);
     case SK_UP: return halo_by_sweeps<true, RES_NONE>(nu);
@@ -779,8 +786,6 @@ static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const Str
 {
     const bool n1 = nu == 1;
     switch (k) {
-    case SK_DOWN_FIRST:
-        return n1 ? go<T, false, true, 2, RES_BOTH>(a, p, s, w) : go<T, false, true, 4, RES_BOTH>(a, p, s, w);
     case SK_FINE:
         switch (fsw) {
         case 2: return go<T, true, false, 4, RES_BOTH>(a, p, s, w);
@@ -799,6 +804,16 @@ static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const Str
     case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, p, s, w);
     case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, p, s, w);
     case SK_SINGLE: return go<T, false, false, 4, RES_NORM>(a, p, s, w);
+    case SK_FIRST_RESTRICT: return go<T, false, true, 0, RES_RESTRICT>(a, p, s, w);
+    case SK_FINE_ZERO:
+        switch (fsw) {
+        case 2: return go<T, true, true, 4, RES_BOTH>(a, p, s, w);
+        case 3: return go<T, true, true, 6, RES_BOTH>(a, p, s, w);
+        case 4: return go<T, true, true, 8, RES_BOTH>(a, p, s, w);
+        case 5: return go<T, true, true, 10, RES_BOTH>(a, p, s, w);
+        case 6: return go<T, true, true, 12, RES_BOTH>(a, p, s, w);
+        default: return hipErrorInvalidValue;
+        }
     default: return hipErrorInvalidValue;
     }
 }
@@ -817,7 +832,7 @@ void strip_prepare(int nu, int fsw, bool fp64)
 {
     StripLaunch a;
     a.n_items = -1;
-    for (int k = SK_DOWN_FIRST; k <= SK_SINGLE; ++k)
+    for (int k = 0; k < SK_COUNT; ++k)
         (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, fsw, true, a, nullptr)
                     : launch_strip_t<float>((StripKind)k, nu, fsw, true, a, nullptr));
 }
