@@ -213,7 +213,7 @@ struct Plan {
     bool need_gs_copy = false;   // fuse_stack MIXED without g_smooth output
     // layout (bytes from the workspace base)
     size_t off_tables, tables_bytes;
-    size_t off_state, off_active, off_only, off_desc, off_items, off_r_cycle, off_r_tiles, off_r_ftiles,
+    size_t off_state, off_active, off_only, off_done, off_desc, off_items, off_r_cycle, off_r_tiles, off_r_ftiles,
         off_r_smooth, off_io, off_u64tab;
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
@@ -447,6 +447,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.off_state = take(sizeof(SliceState) * n);
     P.off_active = take(sizeof(int) * n);
     P.off_only = take(sizeof(int) * n);
+    P.off_done = take(sizeof(int));
     P.off_desc = take(sizeof(LevelDesc) * P.descs.size());
     P.off_items = take(sizeof(Item) * std::max<size_t>(1, P.items.size()));
     P.off_r_cycle = take(sizeof(int) * 2 * n);
@@ -652,6 +653,7 @@ struct Run {
     SliceState *st;
     int *active;
     int *only;      // slices to re-finalize after a resume
+    int *done;      // set when no slice is active (read by the passes of a captured schedule)
     LevelDesc *desc;
     Item *items;
     int *r_cycle, *r_tiles, *r_ftiles, *r_smooth;
@@ -669,6 +671,7 @@ struct Run {
         st = reinterpret_cast<SliceState *>(ws + P.off_state);
         active = reinterpret_cast<int *>(ws + P.off_active);
         only = reinterpret_cast<int *>(ws + P.off_only);
+        done = reinterpret_cast<int *>(ws + P.off_done);
         desc = reinterpret_cast<LevelDesc *>(ws + P.off_desc);
         items = reinterpret_cast<Item *>(ws + P.off_items);
         r_cycle = reinterpret_cast<int *>(ws + P.off_r_cycle);
@@ -699,13 +702,14 @@ struct Run {
         if (li < 0) return GDF_OK;
         const List &L = P.lists[li];
         if (L.count == 0) return GDF_OK;
-        StripLaunch a;
+        StripLaunch a{};
         a.levs = desc;
         a.in_sel = in_sel;
         a.out_sel = out_sel;
         a.cycles = slice_parity ? &st[0].cycles : nullptr;
         a.cycles_stride = (int)(sizeof(SliceState) / sizeof(int));
         a.active = active;
+        a.done = capturing ? done : nullptr;
         a.partials = partials;
         const bool timed = g_prof_on && (!g_prof_fine_only || cls == PC_FINE);
         ProfScope ps(cls, timed ? pass_bytes(li, per_px) : 0.0, s, capturing);
@@ -799,9 +803,12 @@ struct Run {
         }
         const bool z = first;   // first cycle from a zero iterate
         if (capturing) {
+            // passes after the last active slice exit at once (the done flag)
+            HIP_TRY(launch_done(P.n, active, done, s));
             for (int k = 1; k <= (captured ? captured : max_cycles); ++k) {
                 if ((r = cycle(k, fp64, true, z && k == 1))) return r;
                 if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
+                HIP_TRY(launch_done(P.n, active, done, s));
             }
             return GDF_OK;
         }

@@ -70,6 +70,7 @@ struct StripLaunch {
     const int *cycles;       // if non-null: read buffer (cycles[slice] & 1), write the other
     int cycles_stride;       // ints between consecutive slices' counters
     const int *active;       // per-slice "still iterating" flags
+    const int *done;         // if non-null and set: no slice is iterating (every wave exits at once)
     float2 *partials;        // per-item partial sums (r^2, r) (RES_NORM / RES_BOTH)
 };
 
@@ -158,6 +159,11 @@ hipError_t launch_finish_rhs(int n_slices, const int *range, const double *pbb, 
 // After the exact residual of the output (FIN_FINAL): slices whose FP64
 // relative residual still exceeds tol, with cycles left and finite state,
 // get active = only = 1 (resume iterating, re-form f); others get 0.
+// done = 1 when no slice's active flag is set, else 0 (one workgroup).  Lets
+// the passes of a captured schedule that outlast the last active slice exit
+// at their first instruction.
+hipError_t launch_done(int n_slices, const int *active, int *done, hipStream_t s);
+
 hipError_t launch_resume_flags(int n_slices, const SliceState *state, double tol, int max_cycles,
                                int *active, int *only, hipStream_t s);
 

@@ -684,6 +684,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
+    if (a.done && uniform(*a.done)) return;   // a captured pass after the last active slice
     const int stride = gridDim.x * kWavesPerBlock;
     for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
          id += stride) {
@@ -820,7 +821,7 @@ static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const Str
 
 int strip_resident_waves(StripKind k, int nu, int fsw, bool fp64)
 {
-    StripLaunch a;
+    StripLaunch a{};
     a.n_items = -1;
     int w = 0;
     const hipError_t e = fp64 ? launch_strip_t<double>(k, nu, fsw, true, a, nullptr, &w)
@@ -830,7 +831,7 @@ int strip_resident_waves(StripKind k, int nu, int fsw, bool fp64)
 
 void strip_prepare(int nu, int fsw, bool fp64)
 {
-    StripLaunch a;
+    StripLaunch a{};
     a.n_items = -1;
     for (int k = 0; k < SK_COUNT; ++k)
         (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, fsw, true, a, nullptr)

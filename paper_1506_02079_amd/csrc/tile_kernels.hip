@@ -223,6 +223,24 @@ hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void done_kernel(int n_slices, const int *active, int *done)
+{
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int a = 0;
+    for (int i = threadIdx.x; i < n_slices; i += blockDim.x) a |= active[i];
+    if (a) any = 1;   // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) *done = any ? 0 : 1;
+}
+
+hipError_t launch_done(int n_slices, const int *active, int *done, hipStream_t s)
+{
+    hipLaunchKernelGGL(done_kernel, dim3(1), dim3(256), 0, s, n_slices, active, done);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void resume_flags_kernel(int n_slices, const SliceState *st, double tol,
                                                           int max_cycles, int *active, int *only)
 {
