@@ -146,61 +146,6 @@ template <> struct Stor<unsigned short> {   // bfloat16
     }
 };
 
-// ------------------------------------------------------- buffer access ---
-
-// Raw buffer resource over `bytes` bytes from `base` (no stride or swizzle;
-// dword 3 selects plain dword access on this GPU family).  The address of an
-// access is base + row offset (a scalar) + lane offset; a lane offset at or
-// past `bytes` reads zero and drops a store.  So a lane is masked by its
-// offset and a whole row by a zero-sized resource, without a branch.
-typedef __amdgpu_buffer_rsrc_t Rsrc;
-__device__ __forceinline__ Rsrc make_rsrc(const void *base, unsigned bytes)
-{
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
-}
-// a lane offset past every window (the host keeps an item's rows below 2^31 bytes)
-constexpr unsigned kNoLane = 0x80000000u;
-
-template <typename X> struct Buf;
-template <> struct Buf<unsigned short> {
-    __device__ static unsigned short ld(Rsrc r, unsigned vo, unsigned so)
-    {
-        return __builtin_amdgcn_raw_buffer_load_b16(r, (int)vo, (int)so, 0);
-    }
-    __device__ static void st(unsigned short v, Rsrc r, unsigned vo, unsigned so)
-    {
-        __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)vo, (int)so, 0);
-    }
-};
-template <> struct Buf<unsigned> {
-    __device__ static unsigned ld(Rsrc r, unsigned vo, unsigned so)
-    {
-        return __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0);
-    }
-    __device__ static void st(unsigned v, Rsrc r, unsigned vo, unsigned so)
-    {
-        __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)vo, (int)so, 0);
-    }
-};
-template <> struct Buf<float> {
-    __device__ static float ld(Rsrc r, unsigned vo, unsigned so) { return __uint_as_float(Buf<unsigned>::ld(r, vo, so)); }
-    __device__ static void st(float v, Rsrc r, unsigned vo, unsigned so) { Buf<unsigned>::st(__float_as_uint(v), r, vo, so); }
-};
-typedef unsigned U2 __attribute__((ext_vector_type(2)));
-typedef unsigned U4 __attribute__((ext_vector_type(4)));
-template <typename X, typename R> struct BufBits {   // 8- and 16-byte values
-    __device__ static X ld(Rsrc r, unsigned vo, unsigned so)
-    {
-        if constexpr (sizeof(X) == 8) return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
-        else return __builtin_bit_cast(X, __builtin_amdgcn_raw_buffer_load_b128(r, (int)vo, (int)so, 0));
-    }
-    __device__ static void st(X v, Rsrc r, unsigned vo, unsigned so)
-    {
-        if constexpr (sizeof(X) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(R, v), r, (int)vo, (int)so, 0);
-        else __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(R, v), r, (int)vo, (int)so, 0);
-    }
-};
-template <> struct Buf<double> : BufBits<double, U2> {};
 template <> struct Buf<Stor<float>::Pair> : BufBits<Stor<float>::Pair, U2> {};
 template <> struct Buf<Stor<double>::Pair> : BufBits<Stor<double>::Pair, U4> {};
 

@@ -132,7 +132,32 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     const long long nparts = (long long)a.tiles_x * a.tiles_y;   // one partial per tile
 
     uint32_t pf[kPrefetch];   // raw tile of the next input slice, in flight
+    // Each thread loads the same raw dwords of every slice: their offsets in
+    // the tile's row window are fixed per thread (kNoLane outside the slice:
+    // the load reads zero).  A stack whose rows are 4-byte aligned and a
+    // multiple of 4 wide (every dword whole) with a small enough row pitch
+    // takes that path; others read byte by byte.
+    const bool fastld = aligned && (W & 3) == 0 && a.pitch_row * kRawHMax < 0x7fffffffLL;
+    const int gy0 = max(Y0 - RH, 0), gy1 = min(Y0 + kSTY + RH, H);   // the window's rows
+    unsigned voff[kPrefetch];
+#pragma unroll
+    for (int q = 0; q < kPrefetch; ++q) {
+        const int e = tid + q * kSThreads;
+        const int r = e / kRawDw, c = e - r * kRawDw;
+        const int gy = Y0 - RH + r, gx = X0 - 8 + 4 * c;   // gx: a multiple of 4
+        const bool in = e < n_dw && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        voff[q] = in ? (unsigned)((gy - gy0) * a.pitch_row + gx) : kNoLane;
+    }
     auto issue = [&](int zi) {
+        if (fastld) {
+            if (zi < S) {   // uniform
+                const Rsrc rs = make_rsrc(a.stack + (long long)zi * a.pitch_slice + (long long)gy0 * a.pitch_row,
+                                          (unsigned)((gy1 - gy0) * a.pitch_row));
+#pragma unroll
+                for (int q = 0; q < kPrefetch; ++q) pf[q] = Buf<unsigned>::ld(rs, voff[q], 0);
+            }
+            return;
+        }
 #pragma unroll
         for (int q = 0; q < kPrefetch; ++q) {
             const int e = tid + q * kSThreads;
@@ -152,10 +177,27 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
         }
     };
     // raw byte at tile-local raw row r (row 0 = Y0 - RH) and byte column c (x = X0 - 8 + c)
+    // (a byte load from LDS: no shift-and-mask on the vector unit)
     auto raw_at = [&](int slot, int r, int c) -> float {
-        const uint32_t w = ring_raw[slot][r * kRawDw + (c >> 2)];
-        return (float)((w >> (8 * (c & 3))) & 0xffu);
+        return (float)reinterpret_cast<const uint8_t *>(ring_raw[slot])[r * kRawW + c];
     };
+    // output offsets of this thread's rows in the tile's rows of a slice's b
+    // (and of g_s): kNoLane outside the slice, so the stores need no branch;
+    // and the masks of the Laplacian's in-slice neighbours
+    unsigned vb[kSRows], vg[kSRows];
+    bool oin[kSRows];
+    float myu[kSRows], myd[kSRows];
+#pragma unroll
+    for (int i = 0; i < kSRows; ++i) {
+        const int y = Y0 + yb + i;
+        const bool in = y < H && x < W;
+        vb[i] = in ? (unsigned)(((yb + i) * a.b_pitch + x) * (int)sizeof(T)) : kNoLane;
+        vg[i] = in ? (unsigned)(((yb + i) * W + x) * (int)sizeof(T)) : kNoLane;
+        oin[i] = in;
+        myu[i] = y > 0 ? 1.f : 0.f;
+        myd[i] = y < H - 1 ? 1.f : 0.f;
+    }
+    const float mxl = x > 0 ? 1.f : 0.f, mxr = x < W - 1 ? 1.f : 0.f;
 
     issue(0);
     commit(0);
@@ -225,7 +267,13 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                     if constexpr (sizeof(T) == 4) iz = a.inv_wz_f[zlo][zhi];
                     else iz = a.inv_wz[zlo][zhi];
                     const int oslot = zo % NRAW;
-                    T *bdst = static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride;
+                    // this slice's tile rows of b (and of g_s): windows of kSTY rows
+                    const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride +
+                                                   (long long)Y0 * a.b_pitch,
+                                               (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)));
+                    const Rsrc rgw = a.gs_out ? make_rsrc(static_cast<T *>(a.gs_out) + ((long long)zo * H + Y0) * W,
+                                                          (unsigned)(kSTY * W * (int)sizeof(T)))
+                                              : rbw;
                     T sbb = T(0), sb0 = T(0), sbs = T(0);
                     // original slice around this thread's column
                     float oc[kSRows + 2], ol[kSRows], orr[kSRows];
@@ -244,23 +292,22 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                         for (int d = 1; d <= RZ; ++d)
                             acc += wz[d] * (ring[((k - 1 - RZ - d) % NZ + NZ) % NZ][i] +
                                             ring[((k - 1 - RZ + d) % NZ + NZ) % NZ][i]);
-                        const int y = Y0 + yb + i;
-                        if (y < H && x < W) {
-                            const T g = acc * iz;
-                            const float o = oc[i + 1];
-                            float lap = 0.f;   // (L g_o)_p over in-slice neighbours
-                            if (x > 0) lap += o - ol[i];
-                            if (x < W - 1) lap += o - orr[i];
-                            if (y > 0) lap += o - oc[i];
-                            if (y < H - 1) lap += o - oc[i + 2];
-                            const T bu = alT * (g - (T)o);
-                            const T bf = alT * g + (T)lap;
-                            bdst[(size_t)y * a.b_pitch + x] = bu;
-                            if (a.gs_out) static_cast<T *>(a.gs_out)[((long long)zo * H + y) * W + x] = g;
-                            sbb += bf * bf;
-                            sb0 += bu * bu;
-                            sbs += bu;
-                        }
+                        const T g = acc * iz;
+                        const float o = oc[i + 1];
+                        // (L g_o)_p over in-slice neighbours
+                        float lap = mxl * (o - ol[i]);
+                        lap = fmaf(mxr, o - orr[i], lap);
+                        lap = fmaf(myu[i], o - oc[i], lap);
+                        lap = fmaf(myd[i], o - oc[i + 2], lap);
+                        const T bu = alT * (g - (T)o);
+                        const T bf = alT * g + (T)lap;
+                        Buf<T>::st(bu, rbw, vb[i], 0);
+                        if (a.gs_out) Buf<T>::st(g, rgw, vg[i], 0);
+                        // (selects: outside the slice the values may not be finite)
+                        const T bum = oin[i] ? bu : T(0), bfm = oin[i] ? bf : T(0);
+                        sbb = fma(bfm, bfm, sbb);
+                        sb0 = fma(bum, bum, sb0);
+                        sbs += bum;
                     }
                     const double tbb = (double)wave_sum(sbb), tb0 = (double)wave_sum(sb0),
                                  tbs = (double)wave_sum(sbs);
@@ -272,20 +319,16 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                 }
                 commit(zi + 1);      // no reader of that slot in this phase
                 __syncthreads();
-                if (zo >= 0 && tid == 0) {
-                    // one partial per tile and slice: the waves' sums in a fixed order
-                    // (the next write to this buffer half comes two barriers later)
-                    double sb = 0.0, s0 = 0.0, ss = 0.0;
+                if (zo >= 0 && tid < 3) {
+                    // one partial per tile and slice: the waves' sums in a fixed order,
+                    // one quantity per lane (the next write to this buffer half comes
+                    // two barriers later)
+                    double v = 0.0;
 #pragma unroll
-                    for (int w = 0; w < kSmoothWaves; ++w) {
-                        sb += red_s[zo & 1][w][0];
-                        s0 += red_s[zo & 1][w][1];
-                        ss += red_s[zo & 1][w][2];
-                    }
+                    for (int w = 0; w < kSmoothWaves; ++w) v += red_s[zo & 1][w][tid];
                     const long long pi = (long long)zo * nparts + tile;
-                    a.part_bb[pi] = sb;
-                    a.part_b0[pi] = s0;
-                    a.part_bs[pi] = ss;
+                    double *dst = tid == 0 ? a.part_bb : (tid == 1 ? a.part_b0 : a.part_bs);
+                    dst[pi] = v;
                 }
             }
         }
