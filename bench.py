@@ -290,7 +290,7 @@ def main():
     torch.cuda.synchronize()
     gdf.profile_enable(False)
     breakdown = {}
-    for cls in ("smooth", "restrict_first", "vcycle_fine", "coarse", "finalize"):
+    for cls in ("smooth", "restrict_first", "vcycle_fine_first", "vcycle_fine", "coarse", "finalize"):
         n, m, b = gdf.profile_read(cls)
         breakdown[cls] = {"launches_per_step": n / nb, "ms_per_step": m / nb,
                           "algo_GBps": (b / (m * 1e-3) / 1e9) if m > 0 else None}

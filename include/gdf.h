@@ -225,8 +225,10 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
  * accumulates their durations.  gdf_profile_enable(1) times every class,
  * gdf_profile_enable(2) only "vcycle_fine" (fewer events in flight),
  * gdf_profile_enable(0) stops.  Classes: "smooth", "vcycle_fine" (the fused
- * finest-level post-/pre-smoothing pass), "restrict_first", "coarse",
- * "finalize", "prep", "refine", "adjoint".  Returns the number of launches
+ * finest-level post-/pre-smoothing pass), "vcycle_fine_first" (the same pass
+ * in the first cycle of a solve from zero, which reads no iterate),
+ * "restrict_first", "coarse", "finalize", "prep", "refine", "adjoint".
+ * Returns the number of launches
  * recorded and writes the summed milliseconds and the summed algorithmic
  * HBM bytes.                                                                 */
 void gdf_profile_enable(int on);

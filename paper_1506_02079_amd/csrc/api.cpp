@@ -185,9 +185,10 @@ struct List {
     std::vector<std::pair<int, double>> slice_px;   // (slice, pixels at this level)
 };
 
-enum ProfClass { PC_SMOOTH, PC_FINE, PC_FIRST, PC_COARSE, PC_FINALIZE, PC_PREP, PC_REFINE, PC_ADJOINT, PC_COUNT };
-const char *kProfNames[PC_COUNT] = {"smooth", "vcycle_fine", "restrict_first", "coarse",
-                                    "finalize", "prep", "refine", "adjoint"};
+enum ProfClass { PC_SMOOTH, PC_FINE, PC_FIRST, PC_COARSE, PC_FINALIZE, PC_PREP, PC_REFINE, PC_ADJOINT, PC_FINE0,
+                 PC_COUNT };
+const char *kProfNames[PC_COUNT] = {"smooth", "vcycle_fine", "restrict_first", "coarse", "finalize",
+                                    "prep", "refine", "adjoint", "vcycle_fine_first"};
 
 struct Plan {
     Opts o;
@@ -770,8 +771,8 @@ struct Run {
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
         // read u (unless zero) and b, write u; read the coarse correction and
         // write the coarse right-hand side (a quarter per pixel each)
-        if ((r = strip(P.list_fine, zero ? SK_FINE_ZERO : SK_FINE, (k - 1) & 1, k & 1, partf, fp64, PC_FINE,
-                       (zero ? 2 : 3) * e + 0.5 * ce, slice_par)))
+        if ((r = strip(P.list_fine, zero ? SK_FINE_ZERO : SK_FINE, (k - 1) & 1, k & 1, partf, fp64,
+                       zero ? PC_FINE0 : PC_FINE, (zero ? 2 : 3) * e + 0.5 * ce, slice_par)))
             return r;
         if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e, slice_par))) return r;
         return GDF_OK;
