@@ -209,6 +209,7 @@ def main():
     # (--autotune runs the tuner instead, inside the untimed warm-up)
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--fine-sweeps", type=int, default=5)
+    ap.add_argument("--coarse-sweeps", type=int, default=3)
     ap.add_argument("--tile-rows", type=int, default=128)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, mixed-precision and adjoint measurements")
@@ -238,7 +239,8 @@ def main():
     st = torch.from_numpy(stack).to(dev)
     kw = dict(tol=TOL, precision="fp32", launch_mode=args.launch, autotune=args.autotune)
     if not args.autotune:
-        kw.update(nu=args.nu, fine_sweeps=args.fine_sweeps, tile_rows=args.tile_rows)
+        kw.update(nu=args.nu, fine_sweeps=args.fine_sweeps, coarse_sweeps=args.coarse_sweeps,
+                  tile_rows=args.tile_rows)
 
     log("warmup" + (" (autotuning on the first call)" if args.autotune else ""))
     t0 = time.perf_counter()
@@ -320,7 +322,8 @@ def main():
         "worst_rel_residual": worst,
         "vcycles": cycles,
         "settings": ({"autotuned": tuned} if args.autotune else
-                     {"nu": args.nu, "fine_sweeps": args.fine_sweeps, "tile_rows": args.tile_rows,
+                     {"nu": args.nu, "fine_sweeps": args.fine_sweeps, "coarse_sweeps": args.coarse_sweeps,
+                      "tile_rows": args.tile_rows,
                       "launch_mode": args.launch}),
         "warmup_s": t_warm,
         "breakdown": breakdown,

@@ -82,20 +82,25 @@ typedef struct {
     int precision;     /* gdf_precision (default GDF_PREC_FP32) */
     int max_vcycles;   /* cap on V-cycles per slice (default 40; for MIXED: total inner cycles) */
     int nu;            /* red-black Gauss-Seidel sweeps before and after each coarse
-                          correction: 1 or 2 (default 2) */
+                          correction on the finest level: 1 or 2 (default 2) */
     int out_dtype;     /* GDF_F32 or GDF_F64 for f; 0 = F32 for FP32, F64 otherwise */
     int use_graph;     /* 1: record the whole V-cycle schedule once as a hipGraph and
                           replay it, with per-slice convergence flags on the device */
     int tile_rows;     /* rows per strip work item (even, >= 16); 0 = tuned default */
     int inner_cycles;  /* MIXED: FP32 V-cycles per refinement step (default 3) */
     int launch_mode;   /* gdf_launch_mode for the multigrid passes (default GDF_LAUNCH_GRID) */
-    int autotune;      /* 1: pick nu, fine_sweeps, tile_rows and launch_mode by timing
+    int autotune;      /* 1: pick nu, fine_sweeps, coarse_sweeps, tile_rows and launch_mode by timing
                           candidate solves of this very call (see "Autotuning" below) */
     int fine_sweeps;   /* red-black sweeps in each fused finest-level pass (the post-sweeps
                           of one cycle plus the pre-sweeps of the next): 2 nu .. 2 nu + 2;
                           0 = 2 nu.  Extra sweeps lower the residual at each check and can
                           save a whole V-cycle. */
-    int reserved[6];
+    int coarse_sweeps; /* red-black sweeps before and after each coarse correction on the
+                          coarse levels: 1 .. 3; 0 = nu + 1 (nu for GDF_PREC_MIXED, whose
+                          inner solves run a fixed number of cycles).  The coarse levels are
+                          small and latency-bound, so a third sweep there costs little and
+                          lowers the residual of every cycle. */
+    int reserved[5];
 } gdf_solve_opts;
 
 typedef enum {
@@ -207,8 +212,8 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *desc_host, int dty
  * returns.  Tuned, in this order, each among the values left at 0 by the
  * caller: nu (2, 1: sweeps per smoothing step), fine_sweeps (2 nu, 2 nu + 1,
  * 2 nu + 2: how many red-black sweeps the fused finest pass applies per pass
- * over HBM), tile_rows (heuristic, 32, 64, 128, 256 rows per work item) and
- * launch_mode (grid, persistent).  The choice is cached per
+ * over HBM), coarse_sweeps (nu + 1, nu), tile_rows (heuristic, 32, 64, 128,
+ * 256 rows per work item) and launch_mode (grid, persistent).  The choice is cached per
  * batch signature (entry point, sizes, alphas, tol, precision, dtypes, fixed
  * options) until gdf_release.  The workspace size functions return the
  * largest size over the candidates when opts.autotune = 1.  Candidate runs

@@ -38,7 +38,8 @@ class SolveOpts(ctypes.Structure):
                 ("out_dtype", ctypes.c_int), ("use_graph", ctypes.c_int),
                 ("tile_rows", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("launch_mode", ctypes.c_int), ("autotune", ctypes.c_int),
-                ("fine_sweeps", ctypes.c_int), ("reserved", ctypes.c_int * 6)]
+                ("fine_sweeps", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class SliceReport(ctypes.Structure):
@@ -102,7 +103,8 @@ def version() -> str:
 
 
 def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=False,
-              tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0) -> SolveOpts:
+              tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0,
+              coarse_sweeps=0) -> SolveOpts:
     o = SolveOpts()
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.max_vcycles = int(max_vcycles)
@@ -114,16 +116,18 @@ def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=F
     o.launch_mode = LAUNCH[launch_mode] if isinstance(launch_mode, str) else int(launch_mode)
     o.autotune = int(bool(autotune))
     o.fine_sweeps = int(fine_sweeps)
+    o.coarse_sweeps = int(coarse_sweeps)
     return o
 
 
 def autotune_last():
     """Settings chosen by the last autotuned call on this thread, or None:
-    dict(nu, fine_sweeps, tile_rows, launch_mode)."""
+    dict(nu, fine_sweeps, coarse_sweeps, tile_rows, launch_mode)."""
     o = SolveOpts()
     if not lib().gdf_autotune_last(ctypes.byref(o)):
         return None
-    return dict(nu=o.nu, fine_sweeps=o.fine_sweeps, tile_rows=o.tile_rows, launch_mode=o.launch_mode)
+    return dict(nu=o.nu, fine_sweeps=o.fine_sweeps, coarse_sweeps=o.coarse_sweeps, tile_rows=o.tile_rows,
+                launch_mode=o.launch_mode)
 
 
 def _check(status, allow_noconv=False):
@@ -173,7 +177,7 @@ def _require_cuda(*ts):
 
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
-               tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0,
+               tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
                allow_noconv=False):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
 
@@ -188,7 +192,7 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
         stack = stack.contiguous()
     S, H, W = stack.shape
     o = make_opts(precision, max_vcycles, nu, out_dtype, False, tile_rows, inner_cycles,
-                  launch_mode, autotune, fine_sweeps)
+                  launch_mode, autotune, fine_sweeps, coarse_sweeps)
     L = lib()
     ws = L.gdf_fuse_workspace_size(S, H, W, ctypes.byref(o))
     if ws == 0:
@@ -238,7 +242,7 @@ def _descs(gs_list, go_list, f_list, alphas):
 
 def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_dtype=None,
                  nu=0, max_vcycles=0, use_graph=False, tile_rows=0, inner_cycles=0,
-                 launch_mode=0, autotune=False, fine_sweeps=0, allow_noconv=False):
+                 launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False):
     """Eq. (1) per slice.  g_s, g_o: [S, H, W] tensors or lists of 2D tensors
     (uneven batch).  alpha: scalar or per-slice sequence.  Returns (f, report)
     with f shaped like the input (a list for list input)."""
@@ -260,7 +264,7 @@ def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_
         raise ValueError("all g_s slices (and all g_o slices) must share a dtype")
     alphas = [float(alpha)] * n if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
     o = make_opts(precision, max_vcycles, nu, out_dtype, use_graph, tile_rows, inner_cycles,
-                  launch_mode, autotune, fine_sweeps)
+                  launch_mode, autotune, fine_sweeps, coarse_sweeps)
     od = o.out_dtype or (DTYPE_F32 if o.precision == 0 else DTYPE_F64)
     fdt = torch.float64 if od == DTYPE_F64 else torch.float32
     dev = gs_list[0].device
@@ -305,7 +309,7 @@ def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_
 
 def solve_slices_backward(grad_f, f, g_s, alpha, bc="neumann", tol=1e-6, precision=None, nu=0,
                           max_vcycles=0, need=(True, True, True), tile_rows=0, launch_mode=0,
-                          autotune=False, fine_sweeps=0, allow_noconv=False):
+                          autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False):
     """Adjoint of Eq. (1): returns (dL/dg_s, dL/dg_o, dL/dalpha per slice, report)
     for grad_f = dL/df.  Tensors are [S, H, W] of one float dtype."""
     torch = _torch()
@@ -324,7 +328,8 @@ def solve_slices_backward(grad_f, f, g_s, alpha, bc="neumann", tol=1e-6, precisi
         d[i].H, d[i].W, d[i].alpha = H, W, alphas[i]
         d[i].off_gs = d[i].off_go = d[i].off_f = i * H * W
         d[i].pitch_gs = d[i].pitch_go = d[i].pitch_f = W
-    o = make_opts(prec, max_vcycles, nu, None, False, tile_rows, 0, launch_mode, autotune, fine_sweeps)
+    o = make_opts(prec, max_vcycles, nu, None, False, tile_rows, 0, launch_mode, autotune, fine_sweeps,
+                  coarse_sweeps)
     L = lib()
     ws = L.gdf_backward_workspace_size(S, d, ctypes.byref(o))
     if ws == 0:

@@ -78,6 +78,7 @@ template <typename T> void key_push(std::vector<unsigned long long> &k, const T 
 struct Opts {
     int prec, max_vc, nu, out_dtype, use_graph, tile_rows, inner, launch, autotune;
     int fsw;   // sweeps of the fused finest pass
+    int csw;   // sweeps per smoothing step on the coarse levels
 };
 
 gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
@@ -113,6 +114,12 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
     r.fsw = o->fine_sweeps ? o->fine_sweeps : 2 * r.nu;
     if (r.fsw < 2 * r.nu || r.fsw > 2 * r.nu + 2)
         return set_err(GDF_EINVAL, "opts.fine_sweeps must be 0 or in [2 nu, 2 nu + 2] (got %d)", o->fine_sweeps);
+    // default: one sweep more than nu on the coarse levels, where it buys whole
+    // cycles; the inner solves of the mixed scheme run a fixed cycle count, so
+    // there the extra sweep only costs
+    r.csw = o->coarse_sweeps ? o->coarse_sweeps : (r.prec == GDF_PREC_MIXED ? r.nu : r.nu + 1);
+    if (r.csw < 1 || r.csw > 3)
+        return set_err(GDF_EINVAL, "opts.coarse_sweeps must be 0 or in [1, 3] (got %d)", o->coarse_sweeps);
     return GDF_OK;
 }
 
@@ -227,7 +234,7 @@ struct Plan {
 int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripKind kind, int G, int VW)
 {
     if (level == 0 && P.o.tile_rows) return P.o.tile_rows;
-    int slots = strip_resident_waves(kind, P.o.nu, P.o.fsw, P.fp64);
+    int slots = strip_resident_waves(kind, P.o.csw, P.o.fsw, P.fp64);
     if (slots <= 0) slots = 4096;
     const int E = (G + 2) & ~1;
     int th = 128;
@@ -250,7 +257,7 @@ int add_list(Plan &P, StripKind kind, int level, const std::vector<int> &slices)
     List L;
     L.kind = kind;
     L.level = level;
-    L.G = strip_halo(kind, P.o.nu, P.o.fsw);
+    L.G = strip_halo(kind, P.o.csw, P.o.fsw);
     L.VW = kStripCols - 2 * L.G;
     L.TH = choose_rows(P, slices, level, kind, L.G, L.VW);
     // the rows an item touches must span less than 2^31 bytes (the kernel
@@ -534,7 +541,7 @@ gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vecto
                        bool need_gs)
 {
     std::vector<unsigned long long> key;
-    for (int v : {n, smooth_S, need_gs ? 1 : 0, o.prec, o.max_vc, o.nu, o.out_dtype, o.use_graph, o.tile_rows,
+    for (int v : {n, smooth_S, need_gs ? 1 : 0, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype, o.use_graph, o.tile_rows,
                   o.inner, o.launch, o.fsw})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
@@ -718,7 +725,7 @@ struct Run {
         a.n_items = L.count;
         a.n_fast = L.n_fast;
         a.n_rows_in = L.n_rows_in;
-        HIP_TRY(launch_strip(kind, P.o.nu, P.o.fsw, fp64, P.o.launch == GDF_LAUNCH_PERSISTENT, a, s));
+        HIP_TRY(launch_strip(kind, P.o.csw, P.o.fsw, fp64, P.o.launch == GDF_LAUNCH_PERSISTENT, a, s));
         return GDF_OK;
     }
 
@@ -1047,7 +1054,7 @@ gdf_status solve_body(Run &R, const SolveIO &x)
 // cached per batch signature (sizes, screening weights, tolerances, precision
 // and dtypes; not the data or the pointers) until gdf_release.
 
-struct Tuned { int nu, fine_sweeps, tile_rows, launch; };
+struct Tuned { int nu, fine_sweeps, coarse_sweeps, tile_rows, launch; };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::vector<unsigned long long>, Tuned>> g_tuned;
 thread_local gdf_solve_opts g_last_tuned;
@@ -1060,6 +1067,10 @@ std::vector<int> tune_nus(const gdf_solve_opts &b)
 std::vector<int> tune_fine_sweeps(const gdf_solve_opts &b, int nu)
 {
     return b.fine_sweeps ? std::vector<int>{b.fine_sweeps} : std::vector<int>{0, 2 * nu + 1, 2 * nu + 2};
+}
+std::vector<int> tune_coarse_sweeps(const gdf_solve_opts &b, int nu)
+{
+    return b.coarse_sweeps ? std::vector<int>{b.coarse_sweeps} : std::vector<int>{0, nu};
 }
 std::vector<int> tune_tiles(const gdf_solve_opts &b)
 {
@@ -1094,16 +1105,18 @@ size_t tuned_workspace(const std::vector<unsigned long long> &key, const gdf_sol
     size_t m = 0;
     for (int nu : tune_nus(base))
         for (int fs : tune_fine_sweeps(base, nu))
-            for (int tr : tune_tiles(base)) {
-                gdf_solve_opts c = base;
-                c.autotune = 0;
-                c.nu = nu;
-                c.fine_sweeps = fs;
-                c.tile_rows = tr;
-                const size_t b = size_of(&c);
-                if (b == 0) return 0;
-                m = std::max(m, b);
-            }
+            for (int cs : tune_coarse_sweeps(base, nu))
+                for (int tr : tune_tiles(base)) {
+                    gdf_solve_opts c = base;
+                    c.autotune = 0;
+                    c.nu = nu;
+                    c.fine_sweeps = fs;
+                    c.coarse_sweeps = cs;
+                    c.tile_rows = tr;
+                    const size_t b = size_of(&c);
+                    if (b == 0) return 0;
+                    m = std::max(m, b);
+                }
     std::lock_guard<std::mutex> lk(g_wsz_mu);
     if (g_wsz.size() >= 64) g_wsz.erase(g_wsz.begin());
     g_wsz.emplace_back(key, m);
@@ -1115,7 +1128,7 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
 {
     gdf_solve_opts best = base;
     best.autotune = 0;
-    Tuned t{0, 0, 0, 0};
+    Tuned t{0, 0, 0, 0, 0};
     bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1138,6 +1151,7 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
         gdf_solve_opts cur = best;
         cur.nu = nus[0];
         cur.fine_sweeps = base.fine_sweeps;
+        cur.coarse_sweeps = base.coarse_sweeps;
         cur.tile_rows = tiles[0];
         cur.launch_mode = ls[0];
         double tcur = timeit(cur);
@@ -1151,16 +1165,18 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
         };
         try_field(&gdf_solve_opts::nu, nus);
         try_field(&gdf_solve_opts::fine_sweeps, tune_fine_sweeps(base, cur.nu));
+        try_field(&gdf_solve_opts::coarse_sweeps, tune_coarse_sweeps(base, cur.nu));
         try_field(&gdf_solve_opts::tile_rows, tiles);
         try_field(&gdf_solve_opts::launch_mode, ls);
         if (!(tcur < inf)) return call(&best);   // no candidate ran cleanly: report the plain call
-        t = Tuned{cur.nu, cur.fine_sweeps, cur.tile_rows, cur.launch_mode};
+        t = Tuned{cur.nu, cur.fine_sweeps, cur.coarse_sweeps, cur.tile_rows, cur.launch_mode};
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tuned.size() >= 64) g_tuned.erase(g_tuned.begin());
         g_tuned.emplace_back(key, t);
     }
     best.nu = t.nu;
     best.fine_sweeps = t.fine_sweeps;
+    best.coarse_sweeps = t.coarse_sweeps;
     best.tile_rows = t.tile_rows;
     best.launch_mode = t.launch;
     g_last_tuned = best;
@@ -1306,7 +1322,7 @@ size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
     if (b.autotune != 1) return fuse_workspace_plain(S, H, W, opts);
     std::vector<unsigned long long> key;
     key_push(key, 0);
-    for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows,
+    for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
                   b.launch_mode})
         key_push(key, v);
     return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
@@ -1332,7 +1348,7 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
         return r;
     std::vector<unsigned long long> key;
     key_push(key, 0);
-    for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps,
+    for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps,
                   b.tile_rows, b.launch_mode, g_smooth ? 1 : 0})
         key_push(key, v);
     for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
@@ -1517,7 +1533,7 @@ size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_
     if (n < 1 || !d) return 0;
     std::vector<unsigned long long> key;
     key_push(key, 1);
-    for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows,
+    for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
                   b.launch_mode})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
@@ -1558,6 +1574,7 @@ static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const v
     m.max_vcycles = mo.max_vc;
     m.nu = mo.nu;
     m.fine_sweeps = mo.fsw;
+    m.coarse_sweeps = mo.csw;
     m.out_dtype = mo.out_dtype;
     m.tile_rows = mo.tile_rows;
     m.inner_cycles = mo.inner;
@@ -1626,7 +1643,7 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
     std::vector<unsigned long long> key;
     key_push(key, 1);
     for (int v : {n, bc, gs_dtype, go_dtype, b.precision, b.max_vcycles, b.out_dtype, b.use_graph,
-                  b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows, b.launch_mode})
+                  b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {
@@ -1696,6 +1713,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         key_push(key, o.prec);
         key_push(key, o.max_vc);
         key_push(key, o.nu);
+        key_push(key, o.csw);
         key_push(key, o.out_dtype);
         key_push(key, o.tile_rows);
         key_push(key, o.inner);
@@ -1714,7 +1732,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         }
         hipGraphExec_t ex = graph_lookup(key);
         if (!ex) {
-            if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.nu, o.fsw, P.fp64);
+            if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.csw, o.fsw, P.fp64);
             R.capturing = true;
             HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             gdf_status q = body();
@@ -1765,7 +1783,7 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
     std::vector<unsigned long long> key;
     key_push(key, 2);
-    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.tile_rows, b.launch_mode})
+    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {

@@ -133,9 +133,9 @@ struct StripLaunch {
 // Strip kernel variants (template instances live in mg_kernels.hip).
 enum StripKind {
     SK_FIRST_RESTRICT,  // finest, first pass of a solve from zero: restrict b (no sweeps)
-    SK_FINE,         // prolongate, 4nu sweeps, residual -> norm + restrict (finest, fused up+down)
-    SK_DOWN,         // zero start, 2nu sweeps, restrict (coarse levels, down leg)
-    SK_UP,           // prolongate, 2nu sweeps (coarse levels, up leg)
+    SK_FINE,         // prolongate, fsw sweeps, residual -> norm + restrict (finest, fused up+down)
+    SK_DOWN,         // zero start, csw sweeps, restrict (coarse levels, down leg)
+    SK_UP,           // prolongate, csw sweeps (coarse levels, up leg)
     SK_COARSE_ZERO,  // zero start, 2 sweeps (coarsest level)
     SK_COARSE,       // 2 sweeps (coarsest level)
     SK_SINGLE_ZERO,  // zero start, 2 sweeps, residual -> norm (single-level slices)
@@ -146,27 +146,27 @@ enum StripKind {
 
 // Halo (G) of a strip kind: stages after the load, plus one for prolongation,
 // rounded up to even.  Valid output width per strip is 128 - 2G.
-int strip_halo(StripKind k, int nu, int fsw);
+int strip_halo(StripKind k, int csw, int fsw);
 
 // Enqueue one strip pass (one launch).  Items [0, a.n_fast) stay clear of
 // the slice's edges (rows y0 - G .. y1 + G in [1, H - 2], columns x0 - G ..
 // x0 - G + 127 in [1, W - 2]) and run the code without row guards and edge
 // masks; items [a.n_fast, a.n_rows_in) have such rows but touch a column edge
-// (no row guards, per-lane masks); the others run the guarded code.  nu: sweeps per smoothing step of
-// the coarse passes and the first pass; fsw: sweeps of the fused finest pass
+// (no row guards, per-lane masks); the others run the guarded code.  csw: sweeps per smoothing step of
+// the coarse passes; fsw: sweeps of the fused finest pass
 // (SK_FINE).  fp64 selects double precision.  persistent: the grid is capped
 // at the workgroups resident on the device at once and each wave loops over
 // the list's items; otherwise one wave per item.
-hipError_t launch_strip(StripKind k, int nu, int fsw, bool fp64, bool persistent, const StripLaunch &a,
+hipError_t launch_strip(StripKind k, int csw, int fsw, bool fp64, bool persistent, const StripLaunch &a,
                         hipStream_t s);
 
 // Waves of a strip kernel variant that the device holds at once (occupancy x
 // SIMDs); 0 if the runtime cannot tell (no device).
-int strip_resident_waves(StripKind k, int nu, int fsw, bool fp64);
+int strip_resident_waves(StripKind k, int csw, int fsw, bool fp64);
 
 // Resolves the persistent grid sizes of every strip kernel variant for nu,
 // fsw and the precision (device queries; call before a stream capture begins).
-void strip_prepare(int nu, int fsw, bool fp64);
+void strip_prepare(int csw, int fsw, bool fp64);
 
 // ---- per-slice reductions and flags ------------------------------------
 

@@ -656,14 +656,14 @@ template <bool PROLONG, int RMODE> static int halo_by_sweeps(int sw)
     }
 }
 
-int strip_halo(StripKind k, int nu, int fsw)
+int strip_halo(StripKind k, int csw, int fsw)
 {
     switch (k) {
     case SK_FIRST_RESTRICT: return StripShape<false, 0, RES_RESTRICT>::G;
     case SK_FINE_ZERO:
     case SK_FINE: return halo_by_sweeps<true, RES_BOTH>(fsw);
-    case SK_DOWN: return halo_by_sweeps<false, RES_RESTRICT>(nu);
-    case SK_UP: return halo_by_sweeps<true, RES_NONE>(nu);
+    case SK_DOWN: return halo_by_sweeps<false, RES_RESTRICT>(csw);
+    case SK_UP: return halo_by_sweeps<true, RES_NONE>(csw);
     case SK_COARSE_ZERO:
     case SK_COARSE: return StripShape<false, 4, RES_NONE>::G;
     case SK_SINGLE_ZERO:
@@ -727,10 +727,9 @@ static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s, int *
 }
 
 template <typename T>
-static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const StripLaunch &a, hipStream_t s,
+static hipError_t launch_strip_t(StripKind k, int csw, int fsw, bool p, const StripLaunch &a, hipStream_t s,
                                  int *w = nullptr)
 {
-    const bool n1 = nu == 1;
     switch (k) {
     case SK_FINE:
         switch (fsw) {
@@ -742,10 +741,19 @@ static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const Str
         default: return hipErrorInvalidValue;
         }
     case SK_DOWN:
-        return n1 ? go<T, false, true, 2, RES_RESTRICT, true>(a, p, s, w)
-                  : go<T, false, true, 4, RES_RESTRICT, true>(a, p, s, w);
+        switch (csw) {
+        case 1: return go<T, false, true, 2, RES_RESTRICT, true>(a, p, s, w);
+        case 2: return go<T, false, true, 4, RES_RESTRICT, true>(a, p, s, w);
+        case 3: return go<T, false, true, 6, RES_RESTRICT, true>(a, p, s, w);
+        default: return hipErrorInvalidValue;
+        }
     case SK_UP:
-        return n1 ? go<T, true, false, 2, RES_NONE, true>(a, p, s, w) : go<T, true, false, 4, RES_NONE, true>(a, p, s, w);
+        switch (csw) {
+        case 1: return go<T, true, false, 2, RES_NONE, true>(a, p, s, w);
+        case 2: return go<T, true, false, 4, RES_NONE, true>(a, p, s, w);
+        case 3: return go<T, true, false, 6, RES_NONE, true>(a, p, s, w);
+        default: return hipErrorInvalidValue;
+        }
     case SK_COARSE_ZERO: return go<T, false, true, 4, RES_NONE, true>(a, p, s, w);
     case SK_COARSE: return go<T, false, false, 4, RES_NONE, true>(a, p, s, w);
     case SK_SINGLE_ZERO: return go<T, false, true, 4, RES_NORM>(a, p, s, w);
@@ -764,30 +772,30 @@ static hipError_t launch_strip_t(StripKind k, int nu, int fsw, bool p, const Str
     }
 }
 
-int strip_resident_waves(StripKind k, int nu, int fsw, bool fp64)
+int strip_resident_waves(StripKind k, int csw, int fsw, bool fp64)
 {
     StripLaunch a{};
     a.n_items = -1;
     int w = 0;
-    const hipError_t e = fp64 ? launch_strip_t<double>(k, nu, fsw, true, a, nullptr, &w)
-                              : launch_strip_t<float>(k, nu, fsw, true, a, nullptr, &w);
+    const hipError_t e = fp64 ? launch_strip_t<double>(k, csw, fsw, true, a, nullptr, &w)
+                              : launch_strip_t<float>(k, csw, fsw, true, a, nullptr, &w);
     return e == hipSuccess ? w : 0;
 }
 
-void strip_prepare(int nu, int fsw, bool fp64)
+void strip_prepare(int csw, int fsw, bool fp64)
 {
     StripLaunch a{};
     a.n_items = -1;
     for (int k = 0; k < SK_COUNT; ++k)
-        (void)(fp64 ? launch_strip_t<double>((StripKind)k, nu, fsw, true, a, nullptr)
-                    : launch_strip_t<float>((StripKind)k, nu, fsw, true, a, nullptr));
+        (void)(fp64 ? launch_strip_t<double>((StripKind)k, csw, fsw, true, a, nullptr)
+                    : launch_strip_t<float>((StripKind)k, csw, fsw, true, a, nullptr));
 }
 
-hipError_t launch_strip(StripKind k, int nu, int fsw, bool fp64, bool persistent, const StripLaunch &a,
+hipError_t launch_strip(StripKind k, int csw, int fsw, bool fp64, bool persistent, const StripLaunch &a,
                         hipStream_t s)
 {
-    return fp64 ? launch_strip_t<double>(k, nu, fsw, persistent, a, s)
-                : launch_strip_t<float>(k, nu, fsw, persistent, a, s);
+    return fp64 ? launch_strip_t<double>(k, csw, fsw, persistent, a, s)
+                : launch_strip_t<float>(k, csw, fsw, persistent, a, s);
 }
 
 }  // namespace gdf

@@ -64,6 +64,8 @@ def _fuse(**kw):
     (dict(opts=gdf.make_opts(nu=2, fine_sweeps=3)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(nu=2, fine_sweeps=7)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(nu=1, fine_sweeps=5)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(coarse_sweeps=4)), gdf.GDF_EINVAL),
+    (dict(opts=gdf.make_opts(coarse_sweeps=-1)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),
     (dict(wsb=16), gdf.GDF_ENOMEM),

@@ -205,6 +205,7 @@ def test_autotuned_uneven_batch_graph():
     print("tuned", t, flush=True)
     assert t["nu"] in (1, 2) and t["tile_rows"] in (0, 32, 64, 128, 256) and t["launch_mode"] in (1, 2)
     assert t["fine_sweeps"] in (0, 2 * t["nu"] + 1, 2 * t["nu"] + 2)
+    assert t["coarse_sweeps"] in (0, t["nu"])
     assert all(r["rel_residual"] <= 1e-6 and r["status"] == gdf.GDF_OK for r in rep1)
     # cached choice: the same settings given explicitly reproduce the result
     f2, rep2 = gdf.solve_slices(tg, to, al, tol=1e-6, use_graph=True, **t)
@@ -256,6 +257,23 @@ def test_output_pass_row_and_quad_agree():
         o, s = pairs[i]
         fr = oracle.solve(s, o.astype(np.float64), al[i], tol=1e-11)
         assert np.abs(f1[i].cpu().numpy() - fr).max() <= 1e-3
+
+
+@pytest.mark.parametrize("coarse_sweeps", [1, 2, 3])
+def test_coarse_sweep_counts(coarse_sweeps):
+    # sweeps on the coarse levels: same solution; three take no more cycles than two
+    stack = synth.make_stack(4, 300, 412, seed=63, ramp=True)
+    st = torch.from_numpy(stack).to(DEV)
+    f2, r2 = gdf.fuse_stack(st, 0.003, tol=1e-6, coarse_sweeps=2)
+    f1, r1, gsm = gdf.fuse_stack(st, 0.003, tol=1e-6, coarse_sweeps=coarse_sweeps, return_smooth=True)
+    print(coarse_sweeps, [r["vcycles"] for r in r2], [r["vcycles"] for r in r1], flush=True)
+    assert all(r["rel_residual"] <= 1e-6 and r["status"] == gdf.GDF_OK for r in r1)
+    if coarse_sweeps == 3:
+        assert sum(r["vcycles"] for r in r1) <= sum(r["vcycles"] for r in r2)
+    g = gsm.cpu().numpy().astype(np.float64)
+    for j in (0, 3):
+        fr = oracle.solve(g[j], stack[j].astype(np.float64), 0.003, tol=1e-11)
+        assert np.abs(f1[j].cpu().numpy() - fr).max() <= 1e-3
 
 
 @pytest.mark.parametrize("nu,fine_sweeps", [(2, 5), (2, 6), (1, 3), (1, 4)])
