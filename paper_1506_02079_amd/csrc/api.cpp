@@ -438,7 +438,8 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.n_partd = tb;
     if (smooth_S > 0) {
         // smoothing partials: [S][tiles]
-        const long long nparts = (long long)((W[0] + 63) / 64) * ((H[0] + 15) / 16);   // one per tile
+        const long long nparts = (long long)((W[0] + kSmoothTileW - 1) / kSmoothTileW) *
+                                 ((H[0] + kSmoothTileH - 1) / kSmoothTileH);   // one per tile
         P.ranges_smooth.resize(2 * n);
         for (int s = 0; s < n; ++s) {
             P.ranges_smooth[2 * s] = (int)(s * nparts);
@@ -1432,8 +1433,8 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     a.part_bb = R.partd;
     a.part_b0 = R.partd2;
     a.part_bs = R.partd3;
-    a.tiles_x = (W + 63) / 64;
-    a.tiles_y = (H + 15) / 16;
+    a.tiles_x = (W + kSmoothTileW - 1) / kSmoothTileW;
+    a.tiles_y = (H + kSmoothTileH - 1) / kSmoothTileH;
     {
         ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0)), s, false);
         HIP_TRY(launch_smooth(P.fp64, a, s));

@@ -302,6 +302,12 @@ hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *
 // ---- smoothing ------------------------------------------------------------
 
 constexpr int kSmoothWaves = 8;   // waves per smoothing workgroup (one partial-sum slot each)
+#ifndef GDF_SMOOTH_TILE_H
+#define GDF_SMOOTH_TILE_H 24
+#endif
+// smoothing tile: one workgroup per kSmoothTileW x kSmoothTileH tile of every slice
+constexpr int kSmoothTileW = 64, kSmoothTileH = GDF_SMOOTH_TILE_H;
+static_assert(kSmoothTileH % kSmoothWaves == 0, "whole rows per thread");
 
 struct SmoothArgs {
     const uint8_t *stack;

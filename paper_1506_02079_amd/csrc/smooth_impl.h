@@ -5,10 +5,11 @@
 // renormalised 3D sum factors into three 1D passes, each divided by its own
 // in-range weight sum.
 //
-// One workgroup owns a 64 x 16 tile of every slice and marches through the
-// stack.  While it blurs slice z along x and y, the raw tile of slice z + 1
-// (with an in-plane halo) is already in flight as 4-byte loads held in
-// registers; the raw tiles of the slices between the current output and input
+// One workgroup of 8 waves owns a 64 x 24 tile of every slice (three rows per
+// thread) and marches through the stack.  While it blurs slice z along x and
+// y, the raw tile of slice z + 1 (with an in-plane halo) is already in flight
+// as 4-byte loads held in registers, waited for only when it is written to
+// LDS at the end of the step; the raw tiles of the slices between the current output and input
 // slice stay in an LDS byte ring (they also give the Laplacian of the original
 // slice at output time, with no second read from HBM).  Blurred planes go into
 // a register ring of 2 rz + 1 planes; the z blur of an output slice is a
@@ -21,7 +22,7 @@
 
 namespace gdf {
 
-constexpr int kSTX = 64, kSTY = 16, kMaxRxy = 7;
+constexpr int kSTX = kSmoothTileW, kSTY = kSmoothTileH, kMaxRxy = 7;
 constexpr int kRawW = 80;                 // bytes per raw row: x in [X0 - 8, X0 + 72)
 constexpr int kRawDw = kRawW / 4;         // 20 dwords per raw row
 constexpr int kRawHMax = kSTY + 2 * kMaxRxy;
@@ -29,21 +30,26 @@ constexpr int kSThreads = 64 * kSmoothWaves;               // threads per workgr
 constexpr int kSRows = kSTY / kSmoothWaves;                 // output rows per thread
 constexpr int kPrefetch = (kRawHMax * kRawDw + kSThreads - 1) / kSThreads;   // dwords per thread
 
-// Sum over the 64 lanes of a wave with DPP (pair and quad swaps, row shifts,
-// row broadcasts); the total ends in lane 63 and is returned to every lane.
-template <int CTRL, int ROW_MASK, int BANK_MASK> __device__ __forceinline__ float dpp_add(float v)
+// Sum over the 64 lanes of a wave, returned to every lane: row sums with
+// four full-row DPP adds (pair and quad swaps, half-row and row mirrors; each
+// folds into one add), then the rows combined with the lane-swap moves
+// (16-lane rows, then 32-lane halves): after a swap of v with itself one result
+// holds the even row (lower half) and the other the odd row (upper half) of
+// every pair, so their sum is the pair's total in all its lanes.
+template <int CTRL> __device__ __forceinline__ float dpp_row(float v)
 {
-    return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float wave_sum(float v)
 {
-    v = dpp_add<0xB1, 0xF, 0xF>(v);    // quad_perm [1,0,3,2]
-    v = dpp_add<0x4E, 0xF, 0xF>(v);    // quad_perm [2,3,0,1]
-    v = dpp_add<0x114, 0xF, 0xE>(v);   // row_shr:4 into lanes 4..15 of each row
-    v = dpp_add<0x118, 0xF, 0xC>(v);   // row_shr:8 into lanes 8..15
-    v = dpp_add<0x142, 0xA, 0xF>(v);   // row_bcast:15 into rows 1 and 3
-    v = dpp_add<0x143, 0xC, 0xF>(v);   // row_bcast:31 into rows 2 and 3
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+    v += dpp_row<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_row<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_row<0x141>(v);   // row_half_mirror
+    v += dpp_row<0x140>(v);   // row_mirror
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(h[0]) + __uint_as_float(h[1]);
 }
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -66,9 +72,21 @@ __device__ __forceinline__ uint32_t load_raw_dword(const uint8_t *src, long long
     return v;
 }
 
+// Whether a stack takes the fixed-offset dword loads: rows 4-byte aligned and a
+// multiple of 4 wide (every dword whole), and a raw tile window small enough
+// for 32-bit offsets.
+inline bool smooth_fast_loads(const SmoothArgs &a)
+{
+    const bool aligned = ((a.pitch_row & 3) == 0) && ((a.pitch_slice & 3) == 0) &&
+                         ((reinterpret_cast<uintptr_t>(a.stack) & 3) == 0);
+    return aligned && (a.W & 3) == 0 && a.pitch_row * kRawHMax < 0x7fffffffLL;
+}
+
 // RT: compile-time in-plane tap radius (>= the true radius; taps beyond it
-// carry zero weight), RZ: cross-slice tap radius.
-template <typename T, int RZ, int RT>
+// carry zero weight), RZ: cross-slice tap radius.  FAST: the stack takes the
+// fixed-offset dword loads (smooth_fast_loads); otherwise raw tiles are read
+// byte by byte where a dword is not whole.
+template <typename T, int RZ, int RT, bool FAST>
 __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
 {
     constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
@@ -132,12 +150,9 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     const long long nparts = (long long)a.tiles_x * a.tiles_y;   // one partial per tile
 
     uint32_t pf[kPrefetch];   // raw tile of the next input slice, in flight
-    // Each thread loads the same raw dwords of every slice: their offsets in
-    // the tile's row window are fixed per thread (kNoLane outside the slice:
-    // the load reads zero).  A stack whose rows are 4-byte aligned and a
-    // multiple of 4 wide (every dword whole) with a small enough row pitch
-    // takes that path; others read byte by byte.
-    const bool fastld = aligned && (W & 3) == 0 && a.pitch_row * kRawHMax < 0x7fffffffLL;
+    // FAST: each thread loads the same raw dwords of every slice; their offsets
+    // in the tile's row window are fixed per thread (kNoLane outside the slice:
+    // the load reads zero).
     const int gy0 = max(Y0 - RH, 0), gy1 = min(Y0 + kSTY + RH, H);   // the window's rows
     unsigned voff[kPrefetch];
 #pragma unroll
@@ -149,13 +164,17 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
         voff[q] = in ? (unsigned)((gy - gy0) * a.pitch_row + gx) : kNoLane;
     }
     auto issue = [&](int zi) {
-        if (fastld) {
-            if (zi < S) {   // uniform
-                const Rsrc rs = make_rsrc(a.stack + (long long)zi * a.pitch_slice + (long long)gy0 * a.pitch_row,
-                                          (unsigned)((gy1 - gy0) * a.pitch_row));
+        if constexpr (FAST) {
+            // unconditional: a load under a branch would be waited for where the
+            // paths join, right after its issue.  Past the stack the window is
+            // empty (the loads read zero, and the slot is never read).
+            const int zc = min(zi, S - 1);
+            // (the size goes through readfirstlane: a select the compiler places in
+            // vector registers would wrap every load in a per-lane loop)
+            const unsigned nb = (unsigned)__builtin_amdgcn_readfirstlane(zi < S ? (int)((gy1 - gy0) * a.pitch_row) : 0);
+            const Rsrc rs = make_rsrc(a.stack + (long long)zc * a.pitch_slice + (long long)gy0 * a.pitch_row, nb);
 #pragma unroll
-                for (int q = 0; q < kPrefetch; ++q) pf[q] = Buf<unsigned>::ld(rs, voff[q], 0);
-            }
+            for (int q = 0; q < kPrefetch; ++q) pf[q] = Buf<unsigned>::ld(rs, voff[q], 0);
             return;
         }
 #pragma unroll
@@ -199,6 +218,39 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     }
     const float mxl = x > 0 ? 1.f : 0.f, mxr = x < W - 1 ? 1.f : 0.f;
 
+    // One partial per tile and slice: the waves' sums of slice z in a fixed
+    // order.  They are complete after the barrier that ends slice z's output
+    // step, and reduced in the next step, after the raw tile's commit (the next
+    // write to that buffer half comes before the barrier after that).  Lane
+    // 3 s + q of wave 0 holds quantity q of slice kPB m + s; each group of kPB
+    // slices is stored at once.  (A register that held store data or address
+    // is rewritten only after a wait for the store: a store per step would
+    // stall wave 0, and with it the barrier, once per step.)
+    constexpr int kPB = 21;
+    double pbuf = 0.0;
+    const int pq = tid % 3, ps = tid / 3;
+    auto partial = [&](int z) {
+        const int zs = z % kPB;   // uniform
+        if (tid < 3 * kPB && ps == zs) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < kSmoothWaves; ++w) v += red_s[z & 1][w][pq];
+            pbuf = v;
+        }
+        if (zs == kPB - 1 || z == S - 1) {
+            if (tid < 3 * (zs + 1)) {
+                double *dst = pq == 0 ? a.part_bb : (pq == 1 ? a.part_b0 : a.part_bs);
+                dst[(long long)(z - zs + ps) * nparts + tile] = pbuf;
+            }
+        }
+    };
+    // the last step's output values stay in their registers until the next
+    // step's commit has waited for every load and store: rewritten earlier,
+    // they would need a wait for their stores right there
+    T hold[kSRows], holdg[kSRows];
+#pragma unroll
+    for (int i = 0; i < kSRows; ++i) hold[i] = holdg[i] = T(0);
+
     issue(0);
     commit(0);
     __syncthreads();
@@ -207,132 +259,145 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     // zi into hb[zi & 1]; y blur of slice zi - 1 (x-blurred in the previous
     // step) into register ring slot (zi - 1) mod NZ; z blur and output of slice
     // zo = zi - 1 - RZ; the raw tile of slice zi + 1 enters the LDS ring.
-    for (int zb = 0; zb < S + RZ + 1; zb += NZ) {
+    // (called only for zi < S + RZ + 1; k = zi mod NZ, a constant once unrolled)
+    auto step = [&](const int zi, const int k) __attribute__((always_inline)) {
+        const int islot = zi % NRAW;
+        issue(zi + 1);       // next raw tile: its latency is hidden by this step
+        // ------------- x blur of every raw row, 4 consecutive outputs per work item
+        if (zi < S) {
+            T *hbz = hb[zi & 1];
+            for (int wi = tid; wi < rawH * 16; wi += kSThreads) {
+                const int r = wi >> 4, seg = (wi & 15) * 4;
+                const uint32_t *rowp = &ring_raw[islot][r * kRawDw + (seg >> 2)];
+                T v[20];   // v[j] = pixel X0 + seg - 8 + j
 #pragma unroll
-        for (int k = 0; k < NZ; ++k) {
-            const int zi = zb + k;
-            if (zi < S + RZ + 1) {   // uniform across the block
-                const int islot = zi % NRAW;
-                issue(zi + 1);       // next raw tile: its latency is hidden by this step
-                // ------------- x blur of every raw row, 4 consecutive outputs per work item
-                if (zi < S) {
-                    T *hbz = hb[zi & 1];
-                    for (int wi = tid; wi < rawH * 16; wi += kSThreads) {
-                        const int r = wi >> 4, seg = (wi & 15) * 4;
-                        const uint32_t *rowp = &ring_raw[islot][r * kRawDw + (seg >> 2)];
-                        T v[20];   // v[j] = pixel X0 + seg - 8 + j
+                for (int q = 0; q < 5; ++q) {
+                    const uint32_t w = rowp[q];
 #pragma unroll
-                        for (int q = 0; q < 5; ++q) {
-                            const uint32_t w = rowp[q];
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) v[4 * q + i] = (T)((w >> (8 * i)) & 0xffu);
-                        }
-                        typedef T T4 __attribute__((ext_vector_type(4)));
-                        T4 out4;
-#pragma unroll
-                        for (int o = 0; o < 4; ++o) {
-                            T acc = wxy[0] * v[8 + o];
-#pragma unroll
-                            for (int d = 1; d <= RT; ++d) acc += wxy[d] * (v[8 + o - d] + v[8 + o + d]);
-                            out4[o] = acc;
-                        }
-                        // one vector store per item (strided scalar stores would conflict on banks)
-                        *reinterpret_cast<T4 *>(&hbz[r * kSTX + seg]) = out4;
-                    }
+                    for (int i = 0; i < 4; ++i) v[4 * q + i] = (T)((w >> (8 * i)) & 0xffu);
                 }
-                // ------------- y blur of slice zi - 1 into the register ring
-                const int ks = (k + NZ - 1) % NZ;   // its ring slot (static once unrolled)
-                const int zy = zi - 1;
-                if (zy >= 0 && zy < S) {
-                    const T *hby = hb[zy & 1];
-                    T col[kSRows + 2 * RT];   // col[j]: x-blurred raw row yb + RH - RT + j
+                typedef T T4 __attribute__((ext_vector_type(4)));
+                T4 out4;
 #pragma unroll
-                    for (int j = 0; j < kSRows + 2 * RT; ++j) col[j] = hby[(yb + RH - RT + j) * kSTX + tx];
+                for (int o = 0; o < 4; ++o) {
+                    T acc = wxy[0] * v[8 + o];
 #pragma unroll
-                    for (int i = 0; i < kSRows; ++i) {
-                        T acc = wxy[0] * col[i + RT];
-#pragma unroll
-                        for (int d = 1; d <= RT; ++d) acc += wxy[d] * (col[i + RT - d] + col[i + RT + d]);
-                        ring[ks][i] = acc * inv_xy[i];
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < kSRows; ++i) ring[ks][i] = T(0);
+                    for (int d = 1; d <= RT; ++d) acc += wxy[d] * (v[8 + o - d] + v[8 + o + d]);
+                    out4[o] = acc;
                 }
-                // ------------- output slice zo = zi - 1 - RZ
-                const int zo = zi - 1 - RZ;
-                if (zo >= 0) {
-                    const int zlo = min(RZ, zo), zhi = min(RZ, S - 1 - zo);   // in-stack taps
-                    T iz;
-                    if constexpr (sizeof(T) == 4) iz = a.inv_wz_f[zlo][zhi];
-                    else iz = a.inv_wz[zlo][zhi];
-                    const int oslot = zo % NRAW;
-                    // this slice's tile rows of b (and of g_s): windows of kSTY rows
-                    const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride +
-                                                   (long long)Y0 * a.b_pitch,
-                                               (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)));
-                    const Rsrc rgw = a.gs_out ? make_rsrc(static_cast<T *>(a.gs_out) + ((long long)zo * H + Y0) * W,
-                                                          (unsigned)(kSTY * W * (int)sizeof(T)))
-                                              : rbw;
-                    T sbb = T(0), sb0 = T(0), sbs = T(0);
-                    // original slice around this thread's column
-                    float oc[kSRows + 2], ol[kSRows], orr[kSRows];
-#pragma unroll
-                    for (int j = 0; j < kSRows + 2; ++j) oc[j] = raw_at(oslot, yb + RH - 1 + j, tx + 8);
-#pragma unroll
-                    for (int i = 0; i < kSRows; ++i) {
-                        ol[i] = raw_at(oslot, yb + RH + i, tx + 7);
-                        orr[i] = raw_at(oslot, yb + RH + i, tx + 9);
-                    }
-#pragma unroll
-                    for (int i = 0; i < kSRows; ++i) {
-                        // register slot of zo is k - 1 - RZ (mod NZ): static for each k
-                        T acc = wz[0] * ring[((k - 1 - RZ) % NZ + NZ) % NZ][i];
-#pragma unroll
-                        for (int d = 1; d <= RZ; ++d)
-                            acc += wz[d] * (ring[((k - 1 - RZ - d) % NZ + NZ) % NZ][i] +
-                                            ring[((k - 1 - RZ + d) % NZ + NZ) % NZ][i]);
-                        const T g = acc * iz;
-                        const float o = oc[i + 1];
-                        // (L g_o)_p over in-slice neighbours
-                        float lap = mxl * (o - ol[i]);
-                        lap = fmaf(mxr, o - orr[i], lap);
-                        lap = fmaf(myu[i], o - oc[i], lap);
-                        lap = fmaf(myd[i], o - oc[i + 2], lap);
-                        const T bu = alT * (g - (T)o);
-                        const T bf = alT * g + (T)lap;
-                        Buf<T>::st(bu, rbw, vb[i], 0);
-                        if (a.gs_out) Buf<T>::st(g, rgw, vg[i], 0);
-                        // (selects: outside the slice the values may not be finite)
-                        const T bum = oin[i] ? bu : T(0), bfm = oin[i] ? bf : T(0);
-                        sbb = fma(bfm, bfm, sbb);
-                        sb0 = fma(bum, bum, sb0);
-                        sbs += bum;
-                    }
-                    const double tbb = (double)wave_sum(sbb), tb0 = (double)wave_sum(sb0),
-                                 tbs = (double)wave_sum(sbs);
-                    if ((tid & 63) == 0) {
-                        red_s[zo & 1][wv][0] = tbb;
-                        red_s[zo & 1][wv][1] = tb0;
-                        red_s[zo & 1][wv][2] = tbs;
-                    }
-                }
-                commit(zi + 1);      // no reader of that slot in this phase
-                __syncthreads();
-                if (zo >= 0 && tid < 3) {
-                    // one partial per tile and slice: the waves' sums in a fixed order,
-                    // one quantity per lane (the next write to this buffer half comes
-                    // two barriers later)
-                    double v = 0.0;
-#pragma unroll
-                    for (int w = 0; w < kSmoothWaves; ++w) v += red_s[zo & 1][w][tid];
-                    const long long pi = (long long)zo * nparts + tile;
-                    double *dst = tid == 0 ? a.part_bb : (tid == 1 ? a.part_b0 : a.part_bs);
-                    dst[pi] = v;
-                }
+                // one vector store per item (strided scalar stores would conflict on banks)
+                *reinterpret_cast<T4 *>(&hbz[r * kSTX + seg]) = out4;
             }
         }
+        // ------------- y blur of slice zi - 1 into the register ring
+        const int ks = (k + NZ - 1) % NZ;   // its ring slot (static once unrolled)
+        const int zy = zi - 1;
+        if (zy >= 0 && zy < S) {
+            const T *hby = hb[zy & 1];
+            T col[kSRows + 2 * RT];   // col[j]: x-blurred raw row yb + RH - RT + j
+#pragma unroll
+            for (int j = 0; j < kSRows + 2 * RT; ++j) col[j] = hby[(yb + RH - RT + j) * kSTX + tx];
+#pragma unroll
+            for (int i = 0; i < kSRows; ++i) {
+                T acc = wxy[0] * col[i + RT];
+#pragma unroll
+                for (int d = 1; d <= RT; ++d) acc += wxy[d] * (col[i + RT - d] + col[i + RT + d]);
+                ring[ks][i] = acc * inv_xy[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kSRows; ++i) ring[ks][i] = T(0);
+        }
+        // ------------- output slice zo = zi - 1 - RZ
+        const int zo = zi - 1 - RZ;
+        if (zo >= 0) {
+            const int zlo = min(RZ, zo), zhi = min(RZ, S - 1 - zo);   // in-stack taps
+            T iz;
+            if constexpr (sizeof(T) == 4) iz = a.inv_wz_f[zlo][zhi];
+            else iz = a.inv_wz[zlo][zhi];
+            const int oslot = zo % NRAW;
+            // this slice's tile rows of b (and of g_s): windows of kSTY rows
+            const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride +
+                                           (long long)Y0 * a.b_pitch,
+                                       (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)));
+            const Rsrc rgw = a.gs_out ? make_rsrc(static_cast<T *>(a.gs_out) + ((long long)zo * H + Y0) * W,
+                                                  (unsigned)(kSTY * W * (int)sizeof(T)))
+                                      : rbw;
+            T sbb = T(0), sb0 = T(0), sbs = T(0);
+            // original slice around this thread's column
+            float oc[kSRows + 2], ol[kSRows], orr[kSRows];
+#pragma unroll
+            for (int j = 0; j < kSRows + 2; ++j) oc[j] = raw_at(oslot, yb + RH - 1 + j, tx + 8);
+#pragma unroll
+            for (int i = 0; i < kSRows; ++i) {
+                ol[i] = raw_at(oslot, yb + RH + i, tx + 7);
+                orr[i] = raw_at(oslot, yb + RH + i, tx + 9);
+            }
+            T bus[kSRows], gvs[kSRows];
+#pragma unroll
+            for (int i = 0; i < kSRows; ++i) {
+                // register slot of zo is k - 1 - RZ (mod NZ): static for each k
+                T acc = wz[0] * ring[((k - 1 - RZ) % NZ + NZ) % NZ][i];
+#pragma unroll
+                for (int d = 1; d <= RZ; ++d)
+                    acc += wz[d] * (ring[((k - 1 - RZ - d) % NZ + NZ) % NZ][i] +
+                                    ring[((k - 1 - RZ + d) % NZ + NZ) % NZ][i]);
+                const T g = acc * iz;
+                const float o = oc[i + 1];
+                // (L g_o)_p over in-slice neighbours
+                float lap = mxl * (o - ol[i]);
+                lap = fmaf(mxr, o - orr[i], lap);
+                lap = fmaf(myu[i], o - oc[i], lap);
+                lap = fmaf(myd[i], o - oc[i + 2], lap);
+                const T bu = alT * (g - (T)o);
+                const T bf = alT * g + (T)lap;
+                bus[i] = bu;
+                gvs[i] = g;
+                // (selects: outside the slice the values may not be finite)
+                const T bum = oin[i] ? bu : T(0), bfm = oin[i] ? bf : T(0);
+                sbb = fma(bfm, bfm, sbb);
+                sb0 = fma(bum, bum, sb0);
+                sbs += bum;
+            }
+            // the next raw tile goes into its slot (no reader of it in this
+            // step) before the stores: its wait would otherwise also wait
+            // for them
+            commit(zi + 1);
+#pragma unroll
+            for (int i = 0; i < kSRows; ++i) asm volatile("" ::"v"(hold[i]), "v"(holdg[i]));
+            if (zo >= 1) partial(zo - 1);
+#pragma unroll
+            for (int i = 0; i < kSRows; ++i) {
+                Buf<T>::st(bus[i], rbw, vb[i], 0);
+                if (a.gs_out) Buf<T>::st(gvs[i], rgw, vg[i], 0);
+                hold[i] = bus[i];
+                holdg[i] = gvs[i];
+            }
+            const double tbb = (double)wave_sum(sbb), tb0 = (double)wave_sum(sb0),
+                         tbs = (double)wave_sum(sbs);
+            if ((tid & 63) == 0) {
+                red_s[zo & 1][wv][0] = tbb;
+                red_s[zo & 1][wv][1] = tb0;
+                red_s[zo & 1][wv][2] = tbs;
+            }
+        } else {
+            commit(zi + 1);
+        }
+        __syncthreads();
+    };
+    // The first block of NZ steps is peeled: there every slice index is a
+    // constant, so the steps before the first output carry no output code.
+    // In the others every step has an output slice (zo >= NZ - 1 - RZ = RZ).
+#pragma unroll
+    for (int k = 0; k < NZ; ++k)
+        if (k < S + RZ + 1) step(k, k);
+    for (int zb = NZ; zb < S + RZ + 1; zb += NZ) {
+        __builtin_assume(zb >= NZ);
+#pragma unroll
+        for (int k = 0; k < NZ; ++k)
+            if (zb + k < S + RZ + 1) step(zb + k, k);   // uniform across the block
     }
+    partial(S - 1);   // the last slice's sums are complete after the last barrier
 }
 
 // Launch one (precision, radius) instance; defined per cross-slice radius in
@@ -340,7 +405,10 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
 template <typename T, int RZ, int RT>
 hipError_t smooth_launch(const SmoothArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((smooth_kernel<T, RZ, RT>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s, a);
+    if (smooth_fast_loads(a))
+        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, true>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, false>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s, a);
     return hipGetLastError();
 }
 
