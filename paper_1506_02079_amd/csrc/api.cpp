@@ -237,7 +237,20 @@ int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripK
     int slots = strip_resident_waves(kind, P.o.csw, P.o.fsw, P.fp64);
     if (slots <= 0) slots = 4096;
     const int E = (G + 2) & ~1;
+    // Coarse levels start from 64-row items, 32 on levels of at most 256 rows,
+    // and are halved only for batches far too small to fill the GPU: their
+    // passes are bound by the serial row march of each item, so many short
+    // items (each re-walking its halo rows) lose to fewer taller ones (on the
+    // 64 x 2048^2 stack 16-row items on levels 2 and 3 make the coarse levels
+    // 18% slower, and so do 128-row items everywhere)
     int th = 128;
+    double want = 2.0 * slots;   // level 0: items that fill the GPU twice over
+    if (level > 0) {
+        int hmax = 0;
+        for (int s : slices) hmax = std::max(hmax, P.g[s].h[level]);
+        th = hmax <= 256 ? 32 : 64;
+        want = slots / 16.0;
+    }
     for (; th > 16; th /= 2) {
         double items = 0.0;
         for (int s : slices) {
@@ -246,7 +259,7 @@ int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripK
             const int nb = hi - lo >= th ? 2 + (hi - lo + th - 1) / th : (H + th - 1) / th;
             items += (double)((W + VW - 1) / VW) * nb;
         }
-        if (items >= 2.0 * slots) break;
+        if (items >= want) break;
     }
     return th;
 }
