@@ -505,6 +505,7 @@ std::vector<char> bind_tables(const Plan &P, char *ws, const std::vector<SliceIO
             d.u[1] = arena + g.off_u[l][1];
             d.b = arena + g.off_b[l];
             d.bshift = (l == 0 && !P.mixed) ? &st_dev[s].bmean : nullptr;
+            d.bshift_fine = (l == 1 && !P.mixed) ? &st_dev[s].bmean : nullptr;
             if (l + 1 < g.nlev) {
                 d.bc = arena + g.off_b[l + 1];
                 // level l+1's final iterate: buffer 1 after an up pass; the
@@ -687,6 +688,9 @@ struct Run {
     double tol;
     int max_cycles;
     double stall_ratio = 0.0;   // FIN_CHECK stall test (FP32 iterates only)
+    // the smoothing pass restricted the unshifted b to level 1: the first pass
+    // skips its restriction and the next level-1 down pass removes the mean
+    bool raw_rhs_l1 = false;
 
     Run(const Plan &p, char *w, hipStream_t st_) : P(p), ws(w), s(st_)
     {
@@ -719,7 +723,7 @@ struct Run {
     }
 
     gdf_status strip(int li, StripKind kind, int in_sel, int out_sel, float2 *partials, bool fp64,
-                     int cls, double per_px, bool slice_parity = false)
+                     int cls, double per_px, bool slice_parity = false, bool raw_rhs = false)
     {
         if (li < 0) return GDF_OK;
         const List &L = P.lists[li];
@@ -733,6 +737,7 @@ struct Run {
         a.active = active;
         a.done = capturing ? done : nullptr;
         a.partials = partials;
+        a.raw_rhs = raw_rhs ? 1 : 0;
         const bool timed = g_prof_on && (!g_prof_fine_only || cls == PC_FINE);
         ProfScope ps(cls, timed ? pass_bytes(li, per_px) : 0.0, s, capturing);
         a.items = items + L.off;
@@ -759,8 +764,11 @@ struct Run {
     {
         const double e = fp64 ? 8.0 : 2.0;   // coarse-level element bytes
         gdf_status r;
+        const bool raw = raw_rhs_l1;
+        raw_rhs_l1 = false;
         for (int l = 1; l <= P.max_level; ++l) {
-            if ((r = strip(P.list_down[l], SK_DOWN, 0, 0, nullptr, fp64, PC_COARSE, 2.25 * e))) return r;
+            if ((r = strip(P.list_down[l], SK_DOWN, 0, 0, nullptr, fp64, PC_COARSE, 2.25 * e, false, raw && l == 1)))
+                return r;
             if ((r = strip(P.list_coarse[l], SK_COARSE_ZERO, 0, 0, nullptr, fp64, PC_COARSE, 2 * e))) return r;
             for (int k = 1; k < kCoarsePasses; ++k)
                 if ((r = strip(P.list_coarse[l], SK_COARSE, (k - 1) & 1, k & 1, nullptr, fp64, PC_COARSE, 3 * e))) return r;
@@ -775,8 +783,10 @@ struct Run {
         const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
-        // read b, write the coarse right-hand side (a quarter per pixel)
-        if ((r = strip(P.list_first, SK_FIRST_RESTRICT, 0, 0, partf, fp64, PC_FIRST, e + 0.25 * ce))) return r;
+        // read b, write the coarse right-hand side (a quarter per pixel), unless
+        // the smoothing pass wrote it
+        if (!raw_rhs_l1)
+            if ((r = strip(P.list_first, SK_FIRST_RESTRICT, 0, 0, partf, fp64, PC_FIRST, e + 0.25 * ce))) return r;
         if ((r = strip(P.list_single, SK_SINGLE_ZERO, 0, 0, partf + nC, fp64, PC_COARSE, 2 * e))) return r;
         return GDF_OK;
     }
@@ -1435,6 +1445,15 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
         if ((long long)(P.g[z].off_b[0] - P.g[0].off_b[0]) != a.b_slice_stride * z * P.esz)
             return set_err(GDF_EDEVICE, "internal: non-uniform arena layout of a stack");
     a.b_pitch = P.g[0].pitch[0];
+    // FP32 hierarchy: the smoothing pass also restricts b_u to level 1, so the
+    // solve's first pass has nothing left to do
+    if (!P.fp64 && !mixed && P.g[0].nlev >= 2 && P.csz == 2) {
+        a.bc0 = ws + P.off_arena + P.g[0].off_b[1];
+        a.bc_slice_stride = S > 1 ? (long long)((P.g[1].off_b[1] - P.g[0].off_b[1]) / P.csz) : 0;
+        a.bc_pitch = P.g[0].pitch[1];
+        for (int z = 1; z < S; ++z)
+            if ((long long)(P.g[z].off_b[1] - P.g[0].off_b[1]) != a.bc_slice_stride * z * P.csz) a.bc0 = nullptr;
+    }
     for (int lo = 0; lo <= 12; ++lo)
         for (int hi = 0; hi <= 12; ++hi) {
             double w = 0.0;
@@ -1449,9 +1468,11 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     a.tiles_x = (W + kSmoothTileW - 1) / kSmoothTileW;
     a.tiles_y = (H + kSmoothTileH - 1) / kSmoothTileH;
     {
-        ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0)), s, false);
+        ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0) + (a.bc0 ? 0.25 * P.csz : 0.0)),
+                     s, false);
         HIP_TRY(launch_smooth(P.fp64, a, s));
     }
+    R.raw_rhs_l1 = a.bc0 != nullptr;
     HIP_TRY(launch_finish_rhs(P.n, R.r_smooth, R.partd, R.partd2, R.partd3, R.st, s));
 
     SolveIO x;

@@ -101,6 +101,10 @@ struct LevelDesc {
     const double *bshift;  // level 0: per-slice mean of b subtracted on load (null: none)
     int slice;       // slice index (flags, partial sums)
     int pad_;
+    // level 1: the level-0 mean; a right-hand side restricted from the unshifted
+    // level-0 one (StripLaunch::raw_rhs) has each cell's children's share of it
+    // subtracted on load
+    const double *bshift_fine;
 };
 
 // A strip work item: one wave processes columns [x0 - G, x0 - G + 128) of
@@ -128,6 +132,7 @@ struct StripLaunch {
     const int *active;       // per-slice "still iterating" flags
     const int *done;         // if non-null and set: no slice is iterating (every wave exits at once)
     float2 *partials;        // per-item partial sums (r^2, r) (RES_NORM / RES_BOTH)
+    int raw_rhs;             // level 1: b holds sums of unshifted level-0 values (see LevelDesc)
 };
 
 // Strip kernel variants (template instances live in mg_kernels.hip).
@@ -332,6 +337,12 @@ struct SmoothArgs {
     double *part_b0;      // [S][tiles] partial ||b_u||^2
     double *part_bs;      // [S][tiles] partial sum(b_u)
     int tiles_x, tiles_y;
+    // optional (FP32): level-1 right-hand side (bfloat16) of slice 0, written as
+    // the sum of each coarse cell's children's b_u (no mean removed); slices are
+    // bc_slice_stride elements apart, rows bc_pitch
+    void *bc0;
+    long long bc_slice_stride;
+    int bc_pitch;
 };
 
 hipError_t launch_smooth(bool fp64, const SmoothArgs &a, hipStream_t s);

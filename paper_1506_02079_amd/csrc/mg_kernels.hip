@@ -102,6 +102,7 @@ __device__ __forceinline__ LevelDesc uniform_level(const LevelDesc &d)
     r.bshift = uniform_ptr(d.bshift);
     r.slice = uniform(d.slice);
     r.pad_ = 0;
+    r.bshift_fine = uniform_ptr(d.bshift_fine);
     return r;
 }
 
@@ -305,7 +306,11 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     // iterate is the zero-mean part of the correction (smaller values, smaller
     // FP32 rounding); the mean is added back when f is formed
     const T bsh = L.bshift ? (T)uniform_d(*L.bshift) : T(0);
-    const T bshg0 = bsh * g0, bshg1 = bsh * g1;
+    // level 1 after a restriction of the unshifted level-0 right-hand side: a
+    // cell's children (4 wx wy of them) each carry the level-0 mean
+    const T bsc = (a.raw_rhs && L.bshift_fine) ? T(4) * (T)uniform_d(*L.bshift_fine) : T(0);
+    const T bsx0 = bsh + bsc * wx0, bsx1 = bsh + bsc * wx1;   // (rows other than the last)
+    const T bshg0 = bsx0 * g0, bshg1 = bsx1 * g1;
     // (selects, not a runtime index into the descriptor's array: that would spill it)
     int in_sel = a.in_sel, out_sel = a.out_sel;
     if (a.cycles) {   // per-slice parity: the latest iterate sits in buffer cycles & 1
@@ -457,8 +462,9 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                     // splits the ring into per-path copies that wait for every load)
                     const bool rin = y >= 0 && y < H;   // uniform
                     const bool v0 = rin && in0, v1 = rin && in1;
-                    b[k][0] = v0 ? (T)SOt::lo(qb[qs]) - bsh : T(0);
-                    b[k][1] = v1 ? (T)SOt::hi(qb[qs]) - bsh : T(0);
+                    const T wyr = y == H - 1 ? wyL : T(1);
+                    b[k][0] = v0 ? (T)SOt::lo(qb[qs]) - fma(bsc * wx0, wyr, bsh) : T(0);
+                    b[k][1] = v1 ? (T)SOt::hi(qb[qs]) - fma(bsc * wx1, wyr, bsh) : T(0);
                     u[k][0] = v0 ? (ZERO ? T(0) : (T)SOt::lo(qu[qs])) + cor0 : T(0);
                     u[k][1] = v1 ? (ZERO ? T(0) : (T)SOt::hi(qu[qs])) + cor1 : T(0);
                 }

@@ -95,9 +95,10 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     __shared__ uint32_t ring_raw[NRAW][kRawHMax * kRawDw];
     __shared__ T hb[2][kRawHMax * kSTX];   // x-blurred rows of the last two input slices
     __shared__ double red_s[2][kSmoothWaves][3];   // per-wave partial sums, by output slice parity
+    __shared__ float xs[2][kSmoothWaves / 2][64];   // restriction: row shared by two waves, by slice parity
 
     const int tid = threadIdx.x;
-    const int tx = tid & 63, wv = tid >> 6;
+    const int tx = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // (wave-uniform)
     const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD
     const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
     const int X0 = tile_x * kSTX, Y0 = tile_y * kSTY;
@@ -200,19 +201,22 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
     auto raw_at = [&](int slot, int r, int c) -> float {
         return (float)reinterpret_cast<const uint8_t *>(ring_raw[slot])[r * kRawW + c];
     };
-    // output offsets of this thread's rows in the tile's rows of a slice's b
-    // (and of g_s): kNoLane outside the slice, so the stores need no branch;
-    // and the masks of the Laplacian's in-slice neighbours
-    unsigned vb[kSRows], vg[kSRows];
-    bool oin[kSRows];
+    // output offsets: the thread's column (kNoLane outside the slice, so the
+    // stores need no branch) plus each row's offset in the tile's rows of a
+    // slice's b (and of g_s), uniform across the wave like the rows' in-slice
+    // flags and the masks of the Laplacian's vertical neighbours
+    // (the row goes in the scalar offset; rows outside the slice are dropped
+    // through the vector offset, kNoLane, like columns outside it)
+    const unsigned vx = x < W ? (unsigned)x * (unsigned)sizeof(T) : kNoLane;
+    unsigned sb[kSRows];
+    bool rin[kSRows], oin[kSRows];
     float myu[kSRows], myd[kSRows];
 #pragma unroll
     for (int i = 0; i < kSRows; ++i) {
         const int y = Y0 + yb + i;
-        const bool in = y < H && x < W;
-        vb[i] = in ? (unsigned)(((yb + i) * a.b_pitch + x) * (int)sizeof(T)) : kNoLane;
-        vg[i] = in ? (unsigned)(((yb + i) * W + x) * (int)sizeof(T)) : kNoLane;
-        oin[i] = in;
+        rin[i] = y < H;
+        oin[i] = y < H && x < W;
+        sb[i] = (unsigned)((yb + i) * a.b_pitch) * (unsigned)sizeof(T);
         myu[i] = y > 0 ? 1.f : 0.f;
         myd[i] = y < H - 1 ? 1.f : 0.f;
     }
@@ -244,12 +248,28 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
             }
         }
     };
+    // Restriction of b_u to level 1 (a.bc0, FP32 hierarchy): a coarse cell's
+    // right-hand side is the sum of its children's b_u (zero outside the slice).
+    // Lane pairs give the column sums, a thread's rows the row sums; with an odd
+    // number of rows per thread, the row pair split between waves 2m and 2m + 1
+    // meets in LDS and is stored by wave 2m + 1 in the next step.
+    const bool rst = sizeof(T) == 4 && a.bc0 != nullptr;   // (FP64 hierarchies restrict in the solve)
+    const unsigned vcol = ((tx & 1) == 0 && X0 + tx < W) ? (unsigned)((X0 + tx) >> 1) * 2u : kNoLane;
+    float hx = 0.f;   // odd waves: column sum of their first row (the pair's second row)
+    auto cstore = [&](int z, int ty, float v) {   // ty: tile row of the cell's first child (even)
+        if (Y0 + ty >= H) return;
+        const Rsrc rc = make_rsrc(static_cast<unsigned short *>(a.bc0) + (long long)z * a.bc_slice_stride +
+                                      (long long)((Y0 + ty) >> 1) * a.bc_pitch,
+                                  (unsigned)a.bc_pitch * 2u);
+        Buf<unsigned short>::st(__builtin_bit_cast(unsigned short, (__bf16)v), rc, vcol, 0);   // nearest even
+    };
+
     // the last step's output values stay in their registers until the next
     // step's commit has waited for every load and store: rewritten earlier,
     // they would need a wait for their stores right there
-    T hold[kSRows], holdg[kSRows];
+    T hold[kSRows];
 #pragma unroll
-    for (int i = 0; i < kSRows; ++i) hold[i] = holdg[i] = T(0);
+    for (int i = 0; i < kSRows; ++i) hold[i] = T(0);
 
     issue(0);
     commit(0);
@@ -334,6 +354,7 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                 orr[i] = raw_at(oslot, yb + RH + i, tx + 9);
             }
             T bus[kSRows], gvs[kSRows];
+            float bms[kSRows];   // b_u, zero outside the slice
 #pragma unroll
             for (int i = 0; i < kSRows; ++i) {
                 // register slot of zo is k - 1 - RZ (mod NZ): static for each k
@@ -355,6 +376,7 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
                 gvs[i] = g;
                 // (selects: outside the slice the values may not be finite)
                 const T bum = oin[i] ? bu : T(0), bfm = oin[i] ? bf : T(0);
+                bms[i] = (float)bum;
                 sbb = fma(bfm, bfm, sbb);
                 sb0 = fma(bum, bum, sb0);
                 sbs += bum;
@@ -364,14 +386,33 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
             // for them
             commit(zi + 1);
 #pragma unroll
-            for (int i = 0; i < kSRows; ++i) asm volatile("" ::"v"(hold[i]), "v"(holdg[i]));
+            for (int i = 0; i < kSRows; ++i) asm volatile("" ::"v"(hold[i]));
             if (zo >= 1) partial(zo - 1);
+            if (rst) {
+                if constexpr (kSRows % 2 == 1)
+                    if ((wv & 1) && zo >= 1) cstore(zo - 1, yb - 1, xs[(zo - 1) & 1][wv >> 1][tx] + hx);
+                float cs[kSRows];
+#pragma unroll
+                for (int i = 0; i < kSRows; ++i) cs[i] = bms[i] + dpp_row<0xB1>(bms[i]);   // lane pairs
+                if constexpr (kSRows % 2 == 0) {
+#pragma unroll
+                    for (int i = 0; i < kSRows; i += 2) cstore(zo, yb + i, cs[i] + cs[i + 1]);
+                } else if ((wv & 1) == 0) {
+#pragma unroll
+                    for (int i = 0; i + 1 < kSRows; i += 2) cstore(zo, yb + i, cs[i] + cs[i + 1]);
+                    xs[zo & 1][wv >> 1][tx] = cs[kSRows - 1];
+                } else {
+#pragma unroll
+                    for (int i = 1; i + 1 < kSRows; i += 2) cstore(zo, yb + i, cs[i] + cs[i + 1]);
+                    hx = cs[0];
+                }
+            }
 #pragma unroll
             for (int i = 0; i < kSRows; ++i) {
-                Buf<T>::st(bus[i], rbw, vb[i], 0);
-                if (a.gs_out) Buf<T>::st(gvs[i], rgw, vg[i], 0);
+                const unsigned vo = rin[i] ? vx : kNoLane;
+                Buf<T>::st(bus[i], rbw, vo, sb[i]);
+                if (a.gs_out) Buf<T>::st(gvs[i], rgw, vo, (unsigned)((yb + i) * W) * (unsigned)sizeof(T));
                 hold[i] = bus[i];
-                holdg[i] = gvs[i];
             }
             const double tbb = (double)wave_sum(sbb), tb0 = (double)wave_sum(sb0),
                          tbs = (double)wave_sum(sbs);
@@ -398,6 +439,8 @@ __global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
             if (zb + k < S + RZ + 1) step(zb + k, k);   // uniform across the block
     }
     partial(S - 1);   // the last slice's sums are complete after the last barrier
+    if constexpr (kSRows % 2 == 1)
+        if (rst && (wv & 1)) cstore(S - 1, yb - 1, xs[(S - 1) & 1][wv >> 1][tx] + hx);
 }
 
 // Launch one (precision, radius) instance; defined per cross-slice radius in
