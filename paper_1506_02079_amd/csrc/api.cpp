@@ -846,8 +846,13 @@ struct Run {
         }
         bool any = true;
         for (int k = 1; k <= max_cycles; ++k) {
-            if ((r = read_active(any))) return r;
-            if (!any) break;
+            // (a fresh solve starts its first cycle without reading the flags:
+            // slices already converged skip it on the device, and the GPU does
+            // not idle while the host waits for the smoothing pass)
+            if (!(first && k == 1)) {
+                if ((r = read_active(any))) return r;
+                if (!any) break;
+            }
             if ((r = cycle(k, fp64, true, z && k == 1))) return r;
             if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
         }
