@@ -137,3 +137,29 @@ def test_noconv_reported():
     assert all(r["status"] == gdf.GDF_ENOCONV and r["vcycles"] == 1 for r in rep)
     with pytest.raises(gdf.GdfError):
         gdf.fuse_stack(t, 0.01, tol=1e-9, max_vcycles=1)
+
+
+@pytest.mark.parametrize("shape,alpha", [((6, 129, 257), 0.01), ((5, 200, 131), 0.003), ((3, 65, 33), 0.05)])
+def test_fused_restriction_matches_restriction_pass(shape, alpha):
+    # fuse_stack restricts the unshifted level-0 right-hand side inside the
+    # smoothing pass and removes the mean's share (4 wx wy children) in the first
+    # level-1 pass; solve_slices on the same g_s and g_o restricts the shifted one
+    # in a pass of its own.  Odd sizes give partial last cells (wx, wy = 1/2), and
+    # the illumination ramp a large mean.  Both solve the same system.  The
+    # bfloat16 level-1 values differ by rounding (the unshifted sums are larger),
+    # which can cost a slice right at tol one more cycle; a missing or wrong mean
+    # correction would cost every slice one.
+    stack = synth.make_stack(*shape, seed=29 + shape[2], ramp=True)
+    t = torch.from_numpy(stack).to(DEV)
+    f1, rep1, gsm = gdf.fuse_stack(t, alpha, tol=1e-6, return_smooth=True)
+    go = t.to(torch.float32)
+    f2, rep2 = gdf.solve_slices([gsm[z] for z in range(shape[0])], [go[z] for z in range(shape[0])], alpha,
+                                tol=1e-6)
+    torch.cuda.synchronize()
+    c1 = [r["vcycles"] for r in rep1]
+    c2 = [r["vcycles"] for r in rep2]
+    print(shape, alpha, "cycles fused", c1, "separate", c2)
+    assert sum(c1) <= sum(c2) + shape[0] // 2
+    assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep1 + rep2)
+    f2s = torch.stack([x for x in f2]).cpu().numpy()
+    assert np.abs(f1.cpu().numpy() - f2s).max() <= ABS_TOL
