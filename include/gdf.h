@@ -233,7 +233,7 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
  * finest-level post-/pre-smoothing pass), "vcycle_fine_first" (the same pass
  * in the first cycle of a solve from zero, which reads no iterate),
  * "restrict_first" (the restriction of the right-hand side before the first
- * cycle; in an FP32 gdf_fuse_stack the smoothing pass does it and this class
+ * cycle; in an FP32 fuse_stack the smoothing pass does it and this class
  * records nothing), "coarse", "finalize", "prep", "refine", "adjoint".
  * Returns the number of launches
  * recorded and writes the summed milliseconds and the summed algorithmic
