@@ -86,8 +86,10 @@ inline bool smooth_fast_loads(const SmoothArgs &a)
 // carry zero weight), RZ: cross-slice tap radius.  FAST: the stack takes the
 // fixed-offset dword loads (smooth_fast_loads); otherwise raw tiles are read
 // byte by byte where a dword is not whole.
+// FP32 instances keep four waves per SIMD (two workgroups per CU); FP64 ones
+// need more registers than that allows.
 template <typename T, int RZ, int RT, bool FAST>
-__global__ __launch_bounds__(kSThreads) void smooth_kernel(SmoothArgs a)
+__global__ __launch_bounds__(kSThreads, (sizeof(T) == 4 ? 4 : 1)) void smooth_kernel(SmoothArgs a)
 {
     constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
     constexpr int NRAW = RZ + 3;       // LDS ring of raw tiles: slices zo .. zi + 1

@@ -163,3 +163,25 @@ def test_fused_restriction_matches_restriction_pass(shape, alpha):
     assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep1 + rep2)
     f2s = torch.stack([x for x in f2]).cpu().numpy()
     assert np.abs(f1.cpu().numpy() - f2s).max() <= ABS_TOL
+
+
+@pytest.mark.parametrize("sigma_xy,sigma_z,precision", [(0.5, 1.0, "fp32"), (2.0, 0.0, "fp32"), (1.0, 4.0, "fp32"),
+                                                         (0.0, 2.0, "fp32"), (2.3, 1.5, "fp64")])
+def test_smoothing_radii(sigma_xy, sigma_z, precision):
+    # other truncation radii than the default (3 in-plane, 9 across): the
+    # in-plane radius selects the kernel instance (3 or up to 7), the cross-slice
+    # radius another (0 to 12); odd sizes, stacks shallower than the cross-slice
+    # reach, and the restriction into level 1 with an odd slice count per tile
+    stack = synth.make_stack(7, 61, 75, seed=41, ramp=True)
+    t = torch.from_numpy(stack).to(DEV)
+    f, rep, gsm = gdf.fuse_stack(t, 0.02, tol=1e-6, sigma_xy=sigma_xy, sigma_z=sigma_z, precision=precision,
+                                 return_smooth=True, out_dtype=gdf.DTYPE_F64)
+    torch.cuda.synchronize()
+    gs_ref = oracle.smooth(stack, sigma_xy, sigma_z)
+    gerr = np.abs(gsm.cpu().numpy().astype(np.float64) - gs_ref).max()
+    f_ref, _ = oracle.fuse_stack(stack, 0.02, sigma_xy=sigma_xy, sigma_z=sigma_z, tol=1e-12)
+    ferr = np.abs(f.cpu().numpy() - f_ref).max()
+    print(sigma_xy, sigma_z, precision, "smoothing err", gerr, "f err", ferr, [r["vcycles"] for r in rep])
+    assert gerr <= (2e-4 if precision == "fp32" else 1e-9)
+    assert ferr <= ABS_TOL
+    assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep)
