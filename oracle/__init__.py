@@ -59,6 +59,8 @@ def _load():
         lib.oracle_smooth.restype = None
         lib.oracle_smooth_points.argtypes = [P, I, I, I, D, D, P, L, P]
         lib.oracle_smooth_points.restype = None
+        lib.oracle_smooth_robust.argtypes = [P, I, I, I, D, D, P]
+        lib.oracle_smooth_robust.restype = None
         lib.oracle_laplacian.argtypes = [P, I, I, I, P]
         lib.oracle_laplacian.restype = None
         lib.oracle_apply_A.argtypes = [P, I, I, D, I, P]
@@ -195,12 +197,25 @@ def adjoint(gbar: np.ndarray, gs: np.ndarray, f: np.ndarray, alpha: float, bc="n
     return dgs, dgo, da.value
 
 
+def smooth_robust(stack: np.ndarray, sigma_xy: float = 1.0, sigma_z: float = 3.0) -> np.ndarray:
+    """Robust cross-slice averaging ("Extensions and Applications"): the average
+    across slices of the in-plane smoothed values keeps only those within two
+    weighted standard deviations of the window's weighted mean (one pass).
+    float64 [S][H][W]."""
+    st = np.ascontiguousarray(stack, dtype=np.uint8)
+    S, H, W = st.shape
+    out = np.empty((S, H, W), dtype=np.float64)
+    _load().oracle_smooth_robust(_ptr(st), S, H, W, float(sigma_xy), float(sigma_z), _ptr(out))
+    return out
+
+
 def fuse_stack(stack: np.ndarray, alpha: float, sigma_xy: float = 1.0, sigma_z: float = 3.0,
-               bc="neumann", tol: float = 1e-12):
+               bc="neumann", tol: float = 1e-12, robust: bool = False):
     """The whole method: smooth across slices, then blend each slice (Eq. (1)).
+    robust: the robust cross-slice average of smooth_robust.
 
     Returns (f, g_s) as float64 [S][H][W].
     """
-    gs = smooth(stack, sigma_xy, sigma_z)
+    gs = smooth_robust(stack, sigma_xy, sigma_z) if robust else smooth(stack, sigma_xy, sigma_z)
     go = np.asarray(stack, dtype=np.float64)
     return solve_stack(gs, go, alpha, bc, tol), gs

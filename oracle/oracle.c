@@ -106,6 +106,77 @@ void oracle_smooth_points(const uint8_t *stack, int S, int H, int W, double sigm
                                      zyx[3 * i + 2]);
 }
 
+/* Robust cross-slice averaging ("Extensions and Applications": only colour
+ * values within two standard deviations are averaged).  Reading taken here:
+ * the robust step acts on the average across slices.  At (z,y,x) the window's
+ * values are p_d, the in-plane smoothed value of slice z+d at (y,x) (the
+ * renormalised in-plane Gaussian average), with weights w_d of the cross-slice
+ * Gaussian for the slices inside the stack.  Their weighted mean mu and
+ * weighted variance var = sum w (p - mu)^2 / sum w are taken once; the result
+ * is the weighted average of the p_d with (p_d - mu)^2 <= 4 var.  With nothing
+ * left out this is oracle_smooth_voxel (the 3D weights factor).  One pass,
+ * weighted statistics. */
+static double inplane_voxel(const uint8_t *stack, int H, int W, double sigma_xy, int z, int y, int x)
+{
+    const int rxy = tap_radius(sigma_xy);
+    double num = 0.0, den = 0.0;
+    for (int dy = -rxy; dy <= rxy; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= H) continue;
+        for (int dx = -rxy; dx <= rxy; ++dx) {
+            const int xx = x + dx;
+            if (xx < 0 || xx >= W) continue;
+            const double w = gauss_factor(dx, sigma_xy) * gauss_factor(dy, sigma_xy);
+            num += w * (double)stack[((size_t)z * H + yy) * W + xx];
+            den += w;
+        }
+    }
+    return num / den;
+}
+
+double oracle_smooth_robust_voxel(const uint8_t *stack, int S, int H, int W, double sigma_xy,
+                                  double sigma_z, int z, int y, int x)
+{
+    const int rz = tap_radius(sigma_z);
+    double p[64], w[64];
+    int n = 0;
+    for (int dz = -rz; dz <= rz && n < 64; ++dz) {
+        const int zz = z + dz;
+        if (zz < 0 || zz >= S) continue;
+        p[n] = inplane_voxel(stack, H, W, sigma_xy, zz, y, x);
+        w[n] = gauss_factor(dz, sigma_z);
+        ++n;
+    }
+    double sw = 0.0, swp = 0.0;
+    for (int i = 0; i < n; ++i) {
+        sw += w[i];
+        swp += w[i] * p[i];
+    }
+    const double mu = swp / sw;
+    double sv = 0.0;
+    for (int i = 0; i < n; ++i) sv += w[i] * (p[i] - mu) * (p[i] - mu);
+    const double var = sv / sw;
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < n; ++i)
+        if ((p[i] - mu) * (p[i] - mu) <= 4.0 * var) {
+            num += w[i] * p[i];
+            den += w[i];
+        }
+    return num / den;
+}
+
+void oracle_smooth_robust(const uint8_t *stack, int S, int H, int W, double sigma_xy, double sigma_z,
+                          double *out)
+{
+    const long long rows = (long long)S * H;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long long zy = 0; zy < rows; ++zy) {
+        const int z = (int)(zy / H), y = (int)(zy % H);
+        for (int x = 0; x < W; ++x)
+            out[(size_t)zy * W + x] = oracle_smooth_robust_voxel(stack, S, H, W, sigma_xy, sigma_z, z, y, x);
+    }
+}
+
 /* ---------------------------------------------------------- grid operators */
 
 /* Neighbour index of (y,x) displaced by (dy,dx), or -1 if it leaves the slice
