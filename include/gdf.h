@@ -100,7 +100,13 @@ typedef struct {
                           inner solves run a fixed number of cycles).  The coarse levels are
                           small and latency-bound, so a third sweep there costs little and
                           lowers the residual of every cycle. */
-    int reserved[5];
+    int robust;        /* fuse_stack: 1 = robust cross-slice averaging ("Extensions and
+                          Applications"): at each voxel, of the in-plane smoothed values
+                          of the slices in the cross-slice window, those more than two
+                          weighted standard deviations from the window's weighted mean
+                          are left out of the average (one pass).  FP32 and MIXED only
+                          (GDF_EUNSUPPORTED with GDF_PREC_FP64); 0 = plain averaging. */
+    int reserved[4];
 } gdf_solve_opts;
 
 typedef enum {

@@ -39,7 +39,7 @@ class SolveOpts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("launch_mode", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("fine_sweeps", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("robust", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class SliceReport(ctypes.Structure):
@@ -178,8 +178,10 @@ def _require_cuda(*ts):
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
                tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
-               allow_noconv=False):
+               allow_noconv=False, robust=False):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
+    robust=True: robust cross-slice averaging (values more than two weighted
+    standard deviations from the window's weighted mean are left out).
 
     Returns (f, report) or (f, report, g_smooth) with return_smooth=True.
     f has dtype float32 (fp32) or float64 (fp64 / mixed) unless out_dtype is given.
@@ -193,6 +195,7 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
     S, H, W = stack.shape
     o = make_opts(precision, max_vcycles, nu, out_dtype, False, tile_rows, inner_cycles,
                   launch_mode, autotune, fine_sweeps, coarse_sweeps)
+    o.robust = int(bool(robust))
     L = lib()
     ws = L.gdf_fuse_workspace_size(S, H, W, ctypes.byref(o))
     if ws == 0:

@@ -79,6 +79,7 @@ struct Opts {
     int prec, max_vc, nu, out_dtype, use_graph, tile_rows, inner, launch, autotune;
     int fsw;   // sweeps of the fused finest pass
     int csw;   // sweeps per smoothing step on the coarse levels
+    int robust;   // robust cross-slice averaging in fuse_stack
 };
 
 gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
@@ -120,6 +121,10 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
     r.csw = o->coarse_sweeps ? o->coarse_sweeps : (r.prec == GDF_PREC_MIXED ? r.nu : r.nu + 1);
     if (r.csw < 1 || r.csw > 3)
         return set_err(GDF_EINVAL, "opts.coarse_sweeps must be 0 or in [1, 3] (got %d)", o->coarse_sweeps);
+    r.robust = o->robust;
+    if (r.robust != 0 && r.robust != 1) return set_err(GDF_EINVAL, "opts.robust must be 0 or 1 (got %d)", r.robust);
+    if (r.robust && r.prec == GDF_PREC_FP64)
+        return set_err(GDF_EUNSUPPORTED, "opts.robust: robust averaging runs in the FP32 smoothing (FP32 or MIXED)");
     return GDF_OK;
 }
 
@@ -1352,7 +1357,7 @@ size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
-                  b.launch_mode})
+                  b.launch_mode, b.robust})
         key_push(key, v);
     return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
 }
@@ -1378,7 +1383,7 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps,
-                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0})
+                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust})
         key_push(key, v);
     for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
     return autotuned(key, b, [&](const gdf_solve_opts *c) {
@@ -1440,6 +1445,7 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     for (int d = 0; d < 8; ++d) a.wxy_f[d] = (float)a.wxy[d];
     for (int d = 0; d < 16; ++d) a.wz_f[d] = (float)a.wz[d];
     a.alpha_f = (float)alpha;
+    a.robust = o.robust;
     void *gs_used = g_smooth ? g_smooth : (mixed ? (void *)(ws + P.off_gscopy) : nullptr);
     a.gs_out = gs_used;
     // a uniform stack: every slice has the same arena block, so the level-0

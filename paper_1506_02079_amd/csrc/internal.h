@@ -343,6 +343,7 @@ struct SmoothArgs {
     void *bc0;
     long long bc_slice_stride;
     int bc_pitch;
+    int robust;           // robust cross-slice averaging (FP32 only)
 };
 
 hipError_t launch_smooth(bool fp64, const SmoothArgs &a, hipStream_t s);

@@ -85,11 +85,13 @@ inline bool smooth_fast_loads(const SmoothArgs &a)
 // RT: compile-time in-plane tap radius (>= the true radius; taps beyond it
 // carry zero weight), RZ: cross-slice tap radius.  FAST: the stack takes the
 // fixed-offset dword loads (smooth_fast_loads); otherwise raw tiles are read
-// byte by byte where a dword is not whole.
-// FP32 instances keep four waves per SIMD (two workgroups per CU); FP64 ones
-// need more registers than that allows.
-template <typename T, int RZ, int RT, bool FAST>
-__global__ __launch_bounds__(kSThreads, (sizeof(T) == 4 ? 4 : 1)) void smooth_kernel(SmoothArgs a)
+// byte by byte where a dword is not whole.  ROBUST (FP32): the robust
+// cross-slice average of "Extensions and Applications" (values more than two
+// weighted standard deviations from the window's weighted mean left out).
+// Plain FP32 instances keep four waves per SIMD (two workgroups per CU); FP64
+// and robust ones need more registers than that allows.
+template <typename T, int RZ, int RT, bool FAST, bool ROBUST>
+__global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) void smooth_kernel(SmoothArgs a)
 {
     constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
     constexpr int NRAW = RZ + 3;       // LDS ring of raw tiles: slices zo .. zi + 1
@@ -365,7 +367,30 @@ __global__ __launch_bounds__(kSThreads, (sizeof(T) == 4 ? 4 : 1)) void smooth_ke
                 for (int d = 1; d <= RZ; ++d)
                     acc += wz[d] * (ring[((k - 1 - RZ - d) % NZ + NZ) % NZ][i] +
                                     ring[((k - 1 - RZ + d) % NZ + NZ) % NZ][i]);
-                const T g = acc * iz;
+                T g = acc * iz;
+                if constexpr (ROBUST) {
+                    // robust cross-slice average: the window's in-stack values
+                    // (taps -zlo .. zhi) within two weighted standard deviations of
+                    // their weighted mean g, re-averaged with their weights
+                    auto tap = [&](int d) -> T { return ring[((k - 1 - RZ + d) % NZ + NZ) % NZ][i]; };
+                    auto wt = [&](int d) -> T { return (d >= -zlo && d <= zhi) ? wz[d < 0 ? -d : d] : T(0); };
+                    T var = T(0);
+#pragma unroll
+                    for (int d = -RZ; d <= RZ; ++d) {
+                        const T e = tap(d) - g;
+                        var = fma(wt(d) * e, e, var);
+                    }
+                    const T thr = T(4) * var * iz;
+                    T num = T(0), den = T(0);
+#pragma unroll
+                    for (int d = -RZ; d <= RZ; ++d) {
+                        const T e = tap(d) - g;
+                        const T w = e * e <= thr ? wt(d) : T(0);
+                        num = fma(w, tap(d), num);
+                        den += w;
+                    }
+                    g = num / den;   // (den > 0: the value nearest the mean always stays)
+                }
                 const float o = oc[i + 1];
                 // (L g_o)_p over in-slice neighbours
                 float lap = mxl * (o - ol[i]);
@@ -447,13 +472,15 @@ __global__ __launch_bounds__(kSThreads, (sizeof(T) == 4 ? 4 : 1)) void smooth_ke
 
 // Launch one (precision, radius) instance; defined per cross-slice radius in
 // the smooth_rz*.hip translation units so they compile in parallel.
-template <typename T, int RZ, int RT>
+template <typename T, int RZ, int RT, bool ROBUST>
 hipError_t smooth_launch(const SmoothArgs &a, hipStream_t s)
 {
     if (smooth_fast_loads(a))
-        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, true>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s, a);
+        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, true, ROBUST>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s,
+                           a);
     else
-        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, false>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s, a);
+        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, false, ROBUST>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0,
+                           s, a);
     return hipGetLastError();
 }
 
@@ -461,8 +488,12 @@ hipError_t smooth_launch(const SmoothArgs &a, hipStream_t s)
 #define GDF_SMOOTH_RZ(RZ)                                                                  \
     hipError_t smooth_rz_##RZ(bool fp64, const SmoothArgs &a, hipStream_t s)               \
     {                                                                                      \
-        if (fp64) return smooth_launch<double, RZ, kMaxRxy>(a, s);                         \
-        return a.rxy == 3 ? smooth_launch<float, RZ, 3>(a, s) : smooth_launch<float, RZ, kMaxRxy>(a, s); \
+        if (fp64) return a.robust ? hipErrorInvalidValue : smooth_launch<double, RZ, kMaxRxy, false>(a, s); \
+        if (a.robust)                                                                      \
+            return a.rxy == 3 ? smooth_launch<float, RZ, 3, true>(a, s)                    \
+                              : smooth_launch<float, RZ, kMaxRxy, true>(a, s);             \
+        return a.rxy == 3 ? smooth_launch<float, RZ, 3, false>(a, s)                       \
+                          : smooth_launch<float, RZ, kMaxRxy, false>(a, s);                \
     }
 
 }  // namespace gdf

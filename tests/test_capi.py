@@ -38,6 +38,12 @@ def _fuse(**kw):
                                 ctypes.byref(o), a["ws"], a["wsb"], a["rep"], None)
 
 
+def _robust(v, **kw):
+    o = gdf.make_opts(**kw)
+    o.robust = v
+    return o
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(S=0), gdf.GDF_EINVAL),
     (dict(H=-1), gdf.GDF_EINVAL),
@@ -66,6 +72,8 @@ def _fuse(**kw):
     (dict(opts=gdf.make_opts(nu=1, fine_sweeps=5)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(coarse_sweeps=4)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(coarse_sweeps=-1)), gdf.GDF_EINVAL),
+    (dict(opts=_robust(2)), gdf.GDF_EINVAL),
+    (dict(opts=_robust(1, precision="fp64")), gdf.GDF_EUNSUPPORTED),
     (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),
     (dict(wsb=16), gdf.GDF_ENOMEM),

@@ -290,3 +290,52 @@ def test_fused_pass_sweep_counts(nu, fine_sweeps):
     for j in (0, 4):
         fr = oracle.solve(g[j], stack[j].astype(np.float64), 0.01, tol=1e-11)
         assert np.abs(f1[j].cpu().numpy() - fr).max() <= 1e-3
+
+
+def test_robust_averaging_restores_corrupt_slices():
+    # "Extensions and Applications": a constant stack with zeroed (missing)
+    # interior slices.  Robust averaging leaves the zeros out of every window
+    # (their weight share is below 1/5), so the low-frequency target stays
+    # constant and the blend restores the missing slices; plain averaging
+    # pulls the target down around them.
+    # (more than a window apart: a window holding two odd slices can keep the
+    # milder one, its distance being small against the other's)
+    st = np.full((48, 96, 128), 140, np.uint8)
+    st[12] = 0
+    st[34, 48:] = 0   # the lower half of a slice, as in the paper's figure
+    t = torch.from_numpy(st).to(DEV)
+    f, rep, gsm = gdf.fuse_stack(t, 0.01, tol=1e-6, robust=True, return_smooth=True, out_dtype=gdf.DTYPE_F64)
+    # (plain averaging leaves a step in the target of the slices next to the
+    # half-zeroed one while their g_o is flat; one of them ends a hair above tol)
+    fp, _, gsp = gdf.fuse_stack(t, 0.01, tol=1e-6, return_smooth=True, out_dtype=gdf.DTYPE_F64,
+                                allow_noconv=True)
+    torch.cuda.synchronize()
+    assert np.abs(gsm.cpu().numpy() - 140).max() <= 1e-3
+    assert gsp.cpu().numpy()[12].max() < 130
+    f = f.cpu().numpy()
+    assert np.abs(f[12] - 140).max() <= 1e-2   # g_o = 0 there: f is the constant target
+    assert np.abs(fp.cpu().numpy()[12] - 140).max() > 5
+    assert all(r["status"] == gdf.GDF_OK for r in rep)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_robust_averaging_matches_oracle(precision):
+    # EM-like stack with a corrupt slice.  Whether a value lies within two
+    # standard deviations is decided in FP32 on the GPU and in FP64 in the
+    # oracle, so a value right at the threshold can go either way: at most one
+    # voxel in a thousand may differ by more than the smoothing bar.  The solve
+    # is then checked against the oracle on the GPU's own smoothed stack.
+    st = synth.make_stack(24, 70, 90, seed=51, ramp=True)
+    st[11, 20:] = 3
+    t = torch.from_numpy(st).to(DEV)
+    f, rep, gsm = gdf.fuse_stack(t, 0.01, tol=1e-6, robust=True, precision=precision, return_smooth=True,
+                                 out_dtype=gdf.DTYPE_F64)
+    torch.cuda.synchronize()
+    gs = gsm.cpu().numpy().astype(np.float64)
+    ref = oracle.smooth_robust(st)
+    bad = np.abs(gs - ref) > 2e-4
+    print(precision, "voxels off", int(bad.sum()), "of", bad.size, "max err", float(np.abs(gs - ref).max()))
+    assert bad.mean() <= 1e-3
+    fr = oracle.solve_stack(gs, st.astype(np.float64), 0.01, tol=1e-12)
+    assert np.abs(f.cpu().numpy() - fr).max() <= 1e-3
+    assert all(r["status"] == gdf.GDF_OK for r in rep)
