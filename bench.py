@@ -166,6 +166,28 @@ def bench_mixed(gdf, torch, dev, steps, alpha):
             "worst_rel_residual": max(r["rel_residual"] for r in rep), "inner_vcycles_min_max": [min(vc), max(vc)]}
 
 
+def bench_robust(gdf, torch, dev, stack, kw, steps):
+    """The headline stack with robust cross-slice averaging ("Extensions and Applications")."""
+    st = torch.from_numpy(stack).to(dev)
+    run = lambda: gdf.fuse_stack(st, ALPHA, robust=True, **kw)
+    log("robust: timing")
+    ms, (f, rep) = _timed(torch, run, steps, 1)
+    del f
+    gdf.profile_reset()
+    gdf.profile_enable(True)
+    gdf.fuse_stack(st, ALPHA, robust=True, **kw)
+    torch.cuda.synchronize()
+    gdf.profile_enable(False)
+    n, sm, _ = gdf.profile_read("smooth")
+    S_, H_, W_ = stack.shape
+    vc = [r["vcycles"] for r in rep]
+    return {"value": S_ * H_ * W_ / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+            "workload": "fuse_stack on the headline stack with robust cross-slice averaging (values beyond two "
+                        "weighted standard deviations of the window mean left out), FP32, tol 1e-6",
+            "smooth_ms": sm / max(1, n), "worst_rel_residual": max(r["rel_residual"] for r in rep),
+            "vcycles_min_max": [min(vc), max(vc)]}
+
+
 def bench_adjoint(gdf, torch, dev, steps):
     """16 x 1024 x 1024 FP32: loss = sum (f - t)^2 through the autograd function."""
     S4, H4, W4 = 16, 1024, 1024
@@ -338,6 +360,7 @@ def main():
         forms["mixed_alpha_0.01"] = bench_mixed(gdf, torch, dev, 2, 0.01)
         torch.cuda.empty_cache()
         forms["adjoint"] = bench_adjoint(gdf, torch, dev, 5)
+        forms["robust"] = bench_robust(gdf, torch, dev, stack, kw, 3)
         for v in forms.values():
             v["vs_plain"] = v["value"] / plain
         out["forms"] = forms
