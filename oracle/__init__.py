@@ -61,6 +61,8 @@ def _load():
         lib.oracle_smooth_points.restype = None
         lib.oracle_smooth_robust.argtypes = [P, I, I, I, D, D, P]
         lib.oracle_smooth_robust.restype = None
+        lib.oracle_smooth_transpose.argtypes = [P, I, I, I, D, D, P]
+        lib.oracle_smooth_transpose.restype = None
         lib.oracle_laplacian.argtypes = [P, I, I, I, P]
         lib.oracle_laplacian.restype = None
         lib.oracle_apply_A.argtypes = [P, I, I, D, I, P]
@@ -206,6 +208,16 @@ def smooth_robust(stack: np.ndarray, sigma_xy: float = 1.0, sigma_z: float = 3.0
     S, H, W = st.shape
     out = np.empty((S, H, W), dtype=np.float64)
     _load().oracle_smooth_robust(_ptr(st), S, H, W, float(sigma_xy), float(sigma_z), _ptr(out))
+    return out
+
+
+def smooth_transpose(g: np.ndarray, sigma_xy: float = 1.0, sigma_z: float = 3.0) -> np.ndarray:
+    """The transpose of smooth (as a linear map of the stack): the gradient of a
+    loss on the smoothed stack with respect to the stack.  float64 [S][H][W]."""
+    gg = np.ascontiguousarray(g, dtype=np.float64)
+    S, H, W = gg.shape
+    out = np.empty((S, H, W), dtype=np.float64)
+    _load().oracle_smooth_transpose(_ptr(gg), S, H, W, float(sigma_xy), float(sigma_z), _ptr(out))
     return out
 
 

@@ -177,6 +177,48 @@ void oracle_smooth_robust(const uint8_t *stack, int S, int H, int W, double sigm
     }
 }
 
+/* Transpose of the smoothing operator, for the gradient through it (derived:
+ * the paper does not differentiate).  Smoothing is I1(p) = sum_q K(q - p) I0(q)
+ * / D(p) over the in-stack window of p, with D(p) the sum of its in-stack
+ * weights; so for a gradient G on I1, dLoss/dI0(q) = sum_p K(q - p) G(p) / D(p)
+ * over the voxels p whose window holds q (K is symmetric). */
+void oracle_smooth_transpose(const double *g, int S, int H, int W, double sigma_xy, double sigma_z,
+                             double *out)
+{
+    const int rxy = tap_radius(sigma_xy), rz = tap_radius(sigma_z);
+    const long long n = (long long)S * H * W;
+    double *gd = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    for (int z = 0; z < S; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                double den = 0.0;
+                for (int dz = -rz; dz <= rz; ++dz)
+                    for (int dy = -rxy; dy <= rxy; ++dy)
+                        for (int dx = -rxy; dx <= rxy; ++dx) {
+                            const int zz = z + dz, yy = y + dy, xx = x + dx;
+                            if (zz < 0 || zz >= S || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                            den += gauss_factor(dx, sigma_xy) * gauss_factor(dy, sigma_xy) * gauss_factor(dz, sigma_z);
+                        }
+                const size_t i = ((size_t)z * H + y) * W + x;
+                gd[i] = g[i] / den;
+            }
+    for (int z = 0; z < S; ++z)
+        for (int y = 0; y < H; ++y)
+            for (int x = 0; x < W; ++x) {
+                double acc = 0.0;
+                for (int dz = -rz; dz <= rz; ++dz)
+                    for (int dy = -rxy; dy <= rxy; ++dy)
+                        for (int dx = -rxy; dx <= rxy; ++dx) {
+                            const int zz = z + dz, yy = y + dy, xx = x + dx;
+                            if (zz < 0 || zz >= S || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                            acc += gauss_factor(dx, sigma_xy) * gauss_factor(dy, sigma_xy) * gauss_factor(dz, sigma_z) *
+                                   gd[((size_t)zz * H + yy) * W + xx];
+                        }
+                out[((size_t)z * H + y) * W + x] = acc;
+            }
+    free(gd);
+}
+
 /* ---------------------------------------------------------- grid operators */
 
 /* Neighbour index of (y,x) displaced by (dy,dx), or -1 if it leaves the slice
