@@ -188,6 +188,20 @@ def bench_robust(gdf, torch, dev, stack, kw, steps):
             "vcycles_min_max": [min(vc), max(vc)]}
 
 
+def bench_stack_gradient(gdf, torch, dev, shape, steps):
+    """The transpose of the smoothing (the gradient through it) on an FP32
+    gradient of the headline stack's shape: three separable passes."""
+    g = torch.randn(shape, device=dev, dtype=torch.float32)
+    log("stack gradient: timing")
+    ms, out = _timed(torch, lambda: gdf.smooth_transpose(g, 1.0, 3.0), steps, 1)
+    n = g.numel()
+    del out, g
+    return {"value": n / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+            "workload": "smooth_transpose (dLoss/dstack through the smoothing) on a %d x %d x %d FP32 gradient, "
+                        "sigma_xy=1, sigma_z=3" % tuple(shape),
+            "algo_GBps": 3 * 2 * 4 * n / (ms * 1e-3) / 1e9}
+
+
 def bench_adjoint(gdf, torch, dev, steps):
     """16 x 1024 x 1024 FP32: loss = sum (f - t)^2 through the autograd function."""
     S4, H4, W4 = 16, 1024, 1024
@@ -361,6 +375,7 @@ def main():
         torch.cuda.empty_cache()
         forms["adjoint"] = bench_adjoint(gdf, torch, dev, 5)
         forms["robust"] = bench_robust(gdf, torch, dev, stack, kw, 3)
+        forms["stack_gradient"] = bench_stack_gradient(gdf, torch, dev, stack.shape, 5)
         for v in forms.values():
             v["vs_plain"] = v["value"] / plain
         out["forms"] = forms

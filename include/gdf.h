@@ -231,6 +231,28 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *desc_host, int dty
 int gdf_autotune_last(gdf_solve_opts *opts_host);
 
 /* ------------------------------------------------------------------------ */
+/* Gradient through the smoothing (derived from Section III-A; the paper does
+ * not differentiate).  The smoothing maps a stack I0 to I1(p) = sum_q K(q - p)
+ * I0(q) / D(p), K the truncated anisotropic Gaussian (radius floor(3 sigma)
+ * per axis) and D(p) the sum of its in-stack weights.  smooth_transpose
+ * applies the transpose: out(q) = sum_p K(q - p) grad(p) / D(p), the gradient
+ * of a loss with respect to the stack given grad = dLoss/dI1.  Together with
+ * solve_slices_backward (dLoss/dg_s, dLoss/dg_o) it differentiates
+ * fuse_stack: dLoss/dstack = smooth_transpose(dLoss/dg_s) + dLoss/dg_o.
+ *
+ * grad_dev, out_dev  [S][H][W] FP32 device buffers, contiguous; out_dev must
+ *                    not alias grad_dev.
+ * sigma_xy, sigma_z  as for fuse_stack (in-plane radius <= 7, cross-slice
+ *                    radius <= 12).
+ * workspace          gdf_smooth_transpose_workspace_size(S, H, W) bytes of
+ *                    device memory owned by the caller.
+ * Returns GDF_EINVAL / GDF_EUNSUPPORTED on bad arguments (nothing launched),
+ * GDF_EDEVICE on a HIP error.  Asynchronous on `stream`.                     */
+size_t gdf_smooth_transpose_workspace_size(int S, int H, int W);
+gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
+                            float *out_dev, void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Kernel timing for measurement.  When enabled, the library brackets every
  * launch of the named kernel class with HIP events on the launch stream and
  * accumulates their durations.  gdf_profile_enable(1) times every class,

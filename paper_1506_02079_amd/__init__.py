@@ -76,6 +76,8 @@ SIGNATURES = {
     "solve_slices_backward": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _P, _P, _I, _D, _P, _P,
                                ctypes.POINTER(_D), ctypes.POINTER(SolveOpts), _P, _S,
                                ctypes.POINTER(SliceReport), _P], _I),
+    "gdf_smooth_transpose_workspace_size": ([_I, _I, _I], _S),
+    "smooth_transpose": ([_P, _I, _I, _I, _D, _D, _P, _P, _S, _P], _I),
 }
 
 
@@ -351,6 +353,40 @@ def solve_slices_backward(grad_f, f, g_s, alpha, bc="neumann", tol=1e-6, precisi
     _check(st, allow_noconv)
     galpha = torch.tensor([ga[i] for i in range(S)], dtype=torch.float64) if need[2] else None
     return ggs, ggo, galpha, _report_list(rep, S)
+
+
+def smooth_transpose(grad, sigma_xy=1.0, sigma_z=3.0):
+    """Transpose of the smoothing: dLoss/dstack for grad = dLoss/d(smoothed
+    stack), FP32 [S, H, W] (see smooth_transpose in include/gdf.h)."""
+    torch = _torch()
+    _require_cuda(grad)
+    if grad.dim() != 3:
+        raise ValueError("grad must be [S, H, W]")
+    g = grad.to(torch.float32).contiguous()
+    S, H, W = g.shape
+    L = lib()
+    ws = L.gdf_smooth_transpose_workspace_size(S, H, W)
+    if ws == 0:
+        raise GdfError(GDF_EINVAL, "S, H, W must be >= 1")
+    work = torch.empty(ws, dtype=torch.uint8, device=g.device)
+    out = torch.empty_like(g)
+    st = L.smooth_transpose(g.data_ptr(), S, H, W, float(sigma_xy), float(sigma_z), out.data_ptr(),
+                            work.data_ptr(), ws, _stream(g.device))
+    _check(st)
+    return out
+
+
+def fuse_stack_backward(grad_f, f, stack, alpha, sigma_xy=1.0, sigma_z=3.0, tol=1e-6, **kw):
+    """Gradient of a loss through fuse_stack with respect to the stack, the stack
+    taken as real-valued: dLoss/dstack = smooth_transpose(dLoss/dg_s) + dLoss/dg_o,
+    with dLoss/dg_s and dLoss/dg_o from the adjoint solve (solve_slices_backward).
+    grad_f, f: FP32 [S, H, W]; returns (dLoss/dstack FP32, report)."""
+    torch = _torch()
+    g32 = grad_f.to(torch.float32).contiguous()
+    f32 = f.to(torch.float32).contiguous()
+    # (g_s only enters dLoss/dalpha, which is not asked for)
+    ggs, ggo, _, rep = solve_slices_backward(g32, f32, f32, alpha, tol=tol, need=(True, True, False), **kw)
+    return smooth_transpose(ggs, sigma_xy, sigma_z) + ggo, rep
 
 
 def _make_autograd():

@@ -1350,6 +1350,63 @@ static size_t fuse_workspace_plain(int S, int H, int W, const gdf_solve_opts *op
     return std::max({P->total, Q->total, escalation_bytes(o, H, W, 1e-12)});
 }
 
+// ------------------------------------------------- gradient through smoothing
+
+static size_t transpose_tmp_bytes(int S, int H, int W)
+{
+    return ((size_t)S * H * W * sizeof(float) + 255) / 256 * 256;
+}
+
+size_t gdf_smooth_transpose_workspace_size(int S, int H, int W)
+{
+    if (S < 1 || H < 1 || W < 1) return 0;
+    return transpose_tmp_bytes(S, H, W) + sizeof(float) * ((size_t)S + H + W);
+}
+
+gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
+                            float *out_dev, void *workspace, size_t ws_bytes, void *stream)
+{
+    if (S < 1 || H < 1 || W < 1) return set_err(GDF_EINVAL, "S, H, W must be >= 1 (got %d, %d, %d)", S, H, W);
+    if (!grad_dev || !out_dev || !workspace) return set_err(GDF_EINVAL, "grad, out and workspace must be non-null");
+    if (grad_dev == out_dev) return set_err(GDF_EINVAL, "out must not alias grad");
+    if (!(sigma_xy >= 0.0) || !(sigma_z >= 0.0) || !std::isfinite(sigma_xy) || !std::isfinite(sigma_z))
+        return set_err(GDF_EINVAL, "sigma_xy and sigma_z must be finite and >= 0");
+    const int rxy = sigma_xy > 0 ? (int)std::floor(3.0 * sigma_xy) : 0;
+    const int rz = sigma_z > 0 ? (int)std::floor(3.0 * sigma_z) : 0;
+    if (rxy > 7 || rz > 12)
+        return set_err(GDF_EUNSUPPORTED, "smoothing radius beyond 7 (xy) or 12 (z) taps is not supported");
+    const size_t need = gdf_smooth_transpose_workspace_size(S, H, W);
+    if (ws_bytes < need) return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+    // taps exp(-d^2 / 2 sigma^2) and the per-axis in-range weight sums
+    double wxy[8] = {0}, wz[16] = {0};
+    for (int d = 0; d <= rxy; ++d) wxy[d] = sigma_xy > 0 ? std::exp(-(double)d * d / (2 * sigma_xy * sigma_xy)) : 1.0;
+    for (int d = 0; d <= rz; ++d) wz[d] = sigma_z > 0 ? std::exp(-(double)d * d / (2 * sigma_z * sigma_z)) : 1.0;
+    auto inv_sums = [](int n, int r, const double *w, std::vector<float> &out) {
+        for (int c = 0; c < n; ++c) {
+            double sum = 0.0;
+            for (int d = -r; d <= r; ++d)
+                if (c + d >= 0 && c + d < n) sum += w[d < 0 ? -d : d];
+            out.push_back((float)(1.0 / sum));
+        }
+    };
+    std::vector<float> tab;
+    tab.reserve((size_t)S + H + W);
+    inv_sums(S, rz, wz, tab);
+    inv_sums(H, rxy, wxy, tab);
+    inv_sums(W, rxy, wxy, tab);
+    float wxyf[8], wzf[16];
+    for (int d = 0; d < 8; ++d) wxyf[d] = (float)wxy[d];
+    for (int d = 0; d < 16; ++d) wzf[d] = (float)wz[d];
+    char *ws = static_cast<char *>(workspace);
+    float *tmp = reinterpret_cast<float *>(ws);
+    float *inv_d = reinterpret_cast<float *>(ws + transpose_tmp_bytes(S, H, W));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(inv_d, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));   // (pageable source: release it only after the copy)
+    HIP_TRY(launch_smooth_transpose(grad_dev, out_dev, tmp, inv_d, S, H, W, rxy, rz, wxyf, wzf, s));
+    return GDF_OK;
+}
+
 size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
 {
     const gdf_solve_opts b = opts_or_zero(opts);

@@ -339,3 +339,37 @@ def test_robust_averaging_matches_oracle(precision):
     fr = oracle.solve_stack(gs, st.astype(np.float64), 0.01, tol=1e-12)
     assert np.abs(f.cpu().numpy() - fr).max() <= 1e-3
     assert all(r["status"] == gdf.GDF_OK for r in rep)
+
+
+@pytest.mark.parametrize("shape,sxy,sz", [((9, 37, 70), 1.0, 3.0), ((4, 20, 9), 2.0, 1.0), ((6, 33, 40), 0.0, 4.0)])
+def test_smooth_transpose_matches_oracle(shape, sxy, sz):
+    rng = np.random.default_rng(sum(shape))
+    g = rng.standard_normal(shape)
+    out = gdf.smooth_transpose(torch.from_numpy(g).to(DEV, torch.float32), sxy, sz)
+    torch.cuda.synchronize()
+    ref = oracle.smooth_transpose(g, sxy, sz)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-6
+
+
+def test_fuse_stack_backward_matches_oracle():
+    # dLoss/dstack = S^T (alpha lambda) + L lambda, lambda = A^-1 dLoss/df per
+    # slice; the oracle's adjoint and transposed smoothing are pinned separately
+    stack = synth.make_stack(6, 48, 64, seed=61, ramp=True)
+    t = torch.from_numpy(stack).to(DEV)
+    f, rep = gdf.fuse_stack(t, 0.02, tol=1e-8, precision="mixed", out_dtype=gdf.DTYPE_F64)
+    rng = np.random.default_rng(3)
+    gf = rng.standard_normal(stack.shape)
+    gst, rep_b = gdf.fuse_stack_backward(torch.from_numpy(gf).to(DEV, torch.float32), f.to(torch.float32), t, 0.02,
+                                         tol=1e-7)
+    torch.cuda.synchronize()
+    f64 = f.cpu().numpy()
+    gs = oracle.smooth(stack)
+    dgs = np.empty_like(gf)
+    dgo = np.empty_like(gf)
+    for z in range(stack.shape[0]):
+        a, b, _ = oracle.adjoint(gf[z], gs[z], f64[z], 0.02, tol=1e-12)
+        dgs[z], dgo[z] = a, b
+    ref = oracle.smooth_transpose(dgs) + dgo
+    err = np.abs(gst.cpu().numpy() - ref).max()
+    print("stack gradient max err", err, "scale", np.abs(ref).max())
+    assert err <= 1e-3 * np.abs(ref).max()
