@@ -202,6 +202,24 @@ def bench_stack_gradient(gdf, torch, dev, shape, steps):
             "algo_GBps": 3 * 2 * 4 * n / (ms * 1e-3) / 1e9}
 
 
+def bench_color(gdf, torch, dev, steps):
+    """Colour fusion: 3 channels of 4096 x 4096 (low-frequency colour) with one
+    grey image's gradients, FP32 to 1e-6, one batch."""
+    C, H, W = 3, 4096, 4096
+    grey, _ = synth.batch_slice_t(H, W, 7, dev)
+    grey = grey.to(torch.float32)
+    color = torch.stack([grey * 0.6 + 40.0, grey * 0.9, 200.0 - 0.5 * grey])
+    color = torch.nn.functional.avg_pool2d(color[None], 9, stride=1, padding=4, count_include_pad=False)[0]
+    log("color: timing")
+    ms, (f, rep) = _timed(torch, lambda: gdf.fuse_color(color.contiguous(), grey, 0.01, tol=1e-6), steps, 1)
+    del f
+    vc = [r["vcycles"] for r in rep]
+    return {"value": C * H * W / (ms * 1e-3) / 1e6, "unit": "Mpixels/s (all channels)", "ms_per_step": ms,
+            "steps": steps, "workload": "fuse_color: 3 x 4096 x 4096 FP32 colour target with the gradients of "
+                                        "one grey image, alpha 0.01, tol 1e-6",
+            "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+
+
 def bench_adjoint(gdf, torch, dev, steps):
     """16 x 1024 x 1024 FP32: loss = sum (f - t)^2 through the autograd function."""
     S4, H4, W4 = 16, 1024, 1024
@@ -376,6 +394,7 @@ def main():
         forms["adjoint"] = bench_adjoint(gdf, torch, dev, 5)
         forms["robust"] = bench_robust(gdf, torch, dev, stack, kw, 3)
         forms["stack_gradient"] = bench_stack_gradient(gdf, torch, dev, stack.shape, 5)
+        forms["color"] = bench_color(gdf, torch, dev, 3)
         for v in forms.values():
             v["vs_plain"] = v["value"] / plain
         out["forms"] = forms

@@ -389,6 +389,22 @@ def fuse_stack_backward(grad_f, f, stack, alpha, sigma_xy=1.0, sigma_z=3.0, tol=
     return smooth_transpose(ggs, sigma_xy, sigma_z) + ggo, rep
 
 
+def fuse_color(color, grey, alpha, tol=1e-6, **kw):
+    """Fusion of a low-frequency colour image with a high-frequency grey one
+    ("Extensions and Applications"): each channel c solves Eq. (1) with the
+    channel as the value constraint and the grey image's gradients,
+    (alpha I + L) f_c = alpha color_c + L grey, as one batch of solve_slices.
+    color: [C, H, W], grey: [H, W] (float32 or float64, on the GPU); returns
+    (f [C, H, W], report)."""
+    torch = _torch()
+    _require_cuda(color, grey)
+    if color.dim() != 3 or grey.dim() != 2 or tuple(color.shape[1:]) != tuple(grey.shape):
+        raise ValueError("color must be [C, H, W] and grey [H, W] of the same H, W")
+    C = color.shape[0]
+    go = grey.to(color.dtype).contiguous()
+    return solve_slices([color[c] for c in range(C)], [go] * C, alpha, tol=tol, **kw)
+
+
 def _make_autograd():
     torch = _torch()
 

@@ -373,3 +373,21 @@ def test_fuse_stack_backward_matches_oracle():
     err = np.abs(gst.cpu().numpy() - ref).max()
     print("stack gradient max err", err, "scale", np.abs(ref).max())
     assert err <= 1e-3 * np.abs(ref).max()
+
+
+def test_fuse_color_matches_oracle():
+    # colour value constraints with grey gradients: each channel is Eq. (1)
+    # with g_s the channel and g_o the grey image
+    rng = np.random.default_rng(17)
+    H, W = 90, 130
+    base, _ = synth.batch_slice(H, W, 5)
+    grey = base.astype(np.float64)
+    color = np.stack([grey * 0.6 + 40, grey * 0.9, 200 - grey * 0.5]) + rng.normal(0, 2, (3, H, W))
+    blur = oracle.smooth(np.clip(color, 0, 255).astype(np.uint8), 4.0, 0.0)   # low-frequency colour
+    f, rep = gdf.fuse_color(torch.from_numpy(blur).to(DEV), torch.from_numpy(grey).to(DEV), 0.01, tol=1e-8,
+                            precision="fp64")
+    torch.cuda.synchronize()
+    for c in range(3):
+        ref = oracle.solve(blur[c], grey, 0.01, tol=1e-12)
+        assert np.abs(f[c].cpu().numpy() - ref).max() <= 1e-4
+        assert rep[c]["status"] == gdf.GDF_OK
