@@ -26,53 +26,52 @@ struct AxisArgs {
     float w[16];          // taps w[0..r]
 };
 
-// x: one thread per voxel (the taps are neighbours in the same cache lines).
-// y and z: one thread per segment of kSeg voxels along the axis, marching down
-// it, so the taps of consecutive outputs are the same few rows or planes,
-// still in the caches (and enough segments to fill the GPU).
+// One thread per column x of a row, with the grid's y and z dimensions over
+// the other two coordinates (no index division).  x pass: one output per
+// thread (its taps are neighbours in the same cache lines).  y and z passes:
+// each thread marches a segment of kSeg outputs down its line, so the taps of
+// consecutive outputs are the same few rows or planes, still in the caches.
 __global__ __launch_bounds__(256) void transpose_axis_kernel(AxisArgs a)
 {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.W) return;
     const long long plane = (long long)a.H * a.W;
-    const long long stride = a.axis == 0 ? 1 : (a.axis == 1 ? (long long)a.W : plane);
     const int len = a.axis == 0 ? a.W : (a.axis == 1 ? a.H : a.S);
-    // lines along the axis: x lines are single voxels here (len 1 marched)
-    const long long nlines = a.axis == 0 ? (long long)a.S * plane : (a.axis == 1 ? (long long)a.S * a.W : plane);
-    const int seg = a.axis == 0 ? 1 : kSeg;
-    const int nseg = (len + seg - 1) / seg;
-    const long long nwork = a.axis == 0 ? nlines : nlines * nseg;
-    for (long long wi = (long long)blockIdx.x * blockDim.x + threadIdx.x; wi < nwork;
-         wi += (long long)gridDim.x * blockDim.x) {
-        // segments outermost, so neighbouring threads take neighbouring lines
-        const long long l = a.axis == 0 ? wi : wi % nlines;
-        const int t0 = a.axis == 0 ? 0 : (int)(wi / nlines) * seg;
-        const int t1 = a.axis == 0 ? 1 : min(t0 + seg, len);
-        long long base;   // index of the line's first voxel
-        if (a.axis == 0) base = l;
-        else if (a.axis == 1) base = (l / a.W) * plane + (l % a.W);   // (z, x)
-        else base = l;                                               // (y, x) in plane 0
-        for (int t = t0; t < t1; ++t) {
-            const long long i = base + (long long)t * (a.axis == 0 ? 0 : stride);
-            const int x = (int)(i % a.W);
-            const int y = (int)((i / a.W) % a.H);
-            const int z = (int)(i / plane);
-            const int c = a.axis == 0 ? x : (a.axis == 1 ? y : z);
-            const int lo = max(-a.r, -c), hi = min(a.r, len - 1 - c);
-            float acc = 0.f;
-            if (a.inv_d) {
-                // the source voxel's 1 / D; along the pass axis it changes per tap
-                const float *iz = a.inv_d;
-                const float *iy = a.inv_d + a.S;
-                const float *ix = a.inv_d + a.S + a.H;
-                for (int d = lo; d <= hi; ++d) {
-                    const int zz = a.axis == 2 ? z + d : z, yy = a.axis == 1 ? y + d : y, xx = a.axis == 0 ? x + d : x;
-                    acc = fmaf(a.w[d < 0 ? -d : d] * (iz[zz] * iy[yy] * ix[xx]), a.in[i + d * stride], acc);
-                }
-            } else {
-                for (int d = lo; d <= hi; ++d) acc = fmaf(a.w[d < 0 ? -d : d], a.in[i + d * stride], acc);
+    const long long stride = a.axis == 0 ? 1 : (a.axis == 1 ? (long long)a.W : plane);
+    // grid y / z: (y, z) for the x pass, (segment, z) for y, (y, segment) for z
+    const int gy_n = a.axis == 1 ? (a.H + kSeg - 1) / kSeg : a.H;
+    const int gz_n = a.axis == 2 ? (a.S + kSeg - 1) / kSeg : a.S;
+    const float *iz = a.inv_d, *iy = a.inv_d + a.S, *ix = a.inv_d + a.S + a.H;
+    for (int gz = blockIdx.z; gz < gz_n; gz += gridDim.z)
+        for (int gy = blockIdx.y; gy < gy_n; gy += gridDim.y) {
+            int y = gy, z = gz, t0 = 0, t1 = 1;
+            if (a.axis == 1) {
+                t0 = gy * kSeg;
+                t1 = min(t0 + kSeg, a.H);
+            } else if (a.axis == 2) {
+                t0 = gz * kSeg;
+                t1 = min(t0 + kSeg, a.S);
             }
-            a.out[i] = acc;
+            for (int t = t0; t < t1; ++t) {
+                if (a.axis == 1) y = t;
+                else if (a.axis == 2) z = t;
+                const long long i = ((long long)z * a.H + y) * a.W + x;
+                const int c = a.axis == 0 ? x : (a.axis == 1 ? y : z);
+                const int lo = max(-a.r, -c), hi = min(a.r, len - 1 - c);
+                float acc = 0.f;
+                if (a.inv_d) {
+                    // the source voxel's 1 / D; along the pass axis it changes per tap
+                    for (int d = lo; d <= hi; ++d) {
+                        const int zz = a.axis == 2 ? z + d : z, yy = a.axis == 1 ? y + d : y;
+                        const int xx = a.axis == 0 ? x + d : x;
+                        acc = fmaf(a.w[d < 0 ? -d : d] * (iz[zz] * iy[yy] * ix[xx]), a.in[i + d * stride], acc);
+                    }
+                } else {
+                    for (int d = lo; d <= hi; ++d) acc = fmaf(a.w[d < 0 ? -d : d], a.in[i + d * stride], acc);
+                }
+                a.out[i] = acc;
+            }
         }
-    }
 }
 
 }  // namespace
@@ -96,10 +95,10 @@ hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const
         a.in = src[p];
         a.out = dst[p];
         a.inv_d = p == 0 ? inv_d : nullptr;
-        const long long lines = p == 0 ? n : (p == 1 ? (long long)S * W * ((H + kSeg - 1) / kSeg)
-                                                     : (long long)H * W * ((S + kSeg - 1) / kSeg));
-        const int blocks = (int)std::min<long long>((lines + 255) / 256, 65536);
-        hipLaunchKernelGGL(transpose_axis_kernel, dim3(blocks), dim3(256), 0, s, a);
+        const int gy = p == 1 ? (H + kSeg - 1) / kSeg : H;
+        const int gz = p == 2 ? (S + kSeg - 1) / kSeg : S;
+        const dim3 grid((unsigned)((W + 255) / 256), (unsigned)std::min(gy, 65535), (unsigned)std::min(gz, 65535));
+        hipLaunchKernelGGL(transpose_axis_kernel, grid, dim3(256), 0, s, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
