@@ -34,6 +34,10 @@
  *    loss with gradient gbar = dLoss/df, lambda = A^{-1} gbar,
  *    dLoss/dg_s = alpha lambda, dLoss/dg_o = L lambda,
  *    dLoss/dalpha = lambda . (g_s - f).
+ *  - Gradient through the smoothing (derived): the transpose of the linear
+ *    map stack -> smoothed stack, see oracle_smooth_transpose.
+ *  - Robust averaging ("Extensions and Applications"): see
+ *    oracle_smooth_robust_voxel for the reading taken.
  */
 #include <math.h>
 #include <stddef.h>
