@@ -13,6 +13,8 @@ Laplacian g_o, to a relative residual tolerance.
 from __future__ import annotations
 
 import ctypes
+
+import numpy as np
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -403,6 +405,66 @@ def fuse_color(color, grey, alpha, tol=1e-6, **kw):
     C = color.shape[0]
     go = grey.to(color.dtype).contiguous()
     return solve_slices([color[c] for c in range(C)], [go] * C, alpha, tol=tol, **kw)
+
+
+def fuse_stack_streamed(stack, alpha, chunk=32, out=None, sigma_xy=1.0, sigma_z=3.0, tol=1e-6, **kw):
+    """fuse_stack for stacks kept in host memory (larger than HBM).
+
+    stack: uint8 [S, H, W] CPU tensor (pinned, for overlapped uploads).  Slices
+    are processed `chunk` at a time; each chunk is uploaded with the
+    floor(3 sigma_z) slices on either side that its smoothing reads, so every
+    slice's result equals the whole-stack one (the solve is per slice; the halo
+    slices are solved too and dropped).  The next chunk's upload runs on a side
+    stream while the current chunk computes, and each chunk's result goes back
+    on a third stream while the next one computes.  Returns (f float32 [S, H, W] in
+    pinned host memory, or `out`; the per-slice reports)."""
+    torch = _torch()
+    if stack.device.type != "cpu" or stack.dtype != torch.uint8 or stack.dim() != 3:
+        raise ValueError("stack must be a uint8 [S, H, W] tensor in host memory")
+    if chunk < 1:
+        raise ValueError("chunk must be >= 1")
+    S, H, W = stack.shape
+    rz = int(np.floor(3.0 * sigma_z)) if sigma_z > 0 else 0
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if out is None:
+        out = torch.empty((S, H, W), dtype=torch.float32, pin_memory=True)
+    span = min(S, chunk + 2 * rz)
+    bufs = [torch.empty((span, H, W), dtype=torch.uint8, device=dev) for _ in range(2)]
+    freed = [torch.cuda.Event(), torch.cuda.Event()]   # chunk done with a buffer
+    ready = [torch.cuda.Event(), torch.cuda.Event()]   # upload landed
+    copy = torch.cuda.Stream(device=dev)               # uploads (default priority)
+    down = torch.cuda.Stream(device=dev)               # downloads (default priority)
+    main = torch.cuda.current_stream(dev)
+    starts = list(range(0, S, chunk))
+    reports = []
+
+    def upload(c):
+        z0 = starts[c]
+        lo, hi = max(z0 - rz, 0), min(z0 + chunk + rz, S)
+        b = c % 2
+        with torch.cuda.stream(copy):
+            if c >= 2:
+                copy.wait_event(freed[b])
+            bufs[b][:hi - lo].copy_(stack[lo:hi], non_blocking=True)
+            ready[b].record(copy)
+
+    upload(0)
+    for c, z0 in enumerate(starts):
+        if c + 1 < len(starts):
+            upload(c + 1)
+        b = c % 2
+        z1 = min(z0 + chunk, S)
+        lo, hi = max(z0 - rz, 0), min(z0 + chunk + rz, S)
+        main.wait_event(ready[b])
+        f, rep = fuse_stack(bufs[b][:hi - lo], alpha, tol=tol, sigma_xy=sigma_xy, sigma_z=sigma_z, **kw)
+        freed[b].record(main)
+        down.wait_stream(main)
+        with torch.cuda.stream(down):
+            out[z0:z1].copy_(f[z0 - lo:z1 - lo], non_blocking=True)
+        f.record_stream(down)      # the allocator keeps f until the download ends
+        reports += rep[z0 - lo:z1 - lo]
+    torch.cuda.synchronize(dev)
+    return out, reports
 
 
 def _make_autograd():

@@ -139,3 +139,11 @@ def test_autotune_flag_and_workspace():
     small = L.gdf_fuse_workspace_size(8, 1000, 700, ctypes.byref(gdf.make_opts(tile_rows=32)))
     # candidates include 32-row items (more items, larger work tables)
     assert tuned >= max(plain, small) > 0
+
+
+def test_streamed_rejects_device_or_float_stacks():
+    import torch
+    with pytest.raises(ValueError):
+        gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.float32), 0.01)
+    with pytest.raises(ValueError):
+        gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.uint8), 0.01, chunk=0)
