@@ -1391,9 +1391,9 @@ gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double s
     };
     std::vector<float> tab;
     tab.reserve((size_t)S + H + W);
-    inv_sums(S, rz, wz, tab);
+    inv_sums(W, rxy, wxy, tab);   // 1 / Dx first: it starts on the workspace's 256-byte boundary
     inv_sums(H, rxy, wxy, tab);
-    inv_sums(W, rxy, wxy, tab);
+    inv_sums(S, rz, wz, tab);
     float wxyf[8], wzf[16];
     for (int d = 0; d < 8; ++d) wxyf[d] = (float)wxy[d];
     for (int d = 0; d < 16; ++d) wzf[d] = (float)wz[d];

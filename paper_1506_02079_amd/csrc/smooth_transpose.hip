@@ -9,6 +9,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <cstdint>
 
 namespace gdf {
 
@@ -17,7 +18,7 @@ namespace {
 struct XArgs {
     const float *in;
     float *out;
-    const float *inv_d;   // 1 / Dz, 1 / Dy, 1 / Dx tables (S, H, W)
+    const float *inv_d;   // 1 / Dx, 1 / Dy, 1 / Dz tables (W, H, S)
     int S, H, W;
     int r;                // in-plane tap radius
     float w[8];           // taps w[0..r]
@@ -30,7 +31,7 @@ __global__ __launch_bounds__(256) void transpose_x_kernel(XArgs a)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.W) return;
-    const float *iz = a.inv_d, *iy = a.inv_d + a.S, *ix = a.inv_d + a.S + a.H;
+    const float *ix = a.inv_d, *iy = a.inv_d + a.W, *iz = a.inv_d + a.W + a.H;
     const int lo = max(-a.r, -x), hi = min(a.r, a.W - 1 - x);
     for (int z = blockIdx.z; z < a.S; z += gridDim.z)
         for (int y = blockIdx.y; y < a.H; y += gridDim.y) {
@@ -42,7 +43,79 @@ __global__ __launch_bounds__(256) void transpose_x_kernel(XArgs a)
         }
 }
 
-// z pass with a register ring: one thread per (y, x) column marches down the
+// x pass for rows of a multiple of 4 voxels with 16-byte aligned rows: each
+// thread owns 4 consecutive voxels for kXRows rows.  The 4 + 2R sources it
+// needs arrive as 2K + 1 aligned float4 loads (K = ceil(R / 4)); a float4 is
+// wholly inside or outside the row, and one outside is zero, which drops its
+// taps.  The 1 / Dx factors of those sources stay in registers for all rows.
+constexpr int kXRows = 4;
+
+template <int R>
+__global__ __launch_bounds__(256) void transpose_x4_kernel(XArgs a)
+{
+    constexpr int K = (R + 3) / 4;
+    constexpr int NV = 4 * (2 * K + 1);
+    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (x0 >= a.W) return;
+    const float *iy = a.inv_d + a.W, *iz = a.inv_d + a.W + a.H;
+    float sx[NV];
+#pragma unroll
+    for (int g = -K; g <= K; ++g) {
+        const int xg = x0 + 4 * g;
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (xg >= 0 && xg < a.W) t = *reinterpret_cast<const float4 *>(a.inv_d + xg);
+        const int j = 4 * (g + K);
+        sx[j] = t.x;
+        sx[j + 1] = t.y;
+        sx[j + 2] = t.z;
+        sx[j + 3] = t.w;
+    }
+    for (int z = blockIdx.z; z < a.S; z += gridDim.z)
+        for (int yb = blockIdx.y * kXRows; yb < a.H; yb += gridDim.y * kXRows) {
+            const int ye = min(yb + kXRows, a.H);
+            for (int y = yb; y < ye; ++y) {
+                const long long row = ((long long)z * a.H + y) * a.W;
+                float v[NV];
+#pragma unroll
+                for (int g = -K; g <= K; ++g) {
+                    const int xg = x0 + 4 * g;
+                    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (xg >= 0 && xg < a.W) t = *reinterpret_cast<const float4 *>(a.in + row + xg);
+                    const int j = 4 * (g + K);
+                    v[j] = t.x * sx[j];
+                    v[j + 1] = t.y * sx[j + 1];
+                    v[j + 2] = t.z * sx[j + 2];
+                    v[j + 3] = t.w * sx[j + 3];
+                }
+                const float izy = iz[z] * iy[y];
+                float o[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    float acc = 0.f;
+#pragma unroll
+                    for (int d = -R; d <= R; ++d) acc = fmaf(a.w[d < 0 ? -d : d], v[4 * K + t + d], acc);
+                    o[t] = acc * izy;
+                }
+                *reinterpret_cast<float4 *>(a.out + row + x0) = make_float4(o[0], o[1], o[2], o[3]);
+            }
+        }
+}
+
+// Element arithmetic of the ring passes, for one column (float) or four
+// neighbouring columns (float4).
+typedef float vec4f __attribute__((ext_vector_type(4)));   // a register vector, 16-byte aligned
+
+__device__ inline float vzero(float) { return 0.f; }
+__device__ inline vec4f vzero(vec4f) { return vec4f{0.f, 0.f, 0.f, 0.f}; }
+__device__ inline float vmul(float w, float a) { return w * a; }
+__device__ inline vec4f vmul(float w, vec4f a) { return vec4f{w * a.x, w * a.y, w * a.z, w * a.w}; }
+__device__ inline float vfma(float w, float a, float b, float c) { return fmaf(w, a + b, c); }
+__device__ inline vec4f vfma(float w, vec4f a, vec4f b, vec4f c)
+{
+    return vec4f{fmaf(w, a.x + b.x, c.x), fmaf(w, a.y + b.y, c.y), fmaf(w, a.z + b.z, c.z), fmaf(w, a.w + b.w, c.w)};
+}
+
+// z pass with a register ring: one thread per (y, x) column (or 4 columns) marches down the
 // slices holding in[z - R .. z + R]; each input is read once.  Values outside
 // the stack are zero in the ring, which drops their taps (the transpose's
 // correlation has no renormalisation).  The march is unrolled by the ring
@@ -51,28 +124,30 @@ struct Taps {
     float w[16];
 };
 
-template <int R>
-__global__ __launch_bounds__(256) void transpose_z_ring(const float *in, float *out, int S, long long plane, Taps t)
+template <int R, typename V>
+__global__ __launch_bounds__(256) void transpose_z_ring(const V *in, V *out, int S, long long plane, Taps t)
 {
+    // plane: elements of V per slice
     constexpr int N = 2 * R + 1;
     const long long col = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (col >= plane) return;
-    float ring[N];
+    const V zero = vzero(V{});
+    V ring[N];
 #pragma unroll
-    for (int j = 0; j < N; ++j) ring[j] = 0.f;
+    for (int j = 0; j < N; ++j) ring[j] = zero;
     // slot of slice z' is (z' + R) mod N; preload slices 0 .. R - 1
 #pragma unroll
-    for (int zz = 0; zz < R; ++zz) ring[(zz + R) % N] = zz < S ? in[(long long)zz * plane + col] : 0.f;
+    for (int zz = 0; zz < R; ++zz) ring[(zz + R) % N] = zz < S ? in[(long long)zz * plane + col] : zero;
     for (int zb = 0; zb < S; zb += N) {
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             const int z = zb + k;
             if (z < S) {   // uniform
                 const int zl = z + R;   // slice entering the ring
-                ring[(k + 2 * R) % N] = zl < S ? in[(long long)zl * plane + col] : 0.f;
-                float acc = t.w[0] * ring[(k + R) % N];
+                ring[(k + 2 * R) % N] = zl < S ? in[(long long)zl * plane + col] : zero;
+                V acc = vmul(t.w[0], ring[(k + R) % N]);
 #pragma unroll
-                for (int d = 1; d <= R; ++d) acc = fmaf(t.w[d], ring[(k + R - d) % N] + ring[(k + R + d) % N], acc);
+                for (int d = 1; d <= R; ++d) acc = vfma(t.w[d], ring[(k + R - d) % N], ring[(k + R + d) % N], acc);
                 out[(long long)z * plane + col] = acc;
             }
         }
@@ -84,24 +159,26 @@ __global__ __launch_bounds__(256) void transpose_z_ring(const float *in, float *
 // once by this segment, once by the one above).
 constexpr int kYSeg = 64;
 
-template <int R>
-__global__ __launch_bounds__(256) void transpose_y_ring(const float *in, float *out, int S, int H, int W, Taps t)
+template <int R, typename V>
+__global__ __launch_bounds__(256) void transpose_y_ring(const V *in, V *out, int S, int H, int W, Taps t)
 {
+    // W: elements of V per row
     constexpr int N = 2 * R + 1;
+    const V zero = vzero(V{});
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= W) return;
     const int y0 = blockIdx.y * kYSeg;
     if (y0 >= H) return;
     const int y1 = min(y0 + kYSeg, H);
     for (int z = blockIdx.z; z < S; z += gridDim.z) {
-        const float *col = in + (long long)z * H * W + x;
-        float *ocol = out + (long long)z * H * W + x;
-        float ring[N];
+        const V *col = in + (long long)z * H * W + x;
+        V *ocol = out + (long long)z * H * W + x;
+        V ring[N];
         // slot of row y' is (y' - y0 + R) mod N; preload rows y0 - R .. y0 + R - 1
 #pragma unroll
         for (int j = 0; j < 2 * R; ++j) {
             const int yy = y0 - R + j;
-            ring[j] = (yy >= 0 && yy < H) ? col[(long long)yy * W] : 0.f;
+            ring[j] = (yy >= 0 && yy < H) ? col[(long long)yy * W] : zero;
         }
         for (int yb = y0; yb < y1; yb += N) {
 #pragma unroll
@@ -109,10 +186,10 @@ __global__ __launch_bounds__(256) void transpose_y_ring(const float *in, float *
                 const int y = yb + k;
                 if (y < y1) {   // uniform
                     const int yl = y + R;   // row entering the ring
-                    ring[(k + 2 * R) % N] = yl < H ? col[(long long)yl * W] : 0.f;
-                    float acc = t.w[0] * ring[(k + R) % N];
+                    ring[(k + 2 * R) % N] = yl < H ? col[(long long)yl * W] : zero;
+                    V acc = vmul(t.w[0], ring[(k + R) % N]);
 #pragma unroll
-                    for (int d = 1; d <= R; ++d) acc = fmaf(t.w[d], ring[(k + R - d) % N] + ring[(k + R + d) % N], acc);
+                    for (int d = 1; d <= R; ++d) acc = vfma(t.w[d], ring[(k + R - d) % N], ring[(k + R + d) % N], acc);
                     ocol[(long long)y * W] = acc;
                 }
             }
@@ -120,15 +197,27 @@ __global__ __launch_bounds__(256) void transpose_y_ring(const float *in, float *
     }
 }
 
+bool aligned16(const void *a, const void *b)
+{
+    return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+}
+
 hipError_t launch_y_ring(const float *in, float *out, int S, int H, int W, int rxy, const float *wxy, hipStream_t s)
 {
     Taps t{};
     for (int d = 0; d < 8; ++d) t.w[d] = wxy[d];
     if ((H + kYSeg - 1) / kYSeg > 65535) return hipErrorInvalidValue;   // (H <= 4 M rows)
-    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)((H + kYSeg - 1) / kYSeg), (unsigned)std::min(S, 65535));
+    const bool vec = aligned16(in, out) && W % 4 == 0;
+    const int wv = vec ? W / 4 : W;
+    const dim3 grid((unsigned)((wv + 255) / 256), (unsigned)((H + kYSeg - 1) / kYSeg), (unsigned)std::min(S, 65535));
+    const vec4f *in4 = reinterpret_cast<const vec4f *>(in);
+    vec4f *out4 = reinterpret_cast<vec4f *>(out);
     switch (rxy) {
 #define GDF_YR(R) \
-    case R: hipLaunchKernelGGL(transpose_y_ring<R>, grid, dim3(256), 0, s, in, out, S, H, W, t); break;
+    case R: \
+        if (vec) hipLaunchKernelGGL((transpose_y_ring<R, vec4f>), grid, dim3(256), 0, s, in4, out4, S, H, wv, t); \
+        else hipLaunchKernelGGL((transpose_y_ring<R, float>), grid, dim3(256), 0, s, in, out, S, H, W, t); \
+        break;
         GDF_YR(0) GDF_YR(1) GDF_YR(2) GDF_YR(3) GDF_YR(4) GDF_YR(5) GDF_YR(6) GDF_YR(7)
 #undef GDF_YR
     default: return hipErrorInvalidValue;
@@ -141,10 +230,17 @@ hipError_t launch_z_ring(const float *in, float *out, int S, int H, int W, int r
     Taps t{};
     for (int d = 0; d < 16; ++d) t.w[d] = wz[d];
     const long long plane = (long long)H * W;
-    const dim3 grid((unsigned)((plane + 255) / 256));
+    const bool vec = aligned16(in, out) && plane % 4 == 0;
+    const long long pv = vec ? plane / 4 : plane;
+    const dim3 grid((unsigned)((pv + 255) / 256));
+    const vec4f *in4 = reinterpret_cast<const vec4f *>(in);
+    vec4f *out4 = reinterpret_cast<vec4f *>(out);
     switch (rz) {
 #define GDF_ZR(R) \
-    case R: hipLaunchKernelGGL(transpose_z_ring<R>, grid, dim3(256), 0, s, in, out, S, plane, t); break;
+    case R: \
+        if (vec) hipLaunchKernelGGL((transpose_z_ring<R, vec4f>), grid, dim3(256), 0, s, in4, out4, S, pv, t); \
+        else hipLaunchKernelGGL((transpose_z_ring<R, float>), grid, dim3(256), 0, s, in, out, S, plane, t); \
+        break;
         GDF_ZR(0) GDF_ZR(1) GDF_ZR(2) GDF_ZR(3) GDF_ZR(4) GDF_ZR(5) GDF_ZR(6) GDF_ZR(7) GDF_ZR(8) GDF_ZR(9)
         GDF_ZR(10) GDF_ZR(11) GDF_ZR(12)
 #undef GDF_ZR
@@ -170,8 +266,21 @@ hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const
     a.W = W;
     a.r = rxy;
     for (int d = 0; d < 8; ++d) a.w[d] = wxy[d];
-    const dim3 grid((unsigned)((W + 255) / 256), (unsigned)std::min(H, 65535), (unsigned)std::min(S, 65535));
-    hipLaunchKernelGGL(transpose_x_kernel, grid, dim3(256), 0, s, a);
+    const bool vec = W % 4 == 0 && aligned16(g, out) && aligned16(inv_d, inv_d);
+    if (vec) {
+        const int rows = (H + kXRows - 1) / kXRows;
+        const dim3 grid((unsigned)((W / 4 + 255) / 256), (unsigned)std::min(rows, 65535), (unsigned)std::min(S, 65535));
+        switch (rxy) {
+#define GDF_XR(R) \
+    case R: hipLaunchKernelGGL(transpose_x4_kernel<R>, grid, dim3(256), 0, s, a); break;
+            GDF_XR(0) GDF_XR(1) GDF_XR(2) GDF_XR(3) GDF_XR(4) GDF_XR(5) GDF_XR(6) GDF_XR(7)
+#undef GDF_XR
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        const dim3 grid((unsigned)((W + 255) / 256), (unsigned)std::min(H, 65535), (unsigned)std::min(S, 65535));
+        hipLaunchKernelGGL(transpose_x_kernel, grid, dim3(256), 0, s, a);
+    }
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
     const hipError_t e = launch_y_ring(out, tmp, S, H, W, rxy, wxy, s);
