@@ -241,13 +241,20 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
  * fuse_stack: dLoss/dstack = smooth_transpose(dLoss/dg_s) + dLoss/dg_o.
  *
  * grad_dev, out_dev  [S][H][W] FP32 device buffers, contiguous; out_dev must
- *                    not alias grad_dev.
+ *                    not alias grad_dev.  With W a multiple of 4 and 16-byte
+ *                    aligned buffers and workspace the passes move four
+ *                    voxels per thread; any other shape or alignment is
+ *                    accepted and takes one-voxel passes (equal up to FP32
+ *                    rounding order).
  * sigma_xy, sigma_z  as for fuse_stack (in-plane radius <= 7, cross-slice
  *                    radius <= 12).
  * workspace          gdf_smooth_transpose_workspace_size(S, H, W) bytes of
  *                    device memory owned by the caller.
- * Returns GDF_EINVAL / GDF_EUNSUPPORTED on bad arguments (nothing launched),
- * GDF_EDEVICE on a HIP error.  Asynchronous on `stream`.                     */
+ * Returns GDF_EINVAL / GDF_EUNSUPPORTED on bad arguments and GDF_ENOMEM for a
+ * workspace smaller than the query (nothing launched), GDF_EDEVICE on a HIP
+ * error.  The call waits for earlier work on `stream` while it copies the
+ * weight tables from host memory; the three passes then run asynchronously
+ * on `stream`.                                                               */
 size_t gdf_smooth_transpose_workspace_size(int S, int H, int W);
 gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
                             float *out_dev, void *workspace, size_t ws_bytes, void *stream);

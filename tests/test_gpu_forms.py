@@ -357,6 +357,29 @@ def test_smooth_transpose_matches_oracle(shape, sxy, sz):
     assert np.abs(out.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-6
 
 
+def test_smooth_transpose_unaligned_buffers():
+    """Buffers 4 bytes off a 16-byte boundary (W a multiple of 4) take the
+    one-voxel passes through the C ABI; both agree with the oracle."""
+    S, H, W = 5, 21, 64
+    n = S * H * W
+    g = np.random.default_rng(5).standard_normal((S, H, W))
+    buf_g = torch.zeros(n + 4, dtype=torch.float32, device=DEV)
+    buf_o = torch.zeros(n + 4, dtype=torch.float32, device=DEV)
+    buf_g[1:1 + n] = torch.from_numpy(g.reshape(-1)).to(DEV, torch.float32)
+    L = gdf.lib()
+    ws = L.gdf_smooth_transpose_workspace_size(S, H, W)
+    work = torch.empty(ws + 16, dtype=torch.uint8, device=DEV)
+    print("unaligned transpose", (S, H, W), flush=True)
+    st = L.smooth_transpose(buf_g.data_ptr() + 4, S, H, W, 1.0, 3.0, buf_o.data_ptr() + 4,
+                            work.data_ptr() + 4, ws, gdf._stream(DEV))
+    assert st == 0, gdf.last_error()
+    torch.cuda.synchronize()
+    out = buf_o[1:1 + n].cpu().numpy().reshape(S, H, W)
+    ref = oracle.smooth_transpose(g, 1.0, 3.0)
+    assert np.abs(out - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-6
+    assert float(buf_o[0]) == 0.0 and float(buf_o[1 + n]) == 0.0   # nothing written outside
+
+
 def test_fuse_stack_backward_matches_oracle():
     # dLoss/dstack = S^T (alpha lambda) + L lambda, lambda = A^-1 dLoss/df per
     # slice; the oracle's adjoint and transposed smoothing are pinned separately
