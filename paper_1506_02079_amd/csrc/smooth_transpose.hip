@@ -43,64 +43,6 @@ __global__ __launch_bounds__(256) void transpose_x_kernel(XArgs a)
         }
 }
 
-// x pass for rows of a multiple of 4 voxels with 16-byte aligned rows: each
-// thread owns 4 consecutive voxels for kXRows rows.  The 4 + 2R sources it
-// needs arrive as 2K + 1 aligned float4 loads (K = ceil(R / 4)); a float4 is
-// wholly inside or outside the row, and one outside is zero, which drops its
-// taps.  The 1 / Dx factors of those sources stay in registers for all rows.
-constexpr int kXRows = 4;
-
-template <int R>
-__global__ __launch_bounds__(256) void transpose_x4_kernel(XArgs a)
-{
-    constexpr int K = (R + 3) / 4;
-    constexpr int NV = 4 * (2 * K + 1);
-    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (x0 >= a.W) return;
-    const float *iy = a.inv_d + a.W, *iz = a.inv_d + a.W + a.H;
-    float sx[NV];
-#pragma unroll
-    for (int g = -K; g <= K; ++g) {
-        const int xg = x0 + 4 * g;
-        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (xg >= 0 && xg < a.W) t = *reinterpret_cast<const float4 *>(a.inv_d + xg);
-        const int j = 4 * (g + K);
-        sx[j] = t.x;
-        sx[j + 1] = t.y;
-        sx[j + 2] = t.z;
-        sx[j + 3] = t.w;
-    }
-    for (int z = blockIdx.z; z < a.S; z += gridDim.z)
-        for (int yb = blockIdx.y * kXRows; yb < a.H; yb += gridDim.y * kXRows) {
-            const int ye = min(yb + kXRows, a.H);
-            for (int y = yb; y < ye; ++y) {
-                const long long row = ((long long)z * a.H + y) * a.W;
-                float v[NV];
-#pragma unroll
-                for (int g = -K; g <= K; ++g) {
-                    const int xg = x0 + 4 * g;
-                    float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
-                    if (xg >= 0 && xg < a.W) t = *reinterpret_cast<const float4 *>(a.in + row + xg);
-                    const int j = 4 * (g + K);
-                    v[j] = t.x * sx[j];
-                    v[j + 1] = t.y * sx[j + 1];
-                    v[j + 2] = t.z * sx[j + 2];
-                    v[j + 3] = t.w * sx[j + 3];
-                }
-                const float izy = iz[z] * iy[y];
-                float o[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    float acc = 0.f;
-#pragma unroll
-                    for (int d = -R; d <= R; ++d) acc = fmaf(a.w[d < 0 ? -d : d], v[4 * K + t + d], acc);
-                    o[t] = acc * izy;
-                }
-                *reinterpret_cast<float4 *>(a.out + row + x0) = make_float4(o[0], o[1], o[2], o[3]);
-            }
-        }
-}
-
 // Element arithmetic of the ring passes, for one column (float) or four
 // neighbouring columns (float4).
 typedef float vec4f __attribute__((ext_vector_type(4)));   // a register vector, 16-byte aligned
@@ -197,6 +139,91 @@ __global__ __launch_bounds__(256) void transpose_y_ring(const V *in, V *out, int
     }
 }
 
+// x and y passes in one kernel for rows of a multiple of 4 voxels (16-byte
+// aligned): a thread owns 4 neighbouring columns of a segment of kYSeg rows
+// and marches down it with a register ring of the x pass's results for rows
+// y - R .. y + R.  Each incoming row's x pass takes the 4 + 2R sources it
+// needs as 2K + 1 aligned float4 loads (K = ceil(R / 4)); a float4 is wholly
+// inside or outside the row, and one outside is zero, which drops its taps.
+// The 1 / Dx factors of those sources stay in registers, and the x pass's
+// results never go through memory.  The rows above and below a segment are
+// x-passed by both segments that need them.
+template <int R>
+__global__ __launch_bounds__(256) void transpose_xy_ring(XArgs a)
+{
+    constexpr int K = (R + 3) / 4;
+    constexpr int NV = 4 * (2 * K + 1);
+    constexpr int N = 2 * R + 1;
+    const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (x0 >= a.W) return;
+    const int y0 = blockIdx.y * kYSeg;
+    if (y0 >= a.H) return;
+    const int y1 = min(y0 + kYSeg, a.H);
+    const float *iy = a.inv_d + a.W, *iz = a.inv_d + a.W + a.H;
+    float sx[NV];
+#pragma unroll
+    for (int g = -K; g <= K; ++g) {
+        const int xg = x0 + 4 * g;
+        float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (xg >= 0 && xg < a.W) t = *reinterpret_cast<const float4 *>(a.inv_d + xg);
+        const int j = 4 * (g + K);
+        sx[j] = t.x;
+        sx[j + 1] = t.y;
+        sx[j + 2] = t.z;
+        sx[j + 3] = t.w;
+    }
+    for (int z = blockIdx.z; z < a.S; z += gridDim.z) {
+        const float *plane = a.in + (long long)z * a.H * a.W;
+        const float izz = iz[z];
+        // the x pass (with the 1 / D scaling) of row y; zero outside the slice
+        auto xrow = [&](int y) -> vec4f {
+            if (y < 0 || y >= a.H) return vec4f{0.f, 0.f, 0.f, 0.f};
+            const float *row = plane + (long long)y * a.W;
+            float v[NV];
+#pragma unroll
+            for (int g = -K; g <= K; ++g) {
+                const int xg = x0 + 4 * g;
+                float4 t = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (xg >= 0 && xg < a.W) t = *reinterpret_cast<const float4 *>(row + xg);
+                const int j = 4 * (g + K);
+                v[j] = t.x * sx[j];
+                v[j + 1] = t.y * sx[j + 1];
+                v[j + 2] = t.z * sx[j + 2];
+                v[j + 3] = t.w * sx[j + 3];
+            }
+            const float izy = izz * iy[y];
+            float o[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                float acc = 0.f;
+#pragma unroll
+                for (int d = -R; d <= R; ++d) acc = fmaf(a.w[d < 0 ? -d : d], v[4 * K + t + d], acc);
+                o[t] = acc * izy;
+            }
+            return vec4f{o[0], o[1], o[2], o[3]};
+        };
+        vec4f ring[N];
+        // slot of row y' is (y' - y0 + R) mod N; preload rows y0 - R .. y0 + R - 1
+#pragma unroll
+        for (int j = 0; j < 2 * R; ++j) ring[j] = xrow(y0 - R + j);
+        vec4f *ocol = reinterpret_cast<vec4f *>(a.out + (long long)z * a.H * a.W + x0);
+        const int wv = a.W / 4;
+        for (int yb = y0; yb < y1; yb += N) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const int y = yb + k;
+                if (y < y1) {   // uniform
+                    ring[(k + 2 * R) % N] = xrow(y + R);
+                    vec4f acc = vmul(a.w[0], ring[(k + R) % N]);
+#pragma unroll
+                    for (int d = 1; d <= R; ++d) acc = vfma(a.w[d], ring[(k + R - d) % N], ring[(k + R + d) % N], acc);
+                    ocol[(long long)y * wv] = acc;
+                }
+            }
+        }
+    }
+}
+
 bool aligned16(const void *a, const void *b)
 {
     return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
@@ -256,7 +283,7 @@ hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const
 {
     const long long n = (long long)S * H * W;
     if (n == 0) return hipSuccess;
-    // x (with the 1 / D scaling at the source): g -> out; y: out -> tmp; z: tmp -> out
+    // x (with the 1 / D scaling at the source), y, z
     XArgs a{};
     a.in = g;
     a.out = out;
@@ -266,18 +293,25 @@ hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const
     a.W = W;
     a.r = rxy;
     for (int d = 0; d < 8; ++d) a.w[d] = wxy[d];
-    const bool vec = W % 4 == 0 && aligned16(g, out) && aligned16(inv_d, inv_d);
+    const bool vec = W % 4 == 0 && aligned16(g, out) && aligned16(inv_d, tmp);
     if (vec) {
-        const int rows = (H + kXRows - 1) / kXRows;
-        const dim3 grid((unsigned)((W / 4 + 255) / 256), (unsigned)std::min(rows, 65535), (unsigned)std::min(S, 65535));
+        // x and y in one pass: g -> tmp; z: tmp -> out
+        if ((H + kYSeg - 1) / kYSeg > 65535) return hipErrorInvalidValue;   // (H <= 4 M rows)
+        a.out = tmp;
+        const dim3 grid((unsigned)((W / 4 + 255) / 256), (unsigned)((H + kYSeg - 1) / kYSeg), (unsigned)std::min(S, 65535));
         switch (rxy) {
-#define GDF_XR(R) \
-    case R: hipLaunchKernelGGL(transpose_x4_kernel<R>, grid, dim3(256), 0, s, a); break;
-            GDF_XR(0) GDF_XR(1) GDF_XR(2) GDF_XR(3) GDF_XR(4) GDF_XR(5) GDF_XR(6) GDF_XR(7)
-#undef GDF_XR
+#define GDF_XYR(R) \
+    case R: hipLaunchKernelGGL(transpose_xy_ring<R>, grid, dim3(256), 0, s, a); break;
+            GDF_XYR(0) GDF_XYR(1) GDF_XYR(2) GDF_XYR(3) GDF_XYR(4) GDF_XYR(5) GDF_XYR(6) GDF_XYR(7)
+#undef GDF_XYR
         default: return hipErrorInvalidValue;
         }
-    } else {
+        const hipError_t exy = hipGetLastError();
+        if (exy != hipSuccess) return exy;
+        return launch_z_ring(tmp, out, S, H, W, rz, wz, s);
+    }
+    // one-voxel x pass: g -> out; y: out -> tmp; z: tmp -> out
+    {
         const dim3 grid((unsigned)((W + 255) / 256), (unsigned)std::min(H, 65535), (unsigned)std::min(S, 65535));
         hipLaunchKernelGGL(transpose_x_kernel, grid, dim3(256), 0, s, a);
     }

@@ -342,13 +342,13 @@ def test_robust_averaging_matches_oracle(precision):
 
 
 @pytest.mark.parametrize("shape,sxy,sz", [((9, 37, 70), 1.0, 3.0), ((4, 20, 9), 2.0, 1.0), ((6, 33, 40), 0.0, 4.0),
-                                          ((5, 30, 72), 1.0, 3.0), ((3, 17, 48), 2.0, 3.0), ((3, 9, 1104), 1.0, 1.0),
+                                          ((5, 30, 72), 1.0, 3.0), ((3, 17, 48), 2.0, 3.0), ((3, 9, 1104), 1.0, 1.0), ((2, 150, 32), 1.0, 1.0),
                                           ((2, 6, 8), 2.5, 0.5), ((7, 12, 9), 1.0, 3.0)])
 def test_smooth_transpose_matches_oracle(shape, sxy, sz):
-    """Widths of a multiple of 4 take the 4-voxel x and y passes (radii 0, 3, 6
-    and 7, a row wider than one workgroup's 1024 voxels, row counts not a
-    multiple of 4), planes of a multiple of 4 voxels the 4-column z pass
-    (12 x 9); the others the one-voxel forms."""
+    """Widths of a multiple of 4 take the fused 4-column x-y pass (radii 0, 3,
+    6 and 7, a row wider than one workgroup's 1024 voxels, heights that are
+    not a multiple of the 64-row segment), planes of a multiple of 4 voxels
+    the 4-column z pass (12 x 9); the others the one-voxel forms."""
     rng = np.random.default_rng(sum(shape))
     g = rng.standard_normal(shape)
     out = gdf.smooth_transpose(torch.from_numpy(g).to(DEV, torch.float32), sxy, sz)
