@@ -425,6 +425,8 @@ def fuse_stack_streamed(stack, alpha, chunk=32, out=None, sigma_xy=1.0, sigma_z=
         raise ValueError("stack must be a uint8 [S, H, W] tensor in host memory")
     if chunk < 1:
         raise ValueError("chunk must be >= 1")
+    if kw.get("return_smooth"):
+        raise ValueError("fuse_stack_streamed does not return the smoothed stack")
     S, H, W = stack.shape
     rz = int(np.floor(3.0 * sigma_z)) if sigma_z > 0 else 0
     dev = torch.device("cuda", torch.cuda.current_device())

@@ -149,3 +149,5 @@ def test_streamed_rejects_device_or_float_stacks():
         gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.float32), 0.01)
     with pytest.raises(ValueError):
         gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.uint8), 0.01, chunk=0)
+    with pytest.raises(ValueError):
+        gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.uint8), 0.01, return_smooth=True)
