@@ -261,9 +261,8 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
  *                    device memory owned by the caller.
  * Returns GDF_EINVAL / GDF_EUNSUPPORTED on bad arguments and GDF_ENOMEM for a
  * workspace smaller than the query (nothing launched), GDF_EDEVICE on a HIP
- * error.  The call waits for earlier work on `stream` while it copies the
- * weight tables from host memory; the three passes then run asynchronously
- * on `stream`.                                                               */
+ * error.  Asynchronous on `stream`: the per-axis weight-sum tables are
+ * computed on the device, in the workspace.                                  */
 size_t gdf_smooth_transpose_workspace_size(int S, int H, int W);
 gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
                             float *out_dev, void *workspace, size_t ws_bytes, void *stream);

@@ -1387,19 +1387,6 @@ gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double s
     double wxy[8] = {0}, wz[16] = {0};
     for (int d = 0; d <= rxy; ++d) wxy[d] = sigma_xy > 0 ? std::exp(-(double)d * d / (2 * sigma_xy * sigma_xy)) : 1.0;
     for (int d = 0; d <= rz; ++d) wz[d] = sigma_z > 0 ? std::exp(-(double)d * d / (2 * sigma_z * sigma_z)) : 1.0;
-    auto inv_sums = [](int n, int r, const double *w, std::vector<float> &out) {
-        for (int c = 0; c < n; ++c) {
-            double sum = 0.0;
-            for (int d = -r; d <= r; ++d)
-                if (c + d >= 0 && c + d < n) sum += w[d < 0 ? -d : d];
-            out.push_back((float)(1.0 / sum));
-        }
-    };
-    std::vector<float> tab;
-    tab.reserve((size_t)S + H + W);
-    inv_sums(W, rxy, wxy, tab);   // 1 / Dx first: it starts on the workspace's 256-byte boundary
-    inv_sums(H, rxy, wxy, tab);
-    inv_sums(S, rz, wz, tab);
     float wxyf[8], wzf[16];
     for (int d = 0; d < 8; ++d) wxyf[d] = (float)wxy[d];
     for (int d = 0; d < 16; ++d) wzf[d] = (float)wz[d];
@@ -1407,8 +1394,7 @@ gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double s
     float *tmp = reinterpret_cast<float *>(ws);
     float *inv_d = reinterpret_cast<float *>(ws + transpose_tmp_bytes(S, H, W));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(hipMemcpyAsync(inv_d, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));   // (pageable source: release it only after the copy)
+    HIP_TRY(launch_transpose_tables(inv_d, S, H, W, rxy, rz, wxy, wz, s));
     HIP_TRY(launch_smooth_transpose(grad_dev, out_dev, tmp, inv_d, S, H, W, rxy, rz, wxyf, wzf, s));
     return GDF_OK;
 }

@@ -352,6 +352,10 @@ hipError_t launch_smooth(bool fp64, const SmoothArgs &a, hipStream_t s);
 // Transpose of the smoothing for FP32 gradients: out = K (g / D) (see
 // smooth_transpose.hip); tmp holds S H W floats, inv_d the tables 1 / Dz (S),
 // 1 / Dy (H), 1 / Dx (W) in that order; wxy[0..7] and wz[0..15] the taps.
+// 1 / D tables of the smoothing transpose (W + H + S floats at inv_d), from
+// the in-plane (radius rxy <= 7) and cross-slice (rz <= 15) taps in FP64.
+hipError_t launch_transpose_tables(float *inv_d, int S, int H, int W, int rxy, int rz, const double *wxy,
+                                   const double *wz, hipStream_t s);
 hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const float *inv_d, int S, int H, int W,
                                    int rxy, int rz, const float *wxy, const float *wz, hipStream_t s);
 

@@ -278,6 +278,46 @@ hipError_t launch_z_ring(const float *in, float *out, int S, int H, int W, int r
 
 }  // namespace
 
+// The per-axis factors 1 / D: entry c of an axis of n samples is one over the
+// sum of the taps w[|d|], |d| <= r, whose sample c + d lies in [0, n), summed
+// in FP64 from d = -r up.  Layout: W entries (x), H (y), S (z).
+struct TapsD {
+    double wxy[8], wz[16];
+};
+
+__global__ __launch_bounds__(256) void transpose_tables_kernel(float *inv_d, int S, int H, int W, int rxy, int rz,
+                                                               TapsD t)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W + H + S) return;
+    int n, c, r;
+    const double *w;
+    if (i < W) {
+        n = W, c = i, r = rxy, w = t.wxy;
+    } else if (i < W + H) {
+        n = H, c = i - W, r = rxy, w = t.wxy;
+    } else {
+        n = S, c = i - W - H, r = rz, w = t.wz;
+    }
+    double sum = 0.0;
+    for (int d = -r; d <= r; ++d)
+        if (c + d >= 0 && c + d < n) sum += w[d < 0 ? -d : d];
+    inv_d[i] = (float)(1.0 / sum);
+}
+
+hipError_t launch_transpose_tables(float *inv_d, int S, int H, int W, int rxy, int rz, const double *wxy,
+                                   const double *wz, hipStream_t s)
+{
+    if (rxy < 0 || rxy > 7 || rz < 0 || rz > 15) return hipErrorInvalidValue;
+    TapsD t{};
+    for (int d = 0; d < 8; ++d) t.wxy[d] = wxy[d];
+    for (int d = 0; d < 16; ++d) t.wz[d] = wz[d];
+    const long long n = (long long)W + H + S;
+    hipLaunchKernelGGL(transpose_tables_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, inv_d, S, H, W,
+                       rxy, rz, t);
+    return hipGetLastError();
+}
+
 hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const float *inv_d, int S, int H, int W,
                                    int rxy, int rz, const float *wxy, const float *wz, hipStream_t s)
 {
