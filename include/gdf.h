@@ -106,16 +106,7 @@ typedef struct {
                           weighted standard deviations from the window's weighted mean
                           are left out of the average (one pass).  FP32 and MIXED only
                           (GDF_EUNSUPPORTED with GDF_PREC_FP64); 0 = plain averaging. */
-    int omega_milli;   /* over-relaxation of the finest level's red-black sweeps, in
-                          thousandths: every half-sweep after the first of each fused
-                          finest pass moves a pixel to u + omega (u_GS - u).  1000 .. 1900;
-                          0 = plain Gauss-Seidel (omega 1).  Same solution (each slice
-                          still stops on its FP64 residual); fewer sweeps per cycle can
-                          then reach tol in as many cycles.  1200 with fine_sweeps = 2 nu
-                          reached tol on every slice of a sweep over alpha 0.001 .. 0.1
-                          and slices of 512^2 to 4096^2; 1350 and above left single slices
-                          above tol (GDF_ENOCONV) at alpha 0.003 .. 0.03. */
-    int reserved[3];
+    int reserved[4];
 } gdf_solve_opts;
 
 typedef enum {

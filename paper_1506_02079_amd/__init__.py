@@ -41,7 +41,7 @@ class SolveOpts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("launch_mode", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("fine_sweeps", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
-                ("robust", ctypes.c_int), ("omega_milli", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("robust", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
 
 
 class SliceReport(ctypes.Structure):
@@ -108,7 +108,7 @@ def version() -> str:
 
 def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=False,
               tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0,
-              coarse_sweeps=0, omega=0.0) -> SolveOpts:
+              coarse_sweeps=0) -> SolveOpts:
     o = SolveOpts()
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.max_vcycles = int(max_vcycles)
@@ -121,7 +121,6 @@ def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=F
     o.autotune = int(bool(autotune))
     o.fine_sweeps = int(fine_sweeps)
     o.coarse_sweeps = int(coarse_sweeps)
-    o.omega_milli = int(round(float(omega) * 1000)) if omega else 0
     return o
 
 
@@ -183,11 +182,10 @@ def _require_cuda(*ts):
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
                tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
-               allow_noconv=False, robust=False, omega=0.0):
+               allow_noconv=False, robust=False):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
     robust=True: robust cross-slice averaging (values more than two weighted
     standard deviations from the window's weighted mean are left out).
-    omega: over-relaxation of the finest level's sweeps (0 = plain Gauss-Seidel).
 
     Returns (f, report) or (f, report, g_smooth) with return_smooth=True.
     f has dtype float32 (fp32) or float64 (fp64 / mixed) unless out_dtype is given.
@@ -200,7 +198,7 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
         stack = stack.contiguous()
     S, H, W = stack.shape
     o = make_opts(precision, max_vcycles, nu, out_dtype, False, tile_rows, inner_cycles,
-                  launch_mode, autotune, fine_sweeps, coarse_sweeps, omega)
+                  launch_mode, autotune, fine_sweeps, coarse_sweeps)
     o.robust = int(bool(robust))
     L = lib()
     ws = L.gdf_fuse_workspace_size(S, H, W, ctypes.byref(o))
@@ -251,7 +249,7 @@ def _descs(gs_list, go_list, f_list, alphas):
 
 def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_dtype=None,
                  nu=0, max_vcycles=0, use_graph=False, tile_rows=0, inner_cycles=0,
-                 launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False, omega=0.0):
+                 launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False):
     """Eq. (1) per slice.  g_s, g_o: [S, H, W] tensors or lists of 2D tensors
     (uneven batch).  alpha: scalar or per-slice sequence.  Returns (f, report)
     with f shaped like the input (a list for list input)."""
@@ -273,7 +271,7 @@ def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_
         raise ValueError("all g_s slices (and all g_o slices) must share a dtype")
     alphas = [float(alpha)] * n if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
     o = make_opts(precision, max_vcycles, nu, out_dtype, use_graph, tile_rows, inner_cycles,
-                  launch_mode, autotune, fine_sweeps, coarse_sweeps, omega)
+                  launch_mode, autotune, fine_sweeps, coarse_sweeps)
     od = o.out_dtype or (DTYPE_F32 if o.precision == 0 else DTYPE_F64)
     fdt = torch.float64 if od == DTYPE_F64 else torch.float32
     dev = gs_list[0].device

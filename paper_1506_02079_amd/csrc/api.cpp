@@ -80,7 +80,6 @@ struct Opts {
     int fsw;   // sweeps of the fused finest pass
     int csw;   // sweeps per smoothing step on the coarse levels
     int robust;   // robust cross-slice averaging in fuse_stack
-    float omega;  // over-relaxation of the finest passes' later half-sweeps (0: none)
 };
 
 gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
@@ -122,9 +121,6 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
     r.csw = o->coarse_sweeps ? o->coarse_sweeps : (r.prec == GDF_PREC_MIXED ? r.nu : r.nu + 1);
     if (r.csw < 1 || r.csw > 3)
         return set_err(GDF_EINVAL, "opts.coarse_sweeps must be 0 or in [1, 3] (got %d)", o->coarse_sweeps);
-    if (o->omega_milli != 0 && (o->omega_milli < 1000 || o->omega_milli > 1900))
-        return set_err(GDF_EINVAL, "opts.omega_milli must be 0 or in 1000 .. 1900 (got %d)", o->omega_milli);
-    r.omega = o->omega_milli > 1000 ? (float)(o->omega_milli / 1000.0) : 0.f;
     r.robust = o->robust;
     if (r.robust != 0 && r.robust != 1) return set_err(GDF_EINVAL, "opts.robust must be 0 or 1 (got %d)", r.robust);
     if (r.robust && r.prec == GDF_PREC_FP64)
@@ -568,7 +564,6 @@ gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vecto
     for (int v : {n, smooth_S, need_gs ? 1 : 0, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype, o.use_graph, o.tile_rows,
                   o.inner, o.launch, o.fsw})
         key_push(key, v);
-    key_push(key, (double)o.omega);
     for (int i = 0; i < n; ++i) {
         key_push(key, H[i]);
         key_push(key, W[i]);
@@ -748,7 +743,6 @@ struct Run {
         a.done = capturing ? done : nullptr;
         a.partials = partials;
         a.raw_rhs = raw_rhs ? 1 : 0;
-        a.omega = (kind == SK_FINE || kind == SK_FINE_ZERO) ? P.o.omega : 0.f;
         const bool timed = g_prof_on && (!g_prof_fine_only || cls == PC_FINE);
         ProfScope ps(cls, timed ? pass_bytes(li, per_px) : 0.0, s, capturing);
         a.items = items + L.off;
@@ -1406,7 +1400,7 @@ size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
-                  b.launch_mode, b.robust, b.omega_milli})
+                  b.launch_mode, b.robust})
         key_push(key, v);
     return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
 }
@@ -1432,7 +1426,7 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps,
-                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust, b.omega_milli})
+                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust})
         key_push(key, v);
     for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
     return autotuned(key, b, [&](const gdf_solve_opts *c) {
@@ -1629,7 +1623,7 @@ size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_
     std::vector<unsigned long long> key;
     key_push(key, 1);
     for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
-                  b.launch_mode, b.omega_milli})
+                  b.launch_mode})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
         key_push(key, d[i].H);
@@ -1738,7 +1732,7 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
     std::vector<unsigned long long> key;
     key_push(key, 1);
     for (int v : {n, bc, gs_dtype, go_dtype, b.precision, b.max_vcycles, b.out_dtype, b.use_graph,
-                  b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode, b.omega_milli})
+                  b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {
@@ -1814,7 +1808,6 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         key_push(key, o.inner);
         key_push(key, o.launch);
         key_push(key, o.fsw);
-        key_push(key, (double)o.omega);
         for (int i = 0; i < n; ++i) {
             key_push(key, d[i].H);
             key_push(key, d[i].W);
@@ -1879,8 +1872,7 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
     std::vector<unsigned long long> key;
     key_push(key, 2);
-    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode,
-                  b.omega_milli})
+    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {

@@ -133,7 +133,6 @@ struct StripLaunch {
     const int *done;         // if non-null and set: no slice is iterating (every wave exits at once)
     float2 *partials;        // per-item partial sums (r^2, r) (RES_NORM / RES_BOTH)
     int raw_rhs;             // level 1: b holds sums of unshifted level-0 values (see LevelDesc)
-    float omega;             // finest passes: over-relaxation of the half-sweeps after the first (0: none)
 };
 
 // Strip kernel variants (template instances live in mg_kernels.hip).

@@ -309,10 +309,6 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     // level 1 after a restriction of the unshifted level-0 right-hand side: a
     // cell's children (4 wx wy of them) each carry the level-0 mean
     const T bsc = (a.raw_rhs && L.bshift_fine) ? T(4) * (T)uniform_d(*L.bshift_fine) : T(0);
-    // over-relaxation of the half-sweeps after the first (finest passes only;
-    // the first keeps omega = 1, so the dead red values stay unread)
-    const bool sor = a.omega != 0.f;
-    const T om = (T)a.omega;
     const T bsx0 = bsh + bsc * wx0, bsx1 = bsh + bsc * wx1;   // (rows other than the last)
     const T bshg0 = bsx0 * g0, bshg1 = bsx1 * g1;
     // (selects, not a runtime index into the descriptor's array: that would spill it)
@@ -490,12 +486,10 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                         if (!GEN || CIN) {   // unit couplings
                             if (j == 0) {
                                 const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
-                                const T gs = fma(nb, g0, b[sl][0]);
-                                u[sl][0] = (s >= 2 && sor) ? fma(om, gs - u[sl][0], u[sl][0]) : gs;
+                                u[sl][0] = fma(nb, g0, b[sl][0]);
                             } else {
                                 const T nb = wave_shl1(u[sl][0]) + u[sl][0] + u[su][1] + u[sd][1];
-                                const T gs = fma(nb, g1, b[sl][1]);
-                                u[sl][1] = (s >= 2 && sor) ? fma(om, gs - u[sl][1], u[sl][1]) : gs;
+                                u[sl][1] = fma(nb, g1, b[sl][1]);
                             }
                         } else {             // coarse level at a column edge: per-lane couplings
                             if (j == 0) {
@@ -516,13 +510,11 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                                 if (j == 0) {
                                     const T iv = dy == 2 ? inv0[2] : (dy == 1 ? inv0[1] : inv0[0]);
                                     const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
-                                    const T gs = (b[sl][0] + nb) * iv;
-                                    u[sl][0] = (s >= 2 && sor) ? fma(om, gs - u[sl][0], u[sl][0]) : gs;
+                                    u[sl][0] = (b[sl][0] + nb) * iv;
                                 } else {
                                     const T iv = dy == 2 ? inv1[2] : (dy == 1 ? inv1[1] : inv1[0]);
                                     const T nb = wave_shl1(u[sl][0]) + u[sl][0] + u[su][1] + u[sd][1];
-                                    const T gs = (b[sl][1] + nb) * iv;
-                                    u[sl][1] = (s >= 2 && sor) ? fma(om, gs - u[sl][1], u[sl][1]) : gs;
+                                    u[sl][1] = (b[sl][1] + nb) * iv;
                                 }
                             } else {
                                 const RowC rc = row_coef(y);

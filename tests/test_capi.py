@@ -73,8 +73,6 @@ def _robust(v, **kw):
     (dict(opts=gdf.make_opts(coarse_sweeps=4)), gdf.GDF_EINVAL),
     (dict(opts=gdf.make_opts(coarse_sweeps=-1)), gdf.GDF_EINVAL),
     (dict(opts=_robust(2)), gdf.GDF_EINVAL),
-    (dict(opts=gdf.make_opts(omega=0.5)), gdf.GDF_EINVAL),
-    (dict(opts=gdf.make_opts(omega=1.95)), gdf.GDF_EINVAL),
     (dict(opts=_robust(1, precision="fp64")), gdf.GDF_EUNSUPPORTED),
     (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),

@@ -443,37 +443,3 @@ def test_streamed_stack_matches_whole():
     for j in (0, 15, 16, 31, 32, 36):
         fr = oracle.solve(gs[j], stack[j].astype(np.float64), 0.01, tol=1e-12)
         assert np.abs(f_s[j].numpy() - fr).max() <= 1e-3, j
-
-
-# ----------------------------------------------------------- over-relaxation
-
-@pytest.mark.parametrize("alpha", [0.001, 0.01, 0.03, 0.1])
-def test_overrelaxed_finest_sweeps_converge(alpha):
-    """omega = 1.2 on the finest level with 4 fused sweeps: every slice still
-    stops on its FP64 residual and matches the oracle's solve of Eq. (1)."""
-    S, H, W = 4, 300, 257
-    stack = synth.make_stack(S, H, W, seed=91, ramp=True)
-    print("omega", alpha, flush=True)
-    # FP64 output: the check below is then on the solve, not on FP32 output rounding
-    f, rep, gsm = gdf.fuse_stack(torch.from_numpy(stack).to(DEV), alpha, omega=1.2, fine_sweeps=4,
-                                 return_smooth=True, out_dtype=gdf.DTYPE_F64)
-    f = f.cpu().numpy()
-    gsm = gsm.cpu().numpy().astype(np.float64)
-    f_ref = oracle.solve_stack(gsm, stack.astype(np.float64), alpha, tol=1e-12)
-    assert all(r["status"] == 0 and r["rel_residual"] <= 1e-6 for r in rep)
-    rel = [oracle.relres(f[j].astype(np.float64), gsm[j], stack[j].astype(np.float64), alpha) for j in range(S)]
-    assert max(rel) <= 1.01e-6
-    assert np.abs(f - f_ref).max() <= 1e-3
-
-
-def test_overrelaxed_uneven_batch():
-    gs, go = zip(*[(s, o.astype(np.float32)) for o, s in
-                   (synth.batch_slice(H, W, 60 + H) for H, W in ((200, 300), (64, 64), (513, 130)))])
-    alphas = [0.002, 0.05, 0.01]
-    f, rep = gdf.solve_slices([torch.from_numpy(a).to(DEV) for a in gs], [torch.from_numpy(a).to(DEV) for a in go],
-                              alphas, omega=1.2, out_dtype=gdf.DTYPE_F64)
-    for i, a in enumerate(alphas):
-        fr = oracle.solve(gs[i], go[i], a, tol=1e-12)
-        assert rep[i]["status"] == 0
-        assert np.abs(f[i].cpu().numpy() - fr).max() <= 1e-3
-        assert oracle.relres(f[i].cpu().numpy().astype(np.float64), gs[i], go[i], a) <= 1.01e-6
