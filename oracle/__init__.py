@@ -204,6 +204,8 @@ def smooth_robust(stack: np.ndarray, sigma_xy: float = 1.0, sigma_z: float = 3.0
     across slices of the in-plane smoothed values keeps only those within two
     weighted standard deviations of the window's weighted mean (one pass).
     float64 [S][H][W]."""
+    if sigma_z > 0 and int(np.floor(3.0 * sigma_z)) > 31:
+        raise ValueError("smooth_robust: cross-slice windows wider than 63 taps are not supported")
     st = np.ascontiguousarray(stack, dtype=np.uint8)
     S, H, W = st.shape
     out = np.empty((S, H, W), dtype=np.float64)

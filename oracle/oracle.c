@@ -142,9 +142,11 @@ double oracle_smooth_robust_voxel(const uint8_t *stack, int S, int H, int W, dou
                                   double sigma_z, int z, int y, int x)
 {
     const int rz = tap_radius(sigma_z);
+    /* the window's arrays hold 64 taps: a wider window is refused (NaN), never cut short */
+    if (2 * rz + 1 > 64) return NAN;
     double p[64], w[64];
     int n = 0;
-    for (int dz = -rz; dz <= rz && n < 64; ++dz) {
+    for (int dz = -rz; dz <= rz; ++dz) {
         const int zz = z + dz;
         if (zz < 0 || zz >= S) continue;
         p[n] = inplane_voxel(stack, H, W, sigma_xy, zz, y, x);

@@ -8,6 +8,7 @@ and smoothing kernels rely on fully unrolled register rings).
 from __future__ import annotations
 
 import os
+import re
 import shutil
 import subprocess
 from concurrent.futures import ThreadPoolExecutor
@@ -29,8 +30,31 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I", INCLUDE,
           "-mllvm", "-pragma-unroll-threshold=1000000"]
 
 
-def _compile(src: str) -> str:
+def _deps(path: str, seen: set) -> set:
+    """The file and the local headers it includes, transitively."""
+    if path in seen or not os.path.exists(path):
+        return seen
+    seen.add(path)
+    for line in open(path):
+        m = re.match(r'\s*#\s*include\s+"([^"]+)"', line)
+        if m:
+            for d in (CSRC, INCLUDE):
+                _deps(os.path.join(d, m.group(1)), seen)
+    return seen
+
+
+def _stale(src: str, obj: str) -> bool:
+    """The object is older than its source or than a header it includes."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(p) > t for p in _deps(os.path.join(CSRC, src), set()))
+
+
+def _compile(src: str, force: bool = True) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not force and not _stale(src, obj):
+        return obj
     cmd = [HIPCC] + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + COMMON + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
@@ -40,11 +64,12 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(jobs: int = 8) -> str:
-    """Compile all sources and link libgdf.so; returns the library path."""
+def build(jobs: int = 8, force: bool = True) -> str:
+    """Compile the sources and link libgdf.so; returns the library path.
+    force=False recompiles only objects older than their source or a header."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(SOURCES)))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(lambda src: _compile(src, force), SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -55,4 +80,5 @@ def build(jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    print(build())
+    import sys
+    print(build(force="--changed" not in sys.argv))

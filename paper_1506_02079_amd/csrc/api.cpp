@@ -657,6 +657,7 @@ struct ProfScope {
 // kept until the process ends.
 hipError_t pinned_flags(int n, int *&out)
 {
+
     thread_local int *buf = nullptr;
     thread_local int cap = 0;
     if (cap < n) {
@@ -865,20 +866,28 @@ struct Run {
     }
 
     // After the exact FP64 residual of the output: slices that stopped on the
-    // in-loop (working-precision) estimate but miss tol resume iterating.
+    // in-loop (working-precision) estimate but miss tol resume iterating, as
+    // long as each round shrinks their exact residual by the stall factor (a
+    // slice that stops improving has reached the working precision's floor and
+    // is left to the FP64-refinement re-solve).
+    std::vector<double> prev_exact;
     gdf_status resume_missed(bool &any)
     {
         std::vector<SliceState> h(P.n);
         HIP_TRY(hipMemcpyAsync(h.data(), st, sizeof(SliceState) * P.n, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        if (prev_exact.empty()) prev_exact.assign(P.n, HUGE_VAL);
         std::vector<int> act(P.n, 0);
         any = false;
-        for (int i = 0; i < P.n; ++i)
+        for (int i = 0; i < P.n; ++i) {
+            const bool progress = stall_ratio <= 0.0 || h[i].rel < stall_ratio * prev_exact[i];
             if (h[i].status == 0 && !h[i].stalled && std::isfinite(h[i].rel) && h[i].rel > tol &&
-                h[i].cycles < max_cycles) {
+                h[i].cycles < max_cycles && progress) {
                 act[i] = 1;
                 any = true;
             }
+            prev_exact[i] = h[i].rel;
+        }
         if (any) {
             HIP_TRY(hipMemcpyAsync(active, act.data(), sizeof(int) * P.n, hipMemcpyHostToDevice, s));
             HIP_TRY(hipMemcpyAsync(only, act.data(), sizeof(int) * P.n, hipMemcpyHostToDevice, s));
@@ -1308,6 +1317,13 @@ static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const v
                            const void *go, int bc, double tol, void *f, const Opts &o, void *ws,
                            size_t ws_bytes, const std::vector<SliceState> &h, gdf_slice_report *report,
                            void *stream);
+static std::vector<int> escalation_list(int n, const std::vector<SliceState> &h, double tol, int max_vc);
+static std::vector<int> slice_status(int n, const std::vector<SliceState> &h, double tol);
+static gdf_status worst_status(const std::vector<int> &status, double tol);
+static gdf_status escalate_slices(const std::vector<int> &todo, const gdf_slice_desc *d, int gs_dtype,
+                                  const void *gs, int go_dtype, const void *go, int bc, double tol, void *f,
+                                  const Opts &o, void *ws, size_t ws_bytes, std::vector<int> &status,
+                                  gdf_slice_report *report, void *stream);
 
 
 static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long long pr, long long ps,
@@ -1347,7 +1363,11 @@ static size_t fuse_workspace_plain(int S, int H, int W, const gdf_solve_opts *op
     if (fuse_plan(P, S, H, W, 1.0, o, o.prec == GDF_PREC_MIXED)) return 0;
     // the hierarchy depth depends on alpha; size for the deepest (smallest alpha)
     if (fuse_plan(Q, S, H, W, 1e-12, o, o.prec == GDF_PREC_MIXED)) return 0;
-    return std::max({P->total, Q->total, escalation_bytes(o, H, W, 1e-12)});
+    // FP32: room to re-solve one slice with FP64 refinement, beside that
+    // slice's smoothed values (re-computed for the re-solve)
+    const size_t esc = o.prec == GDF_PREC_FP32 ? align_up((size_t)H * W * sizeof(float)) + escalation_bytes(o, H, W, 1e-12)
+                                               : 0;
+    return std::max({P->total, Q->total, esc});
 }
 
 // ------------------------------------------------- gradient through smoothing
@@ -1435,6 +1455,43 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
     });
 }
 
+// Smoothing arguments of a stack (taps, renormalisation tables, tiling); the
+// caller sets the outputs (b_u, level-1 right-hand side, g_s, partial sums).
+static SmoothArgs smooth_args(const uint8_t *stack, int S, int H, int W, long long pitch_row, long long pitch_slice,
+                              double sigma_xy, double sigma_z, double alpha, int robust)
+{
+    SmoothArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.stack = stack;
+    a.pitch_row = pitch_row;
+    a.pitch_slice = pitch_slice;
+    a.S = S;
+    a.H = H;
+    a.W = W;
+    a.rxy = sigma_xy > 0 ? (int)std::floor(3.0 * sigma_xy) : 0;
+    a.rz = sigma_z > 0 ? (int)std::floor(3.0 * sigma_z) : 0;
+    for (int d = 0; d <= a.rxy; ++d)
+        a.wxy[d] = sigma_xy > 0 ? std::exp(-(double)d * d / (2 * sigma_xy * sigma_xy)) : 1.0;
+    for (int d = 0; d <= a.rz; ++d)
+        a.wz[d] = sigma_z > 0 ? std::exp(-(double)d * d / (2 * sigma_z * sigma_z)) : 1.0;
+    a.alpha = alpha;
+    for (int d = 0; d < 8; ++d) a.wxy_f[d] = (float)a.wxy[d];
+    for (int d = 0; d < 16; ++d) a.wz_f[d] = (float)a.wz[d];
+    a.alpha_f = (float)alpha;
+    a.robust = robust;
+    for (int lo = 0; lo <= 12; ++lo)
+        for (int hi = 0; hi <= 12; ++hi) {
+            double w = 0.0;
+            for (int d = -lo; d <= hi; ++d)
+                if (d >= -a.rz && d <= a.rz) w += a.wz[d < 0 ? -d : d];
+            a.inv_wz[lo][hi] = 1.0 / w;
+            a.inv_wz_f[lo][hi] = (float)(1.0 / w);
+        }
+    a.tiles_x = (W + kSmoothTileW - 1) / kSmoothTileW;
+    a.tiles_y = (H + kSmoothTileH - 1) / kSmoothTileH;
+    return a;
+}
+
 static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, long long pitch_row,
                                    long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
                                    double sigma_z, void *f, void *g_smooth, const gdf_solve_opts *opts,
@@ -1470,27 +1527,11 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     R.stall_ratio = o.prec == GDF_PREC_FP32 ? kStallRatio : 0.0;
 
     // smoothing writes the level-0 right-hand side of every slice
-    SmoothArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.stack = stack;
-    a.pitch_row = pitch_row;
-    a.pitch_slice = pitch_slice;
-    a.S = S;
-    a.H = H;
-    a.W = W;
-    a.rxy = sigma_xy > 0 ? (int)std::floor(3.0 * sigma_xy) : 0;
-    a.rz = sigma_z > 0 ? (int)std::floor(3.0 * sigma_z) : 0;
-    for (int d = 0; d <= a.rxy; ++d)
-        a.wxy[d] = sigma_xy > 0 ? std::exp(-(double)d * d / (2 * sigma_xy * sigma_xy)) : 1.0;
-    for (int d = 0; d <= a.rz; ++d)
-        a.wz[d] = sigma_z > 0 ? std::exp(-(double)d * d / (2 * sigma_z * sigma_z)) : 1.0;
-    a.alpha = alpha;
-    for (int d = 0; d < 8; ++d) a.wxy_f[d] = (float)a.wxy[d];
-    for (int d = 0; d < 16; ++d) a.wz_f[d] = (float)a.wz[d];
-    a.alpha_f = (float)alpha;
-    a.robust = o.robust;
+    SmoothArgs a = smooth_args(stack, S, H, W, pitch_row, pitch_slice, sigma_xy, sigma_z, alpha, o.robust);
     void *gs_used = g_smooth ? g_smooth : (mixed ? (void *)(ws + P.off_gscopy) : nullptr);
     a.gs_out = gs_used;
+    a.gs_zlo = 0;
+    a.gs_zhi = S;
     // a uniform stack: every slice has the same arena block, so the level-0
     // right-hand sides are equally spaced
     a.b0 = ws + P.off_arena + P.g[0].off_b[0];
@@ -1508,19 +1549,9 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
         for (int z = 1; z < S; ++z)
             if ((long long)(P.g[z].off_b[1] - P.g[0].off_b[1]) != a.bc_slice_stride * z * P.csz) a.bc0 = nullptr;
     }
-    for (int lo = 0; lo <= 12; ++lo)
-        for (int hi = 0; hi <= 12; ++hi) {
-            double w = 0.0;
-            for (int d = -lo; d <= hi; ++d)
-                if (d >= -a.rz && d <= a.rz) w += a.wz[d < 0 ? -d : d];
-            a.inv_wz[lo][hi] = 1.0 / w;
-            a.inv_wz_f[lo][hi] = (float)(1.0 / w);
-        }
     a.part_bb = R.partd;
     a.part_b0 = R.partd2;
     a.part_bs = R.partd3;
-    a.tiles_x = (W + kSmoothTileW - 1) / kSmoothTileW;
-    a.tiles_y = (H + kSmoothTileH - 1) / kSmoothTileH;
     {
         ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0) + (a.bc0 ? 0.25 * P.csz : 0.0)),
                      s, false);
@@ -1539,22 +1570,43 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     if ((r = solve_body(R, x))) return r;
     std::vector<SliceState> h;
     const gdf_status st = collect(P, ws, s, report, tol, mixed ? o.inner : 1, &h);
-    if (st != GDF_ENOCONV || o.prec != GDF_PREC_FP32 || !g_smooth) return st;
-    // stalled slices are re-solved from the returned g_s (FP32) and the stack
+    if (st != GDF_ENOCONV || o.prec != GDF_PREC_FP32) return st;
+    // Slices left above tol at the FP32 floor are re-solved by FP64 refinement
+    // from their g_s (FP32) and the stack: from the returned g_s when there is
+    // one, else one slice at a time from g_s smoothed again into the front of
+    // the workspace (the re-solve uses the rest of it).
     std::vector<gdf_slice_desc> d(S);
     for (int z = 0; z < S; ++z) {
         d[z].H = H;
         d[z].W = W;
         d[z].alpha = alpha;
-        d[z].off_gs = (long long)z * H * W;
+        d[z].off_gs = g_smooth ? (long long)z * H * W : 0;
         d[z].pitch_gs = W;
         d[z].off_go = (long long)z * pitch_slice;
         d[z].pitch_go = pitch_row;
         d[z].off_f = (long long)z * H * W;
         d[z].pitch_f = W;
     }
-    return escalate(S, d.data(), GDF_F32, g_smooth, GDF_U8, stack, bc, tol, f, o, workspace, ws_bytes, h, report,
-                    stream);
+    if (g_smooth)
+        return escalate(S, d.data(), GDF_F32, g_smooth, GDF_U8, stack, bc, tol, f, o, workspace, ws_bytes, h, report,
+                        stream);
+    std::vector<int> status = slice_status(S, h, tol);
+    const size_t gs1 = align_up((size_t)H * W * sizeof(float));
+    if (ws_bytes <= gs1) return worst_status(status, tol);
+    SmoothArgs a1 = a;   // g_s of one slice only: no b_u, no level-1 restriction, no partial sums
+    a1.b0 = nullptr;
+    a1.bc0 = nullptr;
+    a1.part_bb = a1.part_b0 = a1.part_bs = nullptr;
+    a1.gs_out = ws;
+    for (int z : escalation_list(S, h, tol, o.max_vc)) {
+        a1.gs_zlo = z;
+        a1.gs_zhi = z + 1;
+        HIP_TRY(launch_smooth(false, a1, s));
+        if ((r = escalate_slices({z}, d.data(), GDF_F32, ws, GDF_U8, stack, bc, tol, f, o, ws + gs1, ws_bytes - gs1,
+                                 status, report, stream)))
+            return r;
+    }
+    return worst_status(status, tol);
 }
 
 // -------------------------------------------------------------- solve_slices
@@ -1648,13 +1700,44 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
                                      const gdf_solve_opts *opts, void *workspace, size_t ws_bytes,
                                      gdf_slice_report *report, void *stream);
 
-// Slices whose FP32 iterate stopped at the precision floor (stalled, above
-// tol) are solved again, from zero, by FP32 V-cycles inside FP64 iterative
-// refinement, in groups that fit the workspace, writing their f in place.
-static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
-                           const void *go, int bc, double tol, void *f, const Opts &o, void *ws,
-                           size_t ws_bytes, const std::vector<SliceState> &h, gdf_slice_report *report,
-                           void *stream)
+// Slices to re-solve with FP64 refinement after an FP32 solve: finite, above
+// tol, and stopped before the cycle cap (stalled at the FP32 floor, or resumed
+// without progress).  A slice that used up max_vcycles keeps GDF_ENOCONV: the
+// caller's cap holds.
+static std::vector<int> escalation_list(int n, const std::vector<SliceState> &h, double tol, int max_vc)
+{
+    std::vector<int> todo;
+    for (int i = 0; i < n; ++i) {
+        const bool bad = h[i].status == GDF_ENONFINITE || !std::isfinite(h[i].rel);
+        if (!bad && h[i].rel > tol && (h[i].stalled || h[i].cycles < max_vc)) todo.push_back(i);
+    }
+    return todo;
+}
+
+static std::vector<int> slice_status(int n, const std::vector<SliceState> &h, double tol)
+{
+    std::vector<int> status(n);
+    for (int i = 0; i < n; ++i) {
+        const bool bad = h[i].status == GDF_ENONFINITE || !std::isfinite(h[i].rel);
+        status[i] = bad ? GDF_ENONFINITE : (h[i].rel > tol ? GDF_ENOCONV : GDF_OK);
+    }
+    return status;
+}
+
+static gdf_status worst_status(const std::vector<int> &status, double tol)
+{
+    gdf_status worst = GDF_OK;
+    for (int v : status) {
+        if (v == GDF_ENONFINITE) worst = GDF_ENONFINITE;
+        else if (v == GDF_ENOCONV && worst == GDF_OK) worst = GDF_ENOCONV;
+    }
+    if (worst == GDF_ENOCONV) set_err(worst, "some slices did not reach tol=%g", tol);
+    else if (worst == GDF_ENONFINITE) set_err(worst, "non-finite residual in some slices");
+    else g_err.clear();
+    return worst;
+}
+
+static gdf_solve_opts escalation_call_opts(const Opts &o)
 {
     const Opts mo = escalation_opts(o);
     gdf_solve_opts m;
@@ -1668,12 +1751,18 @@ static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const v
     m.tile_rows = mo.tile_rows;
     m.inner_cycles = mo.inner;
     m.launch_mode = mo.launch;
-    std::vector<int> status(n), todo;
-    for (int i = 0; i < n; ++i) {
-        const bool bad = h[i].status == GDF_ENONFINITE || !std::isfinite(h[i].rel);
-        status[i] = bad ? GDF_ENONFINITE : (h[i].rel > tol ? GDF_ENOCONV : GDF_OK);
-        if (!bad && h[i].stalled && h[i].rel > tol) todo.push_back(i);
-    }
+    return m;
+}
+
+// Re-solves the slices `todo` from zero by FP32 V-cycles inside FP64
+// iterative refinement, in groups that fit the workspace, writing their f in
+// place and updating status[] and the report.
+static gdf_status escalate_slices(const std::vector<int> &todo, const gdf_slice_desc *d, int gs_dtype,
+                                  const void *gs, int go_dtype, const void *go, int bc, double tol, void *f,
+                                  const Opts &o, void *ws, size_t ws_bytes, std::vector<int> &status,
+                                  gdf_slice_report *report, void *stream)
+{
+    const gdf_solve_opts m = escalation_call_opts(o);
     size_t k = 0;
     while (k < todo.size()) {
         std::vector<gdf_slice_desc> g;
@@ -1705,15 +1794,19 @@ static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const v
             }
         }
     }
-    gdf_status worst = GDF_OK;
-    for (int i = 0; i < n; ++i) {
-        if (status[i] == GDF_ENONFINITE) worst = GDF_ENONFINITE;
-        else if (status[i] == GDF_ENOCONV && worst == GDF_OK) worst = GDF_ENOCONV;
-    }
-    if (worst == GDF_ENOCONV) set_err(worst, "some slices did not reach tol=%g", tol);
-    else if (worst == GDF_ENONFINITE) set_err(worst, "non-finite residual in some slices");
-    else g_err.clear();
-    return worst;
+    return GDF_OK;
+}
+
+static gdf_status escalate(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
+                           const void *go, int bc, double tol, void *f, const Opts &o, void *ws,
+                           size_t ws_bytes, const std::vector<SliceState> &h, gdf_slice_report *report,
+                           void *stream)
+{
+    std::vector<int> status = slice_status(n, h, tol);
+    const gdf_status r = escalate_slices(escalation_list(n, h, tol, o.max_vc), d, gs_dtype, gs, go_dtype, go, bc,
+                                         tol, f, o, ws, ws_bytes, status, report, stream);
+    if (r) return r;
+    return worst_status(status, tol);
 }
 
 gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,

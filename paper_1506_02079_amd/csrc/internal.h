@@ -325,8 +325,10 @@ struct SmoothArgs {
     float wxy_f[8];       // the same taps rounded to FP32 (FP32 kernel: kept in scalar registers)
     float wz_f[16];
     float alpha_f;
-    void *gs_out;         // optional smoothed stack (contiguous [S][H][W])
-    void *b0;                 // level-0 right-hand side of slice 0 (b_u is written there)
+    void *gs_out;         // optional smoothed slices (contiguous [gs_zhi - gs_zlo][H][W])
+    int gs_zlo, gs_zhi;   // output slices [gs_zlo, gs_zhi) are stored into gs_out (slice z at z - gs_zlo)
+    void *b0;                 // level-0 right-hand side of slice 0 (b_u is written there);
+                              // null: neither b_u nor the partial sums are stored
     long long b_slice_stride; // elements between consecutive slices' level-0 right-hand sides
     int b_pitch;              // its row pitch (elements)
     // 1 / (sum of the z taps inside the stack) for an output slice with lo

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             for (int w = 0; w < kSmoothWaves; ++w) v += red_s[z & 1][w][pq];
             pbuf = v;
         }
-        if (zs == kPB - 1 || z == S - 1) {
+        if ((zs == kPB - 1 || z == S - 1) && a.b0) {
             if (tid < 3 * (zs + 1)) {
                 double *dst = pq == 0 ? a.part_bb : (pq == 1 ? a.part_b0 : a.part_bs);
                 dst[(long long)(z - zs + ps) * nparts + tile] = pbuf;
@@ -341,11 +341,14 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             else iz = a.inv_wz[zlo][zhi];
             const int oslot = zo % NRAW;
             // this slice's tile rows of b (and of g_s): windows of kSTY rows
+            // (a resource of size zero drops the stores: no b_u without a.b0, and
+            // g_s only for the output slices asked for)
             const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride +
                                            (long long)Y0 * a.b_pitch,
-                                       (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)));
-            const Rsrc rgw = a.gs_out ? make_rsrc(static_cast<T *>(a.gs_out) + ((long long)zo * H + Y0) * W,
-                                                  (unsigned)(kSTY * W * (int)sizeof(T)))
+                                       a.b0 ? (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)) : 0u);
+            const bool gsz = a.gs_out && zo >= a.gs_zlo && zo < a.gs_zhi;   // uniform
+            const Rsrc rgw = a.gs_out ? make_rsrc(static_cast<T *>(a.gs_out) + ((long long)(zo - a.gs_zlo) * H + Y0) * W,
+                                                  gsz ? (unsigned)(kSTY * W * (int)sizeof(T)) : 0u)
                                       : rbw;
             T sbb = T(0), sb0 = T(0), sbs = T(0);
             // original slice around this thread's column

@@ -306,16 +306,55 @@ def test_robust_averaging_restores_corrupt_slices():
     t = torch.from_numpy(st).to(DEV)
     f, rep, gsm = gdf.fuse_stack(t, 0.01, tol=1e-6, robust=True, return_smooth=True, out_dtype=gdf.DTYPE_F64)
     # (plain averaging leaves a step in the target of the slices next to the
-    # half-zeroed one while their g_o is flat; one of them ends a hair above tol)
-    fp, _, gsp = gdf.fuse_stack(t, 0.01, tol=1e-6, return_smooth=True, out_dtype=gdf.DTYPE_F64,
-                                allow_noconv=True)
+    # half-zeroed one while their g_o is flat: FP32 V-cycles stall a hair above
+    # tol there, and those slices are re-solved by FP64 refinement)
+    fp, rep_p, gsp = gdf.fuse_stack(t, 0.01, tol=1e-6, return_smooth=True, out_dtype=gdf.DTYPE_F64)
     torch.cuda.synchronize()
+    assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep_p)
     assert np.abs(gsm.cpu().numpy() - 140).max() <= 1e-3
     assert gsp.cpu().numpy()[12].max() < 130
     f = f.cpu().numpy()
     assert np.abs(f[12] - 140).max() <= 1e-2   # g_o = 0 there: f is the constant target
     assert np.abs(fp.cpu().numpy()[12] - 140).max() > 5
     assert all(r["status"] == gdf.GDF_OK for r in rep)
+
+
+@pytest.mark.parametrize("robust", [False, True])
+def test_blank_slices_default_call_matches_oracle(robust):
+    # The paper's bad-data case ("Extensions and Applications"): one blank and
+    # one half-blank slice in an EM-like stack, through the default call (no
+    # smoothed stack returned, FP32).  Slices next to the blank ones can stall
+    # at the FP32 floor; they are re-solved by FP64 refinement from g_s
+    # smoothed again inside the workspace, so every slice reaches tol.
+    st = synth.make_stack(40, 96, 128, seed=91, ramp=True)
+    st[13] = 0
+    st[27, 40:] = 0
+    t = torch.from_numpy(st).to(DEV)
+    print("blank slices, robust =", robust, flush=True)
+    f, rep = gdf.fuse_stack(t, 0.01, tol=1e-6, robust=robust)
+    torch.cuda.synchronize()
+    print([r["vcycles"] for r in rep], max(r["rel_residual"] for r in rep), flush=True)
+    assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep)
+    f = f.cpu().numpy().astype(np.float64)
+    # the GPU's own g_s (the same deterministic smoothing, returned by a second
+    # call) defines the system each slice solves; the plain smoothing is also
+    # checked against the oracle's (robust decisions at the threshold are
+    # FP32 on the GPU, FP64 in the oracle: covered by the robust parity test)
+    _, _, gsm = gdf.fuse_stack(t, 0.01, tol=1e-6, robust=robust, return_smooth=True)
+    gs = gsm.cpu().numpy().astype(np.float64)
+    if not robust:
+        assert np.abs(gs - oracle.smooth(st)).max() <= 2e-4
+    # (the FP64 output: the residual of an FP32-rounded f can exceed tol by its rounding)
+    f64, rep64 = gdf.fuse_stack(t, 0.01, tol=1e-6, robust=robust, out_dtype=gdf.DTYPE_F64)
+    f64 = f64.cpu().numpy()
+    assert all(r["status"] == gdf.GDF_OK for r in rep64)
+    for z in (0, 12, 13, 14, 26, 27, 28, 39):
+        fr = oracle.solve(gs[z], st[z].astype(np.float64), 0.01, tol=1e-12)
+        err = np.abs(f[z] - fr).max()
+        rel = oracle.relres(f64[z], gs[z], st[z].astype(np.float64), 0.01)
+        print("slice", z, "err %.2e rel %.2e" % (err, rel), flush=True)
+        assert err <= 1e-3
+        assert rel <= 1.01e-6
 
 
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])

@@ -16,6 +16,8 @@ shares lie in [1/5, 4/5] (sigma_z >= 0.6), a symmetric linear ramp loses its
 two tails symmetrically, and any result is a convex combination of the
 window's values.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -71,3 +73,18 @@ def test_convex_combination():
         lo = st[max(0, z - 9):z + 10].min(axis=0)
         hi = st[max(0, z - 9):z + 10].max(axis=0)
         assert (rob[z] >= lo - 1e-9).all() and (rob[z] <= hi + 1e-9).all()
+
+
+def test_window_wider_than_the_oracle_holds_is_refused():
+    # the oracle keeps a window of at most 63 taps (radius 31); a wider window
+    # (sigma_z >= 32/3) is refused, in the wrapper and in the C routine, rather
+    # than silently cut short
+    st = np.full((3, 4, 5), 7, np.uint8)
+    with pytest.raises(ValueError):
+        oracle.smooth_robust(st, 1.0, 11.0)
+    v = oracle._load().oracle_smooth_robust_voxel
+    v.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                  ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    v.restype = ctypes.c_double
+    assert np.isnan(v(st.ctypes.data_as(ctypes.c_void_p), 3, 4, 5, 1.0, 11.0, 1, 1, 1))
+    assert abs(oracle.smooth_robust(st, 1.0, 10.0)[1, 1, 1] - 7.0) <= 1e-12   # radius 30: within the window
