@@ -35,7 +35,8 @@
  *  - `workspace_dev` is caller-allocated device memory of at least the size
  *    returned by the matching *_workspace_size call for the same arguments,
  *    aligned to 256 bytes.  The library allocates no device memory of its own
- *    apart from a small per-device cache of captured graphs (gdf_release).
+ *    apart from a small per-device cache of captured graphs (gdf_release) and
+ *    the static scratch of solve_slices_noalloc.
  *  - Argument checks run on the host before any device work and return
  *    GDF_EINVAL (with gdf_last_error() describing the argument).  No C++
  *    exception crosses this interface.
@@ -257,6 +258,29 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
 size_t gdf_smooth_transpose_workspace_size(int S, int H, int W);
 gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
                             float *out_dev, void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* solve_slices_noalloc: solve_slices for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as solve_slices, without the
+ * workspace: the library's static device scratch of GDF_NOALLOC_SCRATCH_BYTES
+ * per GPU (256 MiB, placed when the library is loaded on that GPU and held
+ * until the process ends) serves instead.  The call allocates no device
+ * memory and no page-locked host memory.
+ *  - GDF_ENOMEM (nothing launched) when gdf_solve_workspace_size for the same
+ *    batch and options exceeds GDF_NOALLOC_SCRATCH_BYTES (a single FP32 slice
+ *    of up to about 2900 x 2900 pixels fits).
+ *  - GDF_EUNSUPPORTED for opts.use_graph (instantiating a graph allocates).
+ *  - The device is the stream's (the current device for a NULL stream).
+ *  - Every call on one GPU uses that GPU's one scratch array, which keeps the
+ *    last call's contents (each call initialises what it reads).  Calls from
+ *    threads of one process are serialised per device, and each call returns
+ *    after its work on the stream has finished, so they do not overlap; calls
+ *    from two processes on one GPU use separate arrays.                       */
+#define GDF_NOALLOC_SCRATCH_BYTES (256u << 20)
+gdf_status solve_slices_noalloc(int n, const gdf_slice_desc *desc_host, int gs_dtype, const void *gs_dev,
+                                int go_dtype, const void *go_dev, int bc, double tol, void *f_dev,
+                                const gdf_solve_opts *opts, gdf_slice_report *report_host, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing for measurement.  When enabled, the library brackets every

@@ -78,6 +78,8 @@ SIGNATURES = {
     "solve_slices_backward": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _P, _P, _I, _D, _P, _P,
                                ctypes.POINTER(_D), ctypes.POINTER(SolveOpts), _P, _S,
                                ctypes.POINTER(SliceReport), _P], _I),
+    "solve_slices_noalloc": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _I, _P, _I, _D, _P,
+                              ctypes.POINTER(SolveOpts), ctypes.POINTER(SliceReport), _P], _I),
     "gdf_smooth_transpose_workspace_size": ([_I, _I, _I], _S),
     "smooth_transpose": ([_P, _I, _I, _I, _D, _D, _P, _P, _S, _P], _I),
 }

@@ -652,12 +652,22 @@ struct ProfScope {
 
 // ------------------------------------------------------------------ driver
 
+// Set for the duration of a solve_slices_noalloc call on this thread: host
+// reads of device flags then go to pageable memory instead of the page-locked
+// buffer below (whose first use allocates it).
+thread_local bool t_no_pinned = false;
+
 // Page-locked host buffer for the per-cycle convergence flags (a direct copy,
 // no staging through a bounce buffer), one per thread, grown as needed and
 // kept until the process ends.
 hipError_t pinned_flags(int n, int *&out)
 {
-
+    if (t_no_pinned) {
+        thread_local std::vector<int> pageable;
+        if ((int)pageable.size() < n) pageable.resize(n);
+        out = pageable.data();
+        return hipSuccess;
+    }
     thread_local int *buf = nullptr;
     thread_local int cap = 0;
     if (cap < n) {
@@ -2032,6 +2042,72 @@ static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, cons
     if (grad_alpha)
         for (int i = 0; i < n; ++i) grad_alpha[i] = h[i].aux;
     return collect(P, ws, s, report, tol, 1);
+}
+
+// ------------------------------------------------------ solve_slices_noalloc
+
+}  // extern "C"
+
+// Device scratch of solve_slices_noalloc: one array per GPU (the runtime
+// places it when the library's code object is loaded on that GPU) and held
+// until the process ends.  Host code never passes `gdf_scratch` itself to the
+// device (on the host the name is only a stand-in for the symbol): its device
+// address on each GPU comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char gdf_scratch[GDF_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];   // one call at a time per device (they share its scratch)
+void *g_scratch_ptr[kMaxDevices];       // device address per device, set under that device's lock
+
+}  // namespace
+
+extern "C" {
+
+gdf_status solve_slices_noalloc(int n, const gdf_slice_desc *d, int gs_dtype, const void *gs, int go_dtype,
+                                const void *go, int bc, double tol, void *f, const gdf_solve_opts *opts,
+                                gdf_slice_report *report, void *stream)
+{
+    const gdf_solve_opts b = opts_or_zero(opts);
+    if (b.use_graph)
+        return set_err(GDF_EUNSUPPORTED, "solve_slices_noalloc: use_graph is not available (instantiating a graph "
+                                         "allocates device memory)");
+    // argument checks and the scratch size come first, on the host
+    Opts o;
+    std::vector<int> H, W;
+    std::vector<double> al;
+    gdf_status r;
+    if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
+    const size_t need = gdf_solve_workspace_size(n, d, opts);
+    if (need == 0) return set_err(GDF_EINVAL, "solve_slices_noalloc: invalid batch");
+    if (need > (size_t)GDF_NOALLOC_SCRATCH_BYTES)
+        return set_err(GDF_ENOMEM, "solve_slices_noalloc: the batch needs %zu bytes of scratch, the static scratch "
+                                   "holds %zu (use solve_slices with a workspace)",
+                       need, (size_t)GDF_NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    if (s) HIP_TRY(hipStreamGetDevice(s, &dev));
+    else HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_err(GDF_EDEVICE, "solve_slices_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    if (!g_scratch_ptr[dev]) {
+        // once per device, with that device current
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(gdf_scratch));
+        if (cur != dev) HIP_TRY(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return set_err(GDF_EDEVICE, "solve_slices_noalloc: hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    t_no_pinned = true;
+    r = solve_slices(n, d, gs_dtype, gs, go_dtype, go, bc, tol, f, opts, g_scratch_ptr[dev],
+                     (size_t)GDF_NOALLOC_SCRATCH_BYTES, report, stream);
+    t_no_pinned = false;
+    return r;
 }
 
 }  // extern "C"

@@ -149,3 +149,20 @@ def test_streamed_rejects_device_or_float_stacks():
         gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.uint8), 0.01, chunk=0)
     with pytest.raises(ValueError):
         gdf.fuse_stack_streamed(torch.zeros((2, 8, 8), dtype=torch.uint8), 0.01, return_smooth=True)
+
+
+def test_noalloc_rejects_on_host():
+    # checks that return before any device work: a batch larger than the
+    # static scratch, and graph capture (whose instantiation allocates)
+    L = gdf.lib()
+    d = (gdf.SliceDesc * 1)()
+    d[0].H, d[0].W, d[0].alpha = 8192, 8192, 0.01
+    d[0].pitch_gs = d[0].pitch_go = d[0].pitch_f = 8192
+    o = gdf.make_opts()
+    call = lambda o: L.solve_slices_noalloc(1, d, 1, 1 << 20, 0, 1 << 21, 0, 1e-6, 1 << 22, ctypes.byref(o),
+                                            None, None)
+    assert call(o) == gdf.GDF_ENOMEM
+    assert "scratch" in gdf.last_error()
+    assert call(gdf.make_opts(use_graph=True)) == gdf.GDF_EUNSUPPORTED
+    d[0].alpha = -1.0
+    assert call(o) == gdf.GDF_EINVAL
