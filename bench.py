@@ -9,13 +9,18 @@ already resident in HBM (smoothing, all V-cycles, output formation).
 
 Prints one JSON line: throughput in Mvoxels/s, the roofline of the dominant
 kernel (the fused finest-level V-cycle pass) from HIP events around its
-launches, and the CPU oracle timed on a bounded sample of the same workload.
+launches, the other forms (batched, mixed precision, adjoint, FP64 small
+stack, ...), and the oracle leg: the CPU oracle timed on a bounded sample of
+the headline workload (cpu_baseline), and the maximum absolute error of every
+form's result against the FP64 oracle on sampled slices, crops or voxels.
+The oracle leg runs after every GPU measurement, so the two never overlap.
 """
 import argparse
 import hashlib
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -30,7 +35,8 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 S, H, W = 64, 2048, 2048
 ALPHA, TOL = 0.01, 1e-6
 SEED = 1001
-FINE_BYTES_PER_PX = 14.0   # FP32 fused finest pass: u 4 + b 4 + coarse 1 in, u 4 + coarse rhs 1 out
+CHECK_SLICES = (0, 31, 32)   # headline slices the oracle solves: an edge slice and the two at a chunk edge
+ORACLE_TOL = 1e-10           # oracle solves for the error checks (the GPU results are at 1e-6 or 1e-8)
 
 
 def log(*a):
@@ -49,23 +55,14 @@ def traffic_from_profile():
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(stack, z):
-    """The oracle as it stands on one slice of the workload: smoothing of every
-    voxel of slice z (tap-by-tap sums over the full stack) plus its CG solve to
-    the same 1e-6 relative residual."""
-    import oracle
-    oracle.build(force=False)
-    yy, xx = np.mgrid[0:H, 0:W]
-    pts = np.stack([np.full(H * W, z), yy.ravel(), xx.ravel()], axis=1).astype(np.int32)
-    t0 = time.perf_counter()
-    gs = oracle.smooth_points(stack, pts).reshape(H, W)
-    t1 = time.perf_counter()
-    oracle.solve(gs, stack[z].astype(np.float64), ALPHA, tol=TOL)
-    t2 = time.perf_counter()
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": H * W / (t2 - t0) / 1e6, "unit": "Mvoxels/s", "cores": cores, "kind": "oracle",
-            "sample": "slice %d of the 64x2048x2048 stack: FP64 tap-by-tap smoothing (%.1f s) + "
-                      "unpreconditioned CG to rel. residual 1e-6 (%.1f s)" % (z, t1 - t0, t2 - t1)}
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # the fused finest pass (FP32 level 0, bfloat16 coarse level): prolongation, no zero
@@ -119,18 +116,54 @@ def _timed(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) * 1e3 / steps, out
 
 
+def _maxerr(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).max())
+
+
+# Each form returns (result, check): `check` is None or a function run in the
+# oracle leg, after every GPU measurement, returning the keys it adds to the
+# result (max_abs_err_vs_oracle and what it was measured on).  A check only
+# holds host copies of the GPU's inputs and outputs.
+
+def bench_plain_fp64_small(gdf, torch, dev, steps):
+    """The plain method in FP64 on 8 x 256 x 256 (alpha 0.01, tol 1e-6), the
+    oracle timed on the same stack."""
+    S0, H0, W0 = 8, 256, 256
+    stack = synth.make_stack(S0, H0, W0, seed=synth.CONFIG_SEED[0])
+    st = torch.from_numpy(stack).to(dev)
+    log("fp64 small stack: timing")
+    ms, (f, rep) = _timed(torch, lambda: gdf.fuse_stack(st, ALPHA, tol=TOL, precision="fp64"), steps, 2)
+    f = f.cpu().numpy()
+    vox = S0 * H0 * W0
+    res = {"value": vox / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+           "workload": "fuse_stack FP64: 8 x 256 x 256 uint8 (no ramp), sigma_xy=1, sigma_z=3, alpha=0.01, "
+                       "Neumann, FP64 V-cycles to rel. residual 1e-6",
+           "worst_rel_residual": max(r["rel_residual"] for r in rep),
+           "vcycles_min_max": [min(r["vcycles"] for r in rep), max(r["vcycles"] for r in rep)]}
+
+    def check():
+        import oracle
+        t0 = time.perf_counter()
+        oracle.fuse_stack(stack, ALPHA, tol=TOL)   # the oracle on the same work: smoothing + CG to 1e-6
+        t_or = time.perf_counter() - t0
+        f_ref, _ = oracle.fuse_stack(stack, ALPHA, tol=1e-12)
+        return {"max_abs_err_vs_oracle": _maxerr(f, f_ref), "err_measured_on": "all 8 slices",
+                "oracle_Mvoxels_s": vox / t_or / 1e6, "oracle_threads": oracle.threads()}
+    return res, check
+
+
 def bench_batched(gdf, torch, dev, steps):
     """512 uneven slices (sides 512..4096 step 256, alpha ~ U(0.001, 0.1)) in one
     graph-captured solve_slices call, settings autotuned on the first call."""
     desc = synth.uneven_batch(512, seed=synth.CONFIG_SEED[2])
     log("batched: generating %d slices" % len(desc))
     go, gs, al = [], [], []
-    for H, W, a, sd in desc:
-        o, s = synth.batch_slice_t(H, W, sd, dev)
+    for H_, W_, a, sd in desc:
+        o, s = synth.batch_slice_t(H_, W_, sd, dev)
         go.append(o)
         gs.append(s)
         al.append(a)
-    px = float(sum(H * W for H, W, _, _ in desc))
+    px = float(sum(H_ * W_ for H_, W_, _, _ in desc))
     kw = dict(tol=TOL, use_graph=True, autotune=True)
     log("batched: autotuning")
     torch.cuda.synchronize()
@@ -142,28 +175,68 @@ def bench_batched(gdf, torch, dev, steps):
     log("batched: tuned %s in %.1f s; timing" % (tuned, t_tune))
     ms, (f, rep) = _timed(torch, lambda: gdf.solve_slices(gs, go, al, **kw), steps, 1)
     vc = [r["vcycles"] for r in rep]
-    return {"value": px / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
-            "workload": "solve_slices: 512 uneven slices (H, W uniform on 512..4096 step 256, %.3f Gpx), "
-                        "alpha per slice U(0.001, 0.1), FP32, tol 1e-6, one captured graph per call" % (px / 1e9),
-            "autotuned": tuned, "autotune_s": t_tune,
-            "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+    res = {"value": px / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+           "workload": "solve_slices: 512 uneven slices (H, W uniform on 512..4096 step 256, %.3f Gpx), "
+                       "alpha per slice U(0.001, 0.1), FP32, tol 1e-6, one captured graph per call" % (px / 1e9),
+           "autotuned": tuned, "autotune_s": t_tune,
+           "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+    # the oracle subset: the two smallest and two largest slices, the two lowest
+    # and two highest alphas (the test suite checks 16 and every residual)
+    n = len(desc)
+    pick = []
+    for k in (sorted(range(n), key=lambda i: desc[i][0] * desc[i][1])[:2] +
+              sorted(range(n), key=lambda i: -desc[i][0] * desc[i][1])[:2] +
+              sorted(range(n), key=lambda i: desc[i][2])[:2] + sorted(range(n), key=lambda i: -desc[i][2])[:2]):
+        if k not in pick:
+            pick.append(k)
+    held = [(i, gs[i].cpu().numpy(), go[i].cpu().numpy(), f[i].cpu().numpy()) for i in pick]
+
+    def check():
+        import oracle
+        errs = []
+        for i, s, o, fi in held:
+            fr = oracle.solve(s, o.astype(np.float64), desc[i][2], tol=ORACLE_TOL)
+            errs.append(_maxerr(fi, fr))
+        return {"max_abs_err_vs_oracle": max(errs),
+                "err_measured_on": "%d whole slices: the 2 smallest, 2 largest (4096 x 4096 among them), 2 lowest "
+                                   "and 2 highest alphas; (H, W, alpha, err) = %s" %
+                                   (len(held), [(desc[i][0], desc[i][1], round(desc[i][2], 5), float("%.3g" % e))
+                                                for (i, _, _, _), e in zip(held, errs)])}
+    return res, check
+
+
+MIXED_SHAPE = (4, 21504, 26624)
+MIXED_CROP = {0.001: ((0, 0), 1), 0.01: ((21504 - 1024, 26624 - 1024), 2)}   # 1024^2 crop corner, slice
 
 
 def bench_mixed(gdf, torch, dev, steps, alpha):
     """4 slices of 21504 x 26624: FP32 V-cycles inside FP64 refinement to 1e-8."""
-    S3, H3, W3 = 4, 21504, 26624
+    S3, H3, W3 = MIXED_SHAPE
     log("mixed: generating %dx%dx%d" % (S3, H3, W3))
     st = synth.make_stack_t(S3, H3, W3, synth.CONFIG_SEED[3], dev)
     run = lambda: gdf.fuse_stack(st, alpha, tol=1e-8, precision="mixed")
     log("mixed alpha=%g: timing" % alpha)
     ms, (f, rep) = _timed(torch, run, steps, 1)
-    del f
     vc = [r["vcycles"] for r in rep]
-    return {"value": S3 * H3 * W3 / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
-            "workload": "fuse_stack mixed: 4 x 21504 x 26624 uint8, sigma_xy=1, sigma_z=3, alpha=%g, FP32 "
-                        "V-cycles (3 per refinement step) + FP64 residual/update to FP64 rel. residual 1e-8"
-                        % alpha,
-            "worst_rel_residual": max(r["rel_residual"] for r in rep), "inner_vcycles_min_max": [min(vc), max(vc)]}
+    res = {"value": S3 * H3 * W3 / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+           "workload": "fuse_stack mixed: 4 x 21504 x 26624 uint8, sigma_xy=1, sigma_z=3, alpha=%g, FP32 "
+                       "V-cycles (3 per refinement step) + FP64 residual/update to FP64 rel. residual 1e-8"
+                       % alpha,
+           "worst_rel_residual": max(r["rel_residual"] for r in rep), "inner_vcycles_min_max": [min(vc), max(vc)]}
+    (y0, x0), z = MIXED_CROP[alpha]
+    fc = f[z, y0:y0 + 1024, x0:x0 + 1024].cpu().numpy()
+    del f, st
+
+    def check():
+        # (the crop oracle regenerates the crop's raw data from the generator's
+        # numpy definition)
+        from oracle.crop import fuse_crop
+        ref, _, _ = fuse_crop(synth.CONFIG_SEED[3], S3, H3, W3, alpha, y0, y0 + 1024, x0, x0 + 1024, [z],
+                              tol=1e-11)
+        return {"max_abs_err_vs_oracle": _maxerr(fc, ref[0]),
+                "err_measured_on": "1024 x 1024 crop at (%d, %d) of slice %d (crop oracle, halo %d px)" %
+                                   (y0, x0, z, int(np.ceil(40 / np.sqrt(alpha))))}
+    return res, check
 
 
 def bench_robust(gdf, torch, dev, stack, kw, steps):
@@ -172,6 +245,7 @@ def bench_robust(gdf, torch, dev, stack, kw, steps):
     run = lambda: gdf.fuse_stack(st, ALPHA, robust=True, **kw)
     log("robust: timing")
     ms, (f, rep) = _timed(torch, run, steps, 1)
+    fz = f[32].cpu().numpy()
     del f
     gdf.profile_reset()
     gdf.profile_enable(True)
@@ -181,11 +255,22 @@ def bench_robust(gdf, torch, dev, stack, kw, steps):
     n, sm, _ = gdf.profile_read("smooth")
     S_, H_, W_ = stack.shape
     vc = [r["vcycles"] for r in rep]
-    return {"value": S_ * H_ * W_ / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
-            "workload": "fuse_stack on the headline stack with robust cross-slice averaging (values beyond two "
-                        "weighted standard deviations of the window mean left out), FP32, tol 1e-6",
-            "smooth_ms": sm / max(1, n), "worst_rel_residual": max(r["rel_residual"] for r in rep),
-            "vcycles_min_max": [min(vc), max(vc)]}
+    res = {"value": S_ * H_ * W_ / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+           "workload": "fuse_stack on the headline stack with robust cross-slice averaging (values beyond two "
+                       "weighted standard deviations of the window mean left out), FP32, tol 1e-6",
+           "smooth_ms": sm / max(1, n), "worst_rel_residual": max(r["rel_residual"] for r in rep),
+           "vcycles_min_max": [min(vc), max(vc)]}
+
+    def check():
+        import oracle
+        yy, xx = np.mgrid[0:H_, 0:W_]
+        pts = np.stack([np.full(H_ * W_, 32), yy.ravel(), xx.ravel()], axis=1)
+        gsr = oracle.smooth_robust_points(stack, pts).reshape(H_, W_)
+        fr = oracle.solve(gsr, stack[32].astype(np.float64), ALPHA, tol=ORACLE_TOL)
+        return {"max_abs_err_vs_oracle": _maxerr(fz, fr),
+                "err_measured_on": "slice 32, the oracle's robust smoothing and solve (a value at the two-standard-"
+                                   "deviation threshold can be decided differently in FP32 and FP64)"}
+    return res, check
 
 
 def bench_stack_gradient(gdf, torch, dev, shape, steps):
@@ -197,10 +282,21 @@ def bench_stack_gradient(gdf, torch, dev, shape, steps):
     ms, out = _timed(torch, lambda: gdf.smooth_transpose(g, 1.0, 3.0), steps, 1)
     n = g.numel()
     del out, g
-    return {"value": n / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
-            "workload": "smooth_transpose (dLoss/dstack through the smoothing) on a %d x %d x %d FP32 gradient, "
-                        "sigma_xy=1, sigma_z=3" % tuple(shape),
-            "algo_GBps": 2 * 2 * 4 * n / (ms * 1e-3) / 1e9}
+    # the error check runs the same call on a smaller gradient (the oracle's
+    # transpose is a plain sum over every voxel's window)
+    gs_small = np.random.default_rng(5).standard_normal((19, 256, 256))
+    out_small = gdf.smooth_transpose(torch.from_numpy(gs_small).to(dev, torch.float32), 1.0, 3.0).cpu().numpy()
+    res = {"value": n / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+           "workload": "smooth_transpose (dLoss/dstack through the smoothing) on a %d x %d x %d FP32 gradient, "
+                       "sigma_xy=1, sigma_z=3" % tuple(shape),
+           "algo_GBps": 2 * 2 * 4 * n / (ms * 1e-3) / 1e9}
+
+    def check():
+        import oracle
+        ref = oracle.smooth_transpose(gs_small, 1.0, 3.0)
+        return {"max_abs_err_vs_oracle": _maxerr(out_small, ref), "err_scale": float(np.abs(ref).max()),
+                "err_measured_on": "a 19 x 256 x 256 standard-normal gradient through the same entry point"}
+    return res, check
 
 
 def bench_host_streamed(gdf, torch, stack, steps):
@@ -218,35 +314,46 @@ def bench_host_streamed(gdf, torch, stack, steps):
     del dev_out
     S_, H_, W_ = stack.shape
     vc = [r["vcycles"] for r in rep]
-    return {"value": S_ * H_ * W_ / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
-            "result_download_ms": d2h_ms, "d2h_GBps": out.numel() * 4 / (d2h_ms * 1e-3) / 1e9,
-            "workload": "fuse_stack_streamed: the headline stack in pinned host memory, chunks of %d slices " % CHUNK +
-                        "(+9 halo slices each side), FP32 result back to pinned host memory, tol 1e-6",
-            "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+    res = {"value": S_ * H_ * W_ / (ms * 1e-3) / 1e6, "unit": "Mvoxels/s", "ms_per_step": ms, "steps": steps,
+           "result_download_ms": d2h_ms, "d2h_GBps": out.numel() * 4 / (d2h_ms * 1e-3) / 1e9,
+           "workload": "fuse_stack_streamed: the headline stack in pinned host memory, chunks of %d slices " % CHUNK +
+                       "(+9 halo slices each side), FP32 result back to pinned host memory, tol 1e-6",
+           "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+    held = {z: out[z].numpy().copy() for z in (31, 32)}   # the two slices either side of the chunk edge
+    return res, held
 
 
 def bench_color(gdf, torch, dev, steps):
     """Colour fusion: 3 channels of 4096 x 4096 (low-frequency colour) with one
     grey image's gradients, FP32 to 1e-6, one batch."""
-    C, H, W = 3, 4096, 4096
-    grey, _ = synth.batch_slice_t(H, W, 7, dev)
+    C, H_, W_ = 3, 4096, 4096
+    grey, _ = synth.batch_slice_t(H_, W_, 7, dev)
     grey = grey.to(torch.float32)
     color = torch.stack([grey * 0.6 + 40.0, grey * 0.9, 200.0 - 0.5 * grey])
     color = torch.nn.functional.avg_pool2d(color[None], 9, stride=1, padding=4, count_include_pad=False)[0]
+    color = color.contiguous()
     log("color: timing")
-    ms, (f, rep) = _timed(torch, lambda: gdf.fuse_color(color.contiguous(), grey, 0.01, tol=1e-6), steps, 1)
-    del f
+    ms, (f, rep) = _timed(torch, lambda: gdf.fuse_color(color, grey, 0.01, tol=1e-6), steps, 1)
     vc = [r["vcycles"] for r in rep]
-    return {"value": C * H * W / (ms * 1e-3) / 1e6, "unit": "Mpixels/s (all channels)", "ms_per_step": ms,
-            "steps": steps, "workload": "fuse_color: 3 x 4096 x 4096 FP32 colour target with the gradients of "
-                                        "one grey image, alpha 0.01, tol 1e-6",
-            "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+    res = {"value": C * H_ * W_ / (ms * 1e-3) / 1e6, "unit": "Mpixels/s (all channels)", "ms_per_step": ms,
+           "steps": steps, "workload": "fuse_color: 3 x 4096 x 4096 FP32 colour target with the gradients of "
+                                       "one grey image, alpha 0.01, tol 1e-6",
+           "worst_rel_residual": max(r["rel_residual"] for r in rep), "vcycles_min_max": [min(vc), max(vc)]}
+    c0, g0, f0 = color[0].cpu().numpy(), grey.cpu().numpy(), f[0].cpu().numpy()
+    del f
+
+    def check():
+        import oracle
+        fr = oracle.solve(c0, g0.astype(np.float64), 0.01, tol=ORACLE_TOL)
+        return {"max_abs_err_vs_oracle": _maxerr(f0, fr), "err_measured_on": "channel 0 (whole 4096 x 4096 image)"}
+    return res, check
 
 
 def bench_adjoint(gdf, torch, dev, steps):
     """16 x 1024 x 1024 FP32: loss = sum (f - t)^2 through the autograd function."""
     S4, H4, W4 = 16, 1024, 1024
-    stack = synth.make_stack_t(S4, H4, W4, synth.CONFIG_SEED[4], dev)
+    stack_np = synth.make_stack(S4, H4, W4, synth.CONFIG_SEED[4])
+    stack = torch.from_numpy(stack_np).to(dev)
     _, _, gsm = gdf.fuse_stack(stack, ALPHA, return_smooth=True)
     gen = torch.Generator(device=dev)
     gen.manual_seed(synth.CONFIG_SEED[4])
@@ -268,12 +375,66 @@ def bench_adjoint(gdf, torch, dev, steps):
     ms_f, _ = _timed(torch, fwd, steps, 1)
     ms_fb, _ = _timed(torch, fwd_bwd, steps, 1)
     vox = S4 * H4 * W4
-    return {"value": vox / (ms_fb * 1e-3) / 1e6, "unit": "Mvoxels/s (forward + backward)",
-            "ms_per_step": ms_fb, "steps": steps, "forward_ms": ms_f, "backward_ms": ms_fb - ms_f,
-            "backward_Mvoxels_s": vox / ((ms_fb - ms_f) * 1e-3) / 1e6,
-            "workload": "ScreenedPoissonSolve on 16 x 1024 x 1024 FP32 (g_s = the method's smoothing), "
-                        "alpha=0.01, loss sum (f - t)^2; backward = adjoint solve (FP32 V-cycles in FP64 "
-                        "refinement) to 1e-6 + gradient assembly"}
+    res = {"value": vox / (ms_fb * 1e-3) / 1e6, "unit": "Mvoxels/s (forward + backward)",
+           "ms_per_step": ms_fb, "steps": steps, "forward_ms": ms_f, "backward_ms": ms_fb - ms_f,
+           "backward_Mvoxels_s": vox / ((ms_fb - ms_f) * 1e-3) / 1e6,
+           "workload": "ScreenedPoissonSolve on 16 x 1024 x 1024 FP32 (g_s = the method's smoothing), "
+                       "alpha=0.01, loss sum (f - t)^2; backward = adjoint solve (FP32 V-cycles in FP64 "
+                       "refinement) to 1e-6 + gradient assembly"}
+    zs = (0, 11)
+    held = {z: (gs.grad[z].cpu().numpy(), go.grad[z].cpu().numpy()) for z in zs}
+    t_np = tgt.cpu().numpy()
+    ga = float(alpha.grad)
+
+    def check():
+        import oracle
+        e_gs = e_go = 0.0
+        for z in zs:
+            pts = np.stack([np.full(H4 * W4, z)] + [a.ravel() for a in np.mgrid[0:H4, 0:W4]], axis=1)
+            gsz = oracle.smooth_points(stack_np, pts).reshape(H4, W4)
+            goz = stack_np[z].astype(np.float64)
+            fz = oracle.solve(gsz, goz, ALPHA, tol=ORACLE_TOL)
+            r_gs, r_go, _ = oracle.adjoint(2.0 * (fz - t_np[z]), gsz, fz, ALPHA, tol=ORACLE_TOL)
+            e_gs = max(e_gs, _maxerr(held[z][0], r_gs) / float(np.abs(r_gs).max()))
+            e_go = max(e_go, _maxerr(held[z][1], r_go) / float(np.abs(r_go).max()))
+        return {"max_abs_err_vs_oracle": {"dL_dg_s_rel_to_max": e_gs, "dL_dg_o_rel_to_max": e_go},
+                "dL_dalpha_gpu": ga,
+                "err_measured_on": "slices 0 and 11: the oracle's own smoothing, solve and adjoint; errors relative "
+                                   "to the largest gradient entry"}
+    return res, check
+
+
+def cpu_baseline(stack, f_gpu):
+    """The oracle as it stands on a bounded sample of the headline workload:
+    for each of three slices, FP64 tap-by-tap smoothing of every voxel of the
+    slice (over the full stack) plus its CG solve to the same 1e-6 relative
+    residual; the median of the three rates.  The smoothed slices are kept for
+    the headline's error check (CG to 1e-10 against the GPU's f)."""
+    import oracle
+    oracle.build(force=False)
+    rates, parts, gsz = [], [], {}
+    yy, xx = np.mgrid[0:H, 0:W]
+    for z in CHECK_SLICES:
+        pts = np.stack([np.full(H * W, z), yy.ravel(), xx.ravel()], axis=1).astype(np.int32)
+        t0 = time.perf_counter()
+        gs = oracle.smooth_points(stack, pts).reshape(H, W)
+        t1 = time.perf_counter()
+        oracle.solve(gs, stack[z].astype(np.float64), ALPHA, tol=TOL)
+        t2 = time.perf_counter()
+        rates.append(H * W / (t2 - t0) / 1e6)
+        parts.append("slice %d: smoothing %.1f s + CG %.1f s" % (z, t1 - t0, t2 - t1))
+        gsz[z] = gs
+    base = {"value": statistics.median(rates), "unit": "Mvoxels/s", "cores": oracle.threads(), "kind": "oracle",
+            "host_cpu": host_cpu_model(),
+            "sample": "median of 3 slices (%s) of the 64 x 2048 x 2048 stack: FP64 tap-by-tap smoothing of every "
+                      "voxel of the slice + unpreconditioned CG to rel. residual 1e-6; %s" %
+                      (", ".join(str(z) for z in CHECK_SLICES), "; ".join(parts)),
+            "rates": rates}
+    errs, refs = {}, {}
+    for z in CHECK_SLICES:
+        refs[z] = oracle.solve(gsz[z], stack[z].astype(np.float64), ALPHA, tol=ORACLE_TOL)
+        errs[z] = _maxerr(f_gpu[z], refs[z])
+    return base, errs, refs
 
 
 def main():
@@ -281,7 +442,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (CPU baseline and error checks)")
     # defaults: the settings the autotuner picks for this workload on MI355X
     # (--autotune runs the tuner instead, inside the untimed warm-up)
     ap.add_argument("--nu", type=int, default=2)
@@ -289,7 +450,7 @@ def main():
     ap.add_argument("--coarse-sweeps", type=int, default=3)
     ap.add_argument("--tile-rows", type=int, default=128)
     ap.add_argument("--no-forms", action="store_true",
-                    help="skip the batched, mixed-precision and adjoint measurements")
+                    help="skip the batched, mixed-precision, adjoint and other forms")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--launch", default="grid", choices=["default", "grid", "persistent"])
     ap.add_argument("--calib-copy", action="store_true",
@@ -353,6 +514,7 @@ def main():
     vox = S * H * W
     worst = max(r["rel_residual"] for r in rep)
     cycles = sorted(set(r["vcycles"] for r in rep))
+    f_check = {z: f[z].cpu().numpy() for z in CHECK_SLICES}
 
     n_fine, ms_fine, bytes_fine = gdf.profile_read("vcycle_fine")
     per_launch_bytes = bytes_fine / max(1, n_fine)
@@ -406,25 +568,43 @@ def main():
         "breakdown": breakdown,
     }
     del f, st
+    checks = {}
+    streamed_held = None
     if not args.no_forms:
         plain = out["value"]
         forms = {}
-        forms["batched"] = bench_batched(gdf, torch, dev, 3)
-        torch.cuda.empty_cache()
-        forms["mixed"] = bench_mixed(gdf, torch, dev, 2, 0.001)
-        forms["mixed_alpha_0.01"] = bench_mixed(gdf, torch, dev, 2, 0.01)
-        torch.cuda.empty_cache()
-        forms["adjoint"] = bench_adjoint(gdf, torch, dev, 5)
-        forms["robust"] = bench_robust(gdf, torch, dev, stack, kw, 3)
-        forms["stack_gradient"] = bench_stack_gradient(gdf, torch, dev, stack.shape, 5)
-        forms["color"] = bench_color(gdf, torch, dev, 3)
-        forms["host_streamed"] = bench_host_streamed(gdf, torch, stack, 3)
+        for name, fn in (("batched", lambda: bench_batched(gdf, torch, dev, 3)),
+                         ("mixed", lambda: bench_mixed(gdf, torch, dev, 2, 0.001)),
+                         ("mixed_alpha_0.01", lambda: bench_mixed(gdf, torch, dev, 2, 0.01)),
+                         ("adjoint", lambda: bench_adjoint(gdf, torch, dev, 5)),
+                         ("plain_fp64_small", lambda: bench_plain_fp64_small(gdf, torch, dev, 10)),
+                         ("robust", lambda: bench_robust(gdf, torch, dev, stack, kw, 3)),
+                         ("stack_gradient", lambda: bench_stack_gradient(gdf, torch, dev, stack.shape, 5)),
+                         ("color", lambda: bench_color(gdf, torch, dev, 3))):
+            forms[name], checks[name] = fn()
+            torch.cuda.empty_cache()
+        forms["host_streamed"], streamed_held = bench_host_streamed(gdf, torch, stack, 3)
         for v in forms.values():
             v["vs_plain"] = v["value"] / plain
         out["forms"] = forms
     if not args.no_cpu:
-        log("cpu baseline")
-        out["cpu_baseline"] = cpu_baseline(stack, S // 2)
+        # the oracle leg: CPU baseline, then every result against the oracle
+        log("oracle leg: cpu baseline")
+        base, errs, refs = cpu_baseline(stack, f_check)
+        out["cpu_baseline"] = base
+        out["max_abs_err_vs_oracle"] = max(errs.values())
+        out["err_measured_on"] = "whole slices %s (oracle smoothing of every voxel + CG to 1e-10)" % (
+            ", ".join(str(z) for z in CHECK_SLICES))
+        if streamed_held is not None:
+            out["forms"]["host_streamed"]["max_abs_err_vs_oracle"] = max(
+                _maxerr(streamed_held[z], refs[z]) for z in (31, 32))
+            out["forms"]["host_streamed"]["err_measured_on"] = "slices 31 and 32 (either side of the chunk edge)"
+        for name, chk in checks.items():
+            if chk is not None:
+                log("oracle leg: %s" % name)
+                t0 = time.perf_counter()
+                out["forms"][name].update(chk())
+                out["forms"][name]["oracle_check_s"] = time.perf_counter() - t0
     print(json.dumps(out), flush=True)
 
 

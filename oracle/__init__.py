@@ -53,12 +53,16 @@ def _load():
         I = ctypes.c_int
         D = ctypes.c_double
         L = ctypes.c_longlong
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = I
         lib.oracle_smooth_voxel.argtypes = [P, I, I, I, D, D, I, I, I]
         lib.oracle_smooth_voxel.restype = D
         lib.oracle_smooth.argtypes = [P, I, I, I, D, D, P]
         lib.oracle_smooth.restype = None
         lib.oracle_smooth_points.argtypes = [P, I, I, I, D, D, P, L, P]
         lib.oracle_smooth_points.restype = None
+        lib.oracle_smooth_robust_points.argtypes = [P, I, I, I, D, D, P, L, P]
+        lib.oracle_smooth_robust_points.restype = None
         lib.oracle_smooth_robust.argtypes = [P, I, I, I, D, D, P]
         lib.oracle_smooth_robust.restype = None
         lib.oracle_smooth_transpose.argtypes = [P, I, I, I, D, D, P]
@@ -79,6 +83,11 @@ def _load():
         lib.oracle_adjoint.restype = I
         _lib = lib
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(_load().oracle_threads())
 
 
 def _f64(a) -> np.ndarray:
@@ -210,6 +219,20 @@ def smooth_robust(stack: np.ndarray, sigma_xy: float = 1.0, sigma_z: float = 3.0
     S, H, W = st.shape
     out = np.empty((S, H, W), dtype=np.float64)
     _load().oracle_smooth_robust(_ptr(st), S, H, W, float(sigma_xy), float(sigma_z), _ptr(out))
+    return out
+
+
+def smooth_robust_points(stack: np.ndarray, zyx: np.ndarray, sigma_xy: float = 1.0,
+                         sigma_z: float = 3.0) -> np.ndarray:
+    """smooth_robust at the given (z, y, x) voxels."""
+    if sigma_z > 0 and int(np.floor(3.0 * sigma_z)) > 31:
+        raise ValueError("smooth_robust: cross-slice windows wider than 63 taps are not supported")
+    st = np.ascontiguousarray(stack, dtype=np.uint8)
+    S, H, W = st.shape
+    pts = np.ascontiguousarray(zyx, dtype=np.int32).reshape(-1, 3)
+    out = np.empty(len(pts), dtype=np.float64)
+    _load().oracle_smooth_robust_points(_ptr(st), S, H, W, float(sigma_xy), float(sigma_z), _ptr(pts),
+                                        len(pts), _ptr(out))
     return out
 
 

@@ -40,10 +40,14 @@
  *    oracle_smooth_robust_voxel for the reading taken.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads the OpenMP loops below run on (reported beside oracle timings). */
+int oracle_threads(void) { return omp_get_max_threads(); }
 
 #define ORACLE_BC_NEUMANN 0
 #define ORACLE_BC_PERIODIC 1
@@ -169,6 +173,16 @@ double oracle_smooth_robust_voxel(const uint8_t *stack, int S, int H, int W, dou
             den += w[i];
         }
     return num / den;
+}
+
+/* Robust values at a list of voxels (z, y, x triples). */
+void oracle_smooth_robust_points(const uint8_t *stack, int S, int H, int W, double sigma_xy, double sigma_z,
+                                 const int *zyx, long long n, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (long long i = 0; i < n; ++i)
+        out[i] = oracle_smooth_robust_voxel(stack, S, H, W, sigma_xy, sigma_z, zyx[3 * i], zyx[3 * i + 1],
+                                            zyx[3 * i + 2]);
 }
 
 void oracle_smooth_robust(const uint8_t *stack, int S, int H, int W, double sigma_xy, double sigma_z,

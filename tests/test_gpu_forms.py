@@ -357,13 +357,36 @@ def test_blank_slices_default_call_matches_oracle(robust):
         assert rel <= 1.01e-6
 
 
+def _robust_margin(st, z, y, x, sxy=1.0, sz=3.0):
+    """The oracle's decision margin at voxel (z, y, x): the smallest
+    |(p - mu)^2 - 4 var| over the in-stack taps of the cross-slice window (how
+    far each value is from the two-standard-deviation threshold), and the
+    largest |p - mu|; p are the in-plane smoothed values (the oracle's
+    smoothing with no cross-slice blur), mu and var their weighted mean and
+    variance with the cross-slice Gaussian weights."""
+    S = st.shape[0]
+    rz = int(np.floor(3 * sz))
+    zs = [zz for zz in range(z - rz, z + rz + 1) if 0 <= zz < S]
+    pts = np.array([[zz, y, x] for zz in zs], dtype=np.int32)
+    p = oracle.smooth_points(st, pts, sxy, 0.0)
+    w = np.exp(-(np.array(zs) - z) ** 2 / (2 * sz * sz))
+    mu = np.sum(w * p) / np.sum(w)
+    var = np.sum(w * (p - mu) ** 2) / np.sum(w)
+    return np.min(np.abs((p - mu) ** 2 - 4 * var)), np.max(np.abs(p - mu))
+
+
 @pytest.mark.parametrize("precision", ["fp32", "mixed"])
 def test_robust_averaging_matches_oracle(precision):
     # EM-like stack with a corrupt slice.  Whether a value lies within two
     # standard deviations is decided in FP32 on the GPU and in FP64 in the
-    # oracle, so a value right at the threshold can go either way: at most one
-    # voxel in a thousand may differ by more than the smoothing bar.  The solve
-    # is then checked against the oracle on the GPU's own smoothed stack.
+    # oracle, so a value right at the threshold can go either way.  Every
+    # voxel that differs by more than the smoothing bar must be such a tie:
+    # with in-plane values off by at most e (FP32 rounding of a 49-tap sum of
+    # values <= 255: e = 1e-3), p - mu is off by at most 2e and var by at most
+    # 4 e M + 4 e^2 (M = max |p - mu|), so (p - mu)^2 - 4 var moves by at most
+    # 20 e M + 20 e^2; a decision can flip only where the oracle's margin is
+    # within that.  At most one voxel in a thousand may be such a tie.  The
+    # solve is then checked against the oracle on the GPU's own smoothed stack.
     st = synth.make_stack(24, 70, 90, seed=51, ramp=True)
     st[11, 20:] = 3
     t = torch.from_numpy(st).to(DEV)
@@ -375,6 +398,11 @@ def test_robust_averaging_matches_oracle(precision):
     bad = np.abs(gs - ref) > 2e-4
     print(precision, "voxels off", int(bad.sum()), "of", bad.size, "max err", float(np.abs(gs - ref).max()))
     assert bad.mean() <= 1e-3
+    e = 1e-3
+    for z, y, x in zip(*np.nonzero(bad)):
+        margin, M = _robust_margin(st, z, y, x)
+        print("tie at", (z, y, x), "margin %.3e bound %.3e" % (margin, 20 * e * M + 20 * e * e))
+        assert margin <= 20 * e * M + 20 * e * e
     fr = oracle.solve_stack(gs, st.astype(np.float64), 0.01, tol=1e-12)
     assert np.abs(f.cpu().numpy() - fr).max() <= 1e-3
     assert all(r["status"] == gdf.GDF_OK for r in rep)
@@ -443,21 +471,31 @@ def test_fuse_stack_backward_matches_oracle():
     assert err <= 1e-3 * np.abs(ref).max()
 
 
-def test_fuse_color_matches_oracle():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fuse_color_matches_oracle(precision):
     # colour value constraints with grey gradients: each channel is Eq. (1)
-    # with g_s the channel and g_o the grey image
+    # with g_s the channel and g_o the grey image; FP64 to 1e-8, and FP32 (the
+    # benchmark's form) to 1e-6 with the FP64 residual recomputed on the CPU
     rng = np.random.default_rng(17)
     H, W = 90, 130
     base, _ = synth.batch_slice(H, W, 5)
     grey = base.astype(np.float64)
     color = np.stack([grey * 0.6 + 40, grey * 0.9, 200 - grey * 0.5]) + rng.normal(0, 2, (3, H, W))
     blur = oracle.smooth(np.clip(color, 0, 255).astype(np.uint8), 4.0, 0.0)   # low-frequency colour
-    f, rep = gdf.fuse_color(torch.from_numpy(blur).to(DEV), torch.from_numpy(grey).to(DEV), 0.01, tol=1e-8,
-                            precision="fp64")
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    tol = 1e-8 if precision == "fp64" else 1e-6
+    blur_in, grey_in = blur.astype(np.float32 if precision == "fp32" else np.float64), grey
+    f, rep = gdf.fuse_color(torch.from_numpy(blur_in).to(DEV, dt), torch.from_numpy(grey_in).to(DEV, dt), 0.01,
+                            tol=tol, precision=precision, out_dtype=gdf.DTYPE_F64)
     torch.cuda.synchronize()
     for c in range(3):
-        ref = oracle.solve(blur[c], grey, 0.01, tol=1e-12)
-        assert np.abs(f[c].cpu().numpy() - ref).max() <= 1e-4
+        g_c = blur_in[c].astype(np.float64)
+        ref = oracle.solve(g_c, grey, 0.01, tol=1e-12)
+        err = np.abs(f[c].cpu().numpy() - ref).max()
+        rel = oracle.relres(f[c].cpu().numpy(), g_c, grey, 0.01)
+        print(precision, "channel", c, "err %.2e rel %.2e" % (err, rel), flush=True)
+        assert err <= (1e-4 if precision == "fp64" else 1e-3)
+        assert rel <= tol * 1.01
         assert rep[c]["status"] == gdf.GDF_OK
 
 

@@ -185,3 +185,34 @@ def test_smoothing_radii(sigma_xy, sigma_z, precision):
     assert gerr <= (2e-4 if precision == "fp32" else 1e-9)
     assert ferr <= ABS_TOL
     assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= 1e-6 for r in rep)
+
+
+@pytest.mark.parametrize("S,H,W,Wp,extra_rows,precision", [(5, 70, 93, 101, 3, "fp32"), (6, 64, 128, 160, 5, "fp32"),
+                                                            (4, 50, 77, 80, 2, "mixed")])
+def test_fuse_stack_pitched_stack(S, H, W, Wp, extra_rows, precision):
+    # a stack viewed inside a larger buffer: row pitch Wp > W and slice pitch
+    # (H + extra_rows) Wp > H Wp, through fuse_stack's pitches.  An odd width
+    # takes the smoothing's byte loads; W = 128 with a 160-byte pitch the
+    # dword loads with a pitch; the output pass and the FP64 re-solve of the
+    # mixed scheme read g_o at the pitched offsets.  The bytes between rows
+    # and slices hold 255 and must not leak into the result.
+    stack = synth.make_stack(S, H, W, seed=300 + W, ramp=True)
+    big = torch.full((S, H + extra_rows, Wp), 255, dtype=torch.uint8, device=DEV)
+    view = big[:, :H, :W]
+    view.copy_(torch.from_numpy(stack).to(DEV))
+    assert view.stride() == ((H + extra_rows) * Wp, Wp, 1)
+    print("pitched", (S, H, W), "pitches", view.stride()[:2], precision, flush=True)
+    f, rep, gsm = gdf.fuse_stack(view, 0.01, tol=1e-6, precision=precision, return_smooth=True,
+                                 out_dtype=gdf.DTYPE_F64)
+    f2, rep2 = gdf.fuse_stack(view, 0.01, tol=1e-6, precision=precision)   # no g_s output
+    torch.cuda.synchronize()
+    f_ref, gs_ref = oracle.fuse_stack(stack, 0.01, tol=1e-12)
+    gerr = np.abs(gsm.cpu().numpy().astype(np.float64) - gs_ref).max()
+    err = np.abs(f.cpu().numpy() - f_ref).max()
+    err2 = np.abs(f2.cpu().numpy().astype(np.float64) - f_ref).max()
+    print("smoothing err %.2e f err %.2e (without g_s %.2e)" % (gerr, err, err2), flush=True)
+    assert gerr <= 2e-4
+    assert err <= ABS_TOL and err2 <= ABS_TOL
+    cpu_rel = _relres_stack(f.cpu().numpy(), gsm.cpu().numpy().astype(np.float64), stack.astype(np.float64), 0.01)
+    assert max(cpu_rel) <= 1e-6 * 1.01
+    assert all(r["status"] == gdf.GDF_OK for r in rep + rep2)

@@ -1,9 +1,9 @@
-"""The crop oracle equals the full oracle inside the crop (pins crop_oracle)."""
+"""The crop oracle equals the full oracle inside the crop (pins oracle.crop)."""
 import numpy as np
 
 import oracle
 import synth
-from crop_oracle import crop_halo, fuse_crop
+from oracle.crop import crop_halo, fuse_crop
 
 
 def test_crop_matches_full_solve():

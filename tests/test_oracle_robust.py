@@ -88,3 +88,13 @@ def test_window_wider_than_the_oracle_holds_is_refused():
     v.restype = ctypes.c_double
     assert np.isnan(v(st.ctypes.data_as(ctypes.c_void_p), 3, 4, 5, 1.0, 11.0, 1, 1, 1))
     assert abs(oracle.smooth_robust(st, 1.0, 10.0)[1, 1, 1] - 7.0) <= 1e-12   # radius 30: within the window
+
+
+def test_points_equal_whole_stack():
+    # the point form evaluates the same voxel routine as the whole-stack form
+    rng = np.random.default_rng(4)
+    st = rng.integers(0, 256, (12, 9, 11)).astype(np.uint8)
+    st[5] = 0
+    full = oracle.smooth_robust(st, 1.0, 3.0)
+    pts = np.stack([rng.integers(0, n, 50) for n in st.shape], axis=1)
+    np.testing.assert_array_equal(oracle.smooth_robust_points(st, pts, 1.0, 3.0), full[tuple(pts.T)])
