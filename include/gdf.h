@@ -65,7 +65,11 @@ typedef enum {
 
 typedef enum {
     GDF_BC_NEUMANN = 0,    /* reflecting edges: the energy's natural boundary condition */
-    GDF_BC_PERIODIC = 1,   /* wrap-around (the paper's Fourier basis); not implemented on the GPU */
+    GDF_BC_PERIODIC = 1,   /* wrap-around (the paper's Fourier basis, Section III-B): the first
+                              and last row and column of a slice are neighbours; a side of two
+                              pixels couples them across both faces, a side of one has no
+                              coupling.  Solved by a multigrid of its own (plain per-level
+                              kernels); workspace sizes are the same for either boundary. */
     GDF_BC_DIRICHLET = 2   /* boundary values are not specified by the method: GDF_EUNSUPPORTED */
 } gdf_bc;
 
@@ -153,7 +157,8 @@ void gdf_release(void);
  * stack_dev      uint8 [S][H][W] at element strides (pitch_slice, pitch_row);
  *                W <= 4194304.
  * alpha          screening weight, > 0 and finite.
- * bc             gdf_bc; only GDF_BC_NEUMANN runs on the GPU.
+ * bc             gdf_bc: GDF_BC_NEUMANN or GDF_BC_PERIODIC (the blend only: the
+ *                smoothing renormalises at the stack's edges for either).
  * tol            target relative residual per slice, in (0, 1).
  * sigma_xy/z     Gaussian widths in pixels/slices, >= 0; 0 disables that axis.
  *                The kernel is truncated at floor(3 sigma) taps per axis and

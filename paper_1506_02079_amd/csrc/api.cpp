@@ -130,11 +130,9 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
 
 gdf_status check_common(int bc, double tol)
 {
-    if (bc == GDF_BC_PERIODIC)
-        return set_err(GDF_EUNSUPPORTED, "periodic boundaries are not implemented on the GPU path");
     if (bc == GDF_BC_DIRICHLET)
         return set_err(GDF_EUNSUPPORTED, "Dirichlet boundaries need boundary values the method does not define");
-    if (bc != GDF_BC_NEUMANN) return set_err(GDF_EINVAL, "unknown boundary condition %d", bc);
+    if (bc != GDF_BC_NEUMANN && bc != GDF_BC_PERIODIC) return set_err(GDF_EINVAL, "unknown boundary condition %d", bc);
     if (!(tol > 0.0 && tol < 1.0)) return set_err(GDF_EINVAL, "tol must be in (0, 1) (got %g)", tol);
     return GDF_OK;
 }
@@ -224,10 +222,19 @@ struct Plan {
     long long n_partd = 0;
     bool mixed = false;
     bool need_gs_copy = false;   // fuse_stack MIXED without g_smooth output
+    // periodic boundaries: tiles of every level (list l = all slices having
+    // level l, the slices with a level below l first: pmid[l] items); level
+    // 0's per-slice slot ranges.  Every plan reserves the tables and partial
+    // sums they need, so workspace sizes do not depend on the boundary.
+    bool periodic = false;
+    std::vector<PItem> pitems;
+    int poff[kMaxLevels], pcnt[kMaxLevels], pmid[kMaxLevels];
+    std::vector<int> ranges_p0;
+    long long n_pitems = 0, n_p0 = 0;
     // layout (bytes from the workspace base)
     size_t off_tables, tables_bytes;
     size_t off_state, off_active, off_only, off_done, off_desc, off_items, off_r_cycle, off_r_tiles, off_r_ftiles,
-        off_r_smooth, off_io, off_u64tab;
+        off_r_smooth, off_io, off_u64tab, off_pitems, off_r_p0;
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
 
@@ -454,6 +461,37 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.n_tiles = tb;
     P.n_ftiles = fb;
     P.n_partd = tb;
+    // periodic tiles (counted for every plan, built for periodic ones)
+    auto ptiles = [&](int s, int l) {
+        return (long long)((P.g[s].h[l] + kPTileH - 1) / kPTileH) * ((P.g[s].w[l] + kPTileW - 1) / kPTileW);
+    };
+    for (int s = 0; s < n; ++s)
+        for (int l = 0; l < P.g[s].nlev; ++l) {
+            P.n_pitems += ptiles(s, l);
+            if (l == 0) P.n_p0 += ptiles(s, l);
+        }
+    P.n_partd = std::max(P.n_partd, P.n_p0);
+    P.ranges_p0.assign(2 * n, 0);
+    for (int l = 0; l < kMaxLevels; ++l) P.poff[l] = P.pcnt[l] = P.pmid[l] = 0;
+    if (P.periodic) {
+        std::vector<int> order(n);
+        for (int s = 0; s < n; ++s) order[s] = s;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return P.g[a].nlev > P.g[b].nlev; });
+        for (int l = 0; l <= P.max_level; ++l) {
+            P.poff[l] = (int)P.pitems.size();
+            for (int s : order) {
+                const SliceGeom &g = P.g[s];
+                if (g.nlev <= l) continue;
+                if (l == 0) P.ranges_p0[2 * s] = (int)P.pitems.size() - P.poff[0];
+                for (int y0 = 0; y0 < g.h[l]; y0 += kPTileH)
+                    for (int x0 = 0; x0 < g.w[l]; x0 += kPTileW)
+                        P.pitems.push_back(PItem{P.desc_base[s] + l, s, x0, y0});
+                if (l == 0) P.ranges_p0[2 * s + 1] = (int)P.pitems.size() - P.poff[0];
+                if (g.nlev > l + 1) P.pmid[l] = (int)P.pitems.size() - P.poff[l];
+            }
+            P.pcnt[l] = (int)P.pitems.size() - P.poff[l];
+        }
+    }
     if (smooth_S > 0) {
         // smoothing partials: [S][tiles]
         const long long nparts = (long long)((W[0] + kSmoothTileW - 1) / kSmoothTileW) *
@@ -465,7 +503,7 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
         }
         P.n_partd = std::max<long long>(P.n_partd, nparts * n);
     }
-    if (P.n_partd > 0x7fffffffLL || P.items.size() > 0x7fffffffULL)
+    if (P.n_partd > 0x7fffffffLL || P.items.size() > 0x7fffffffULL || P.n_pitems > 0x7fffffffLL)
         return set_err(GDF_EUNSUPPORTED, "problem too large for 32-bit work indices");
     // layout: [tables][partials][gs copy][arena]
     size_t o2 = 0;
@@ -483,6 +521,8 @@ gdf_status make_plan(Plan &P, int n, const std::vector<int> &H, const std::vecto
     P.off_r_smooth = take(sizeof(int) * 2 * n);
     P.off_io = take(sizeof(SliceIO) * n);
     P.off_u64tab = take(sizeof(double *) * 2 * n);
+    P.off_r_p0 = take(sizeof(int) * 2 * n);
+    P.off_pitems = take(sizeof(PItem) * (size_t)std::max<long long>(1, P.n_pitems));
     P.tables_bytes = o2;
     P.off_partf = take(sizeof(float2) * std::max(1, P.n_norm));
     P.off_partd = take(sizeof(double) * std::max<long long>(1, P.n_partd));
@@ -520,7 +560,7 @@ std::vector<char> bind_tables(const Plan &P, char *ws, const std::vector<SliceIO
             }
         }
     }
-    std::vector<char> img(P.tables_bytes, 0);
+    std::vector<char> img(P.periodic ? P.tables_bytes : P.off_pitems, 0);
     // state zeroed except the per-slice constants; active = 1
     SliceState *st = reinterpret_cast<SliceState *>(img.data() + P.off_state);
     int *act = reinterpret_cast<int *>(img.data() + P.off_active);
@@ -537,6 +577,9 @@ std::vector<char> bind_tables(const Plan &P, char *ws, const std::vector<SliceIO
     if (!P.ranges_smooth.empty())
         std::memcpy(img.data() + P.off_r_smooth, P.ranges_smooth.data(), sizeof(int) * 2 * P.n);
     std::memcpy(img.data() + P.off_io, io.data(), sizeof(SliceIO) * P.n);
+    std::memcpy(img.data() + P.off_r_p0, P.ranges_p0.data(), sizeof(int) * 2 * P.n);
+    if (!P.pitems.empty())
+        std::memcpy(img.data() + P.off_pitems, P.pitems.data(), sizeof(PItem) * P.pitems.size());
     if (P.mixed) {
         double **tab = reinterpret_cast<double **>(img.data() + P.off_u64tab);
         for (int s = 0; s < P.n; ++s) {
@@ -558,11 +601,11 @@ std::vector<std::pair<std::vector<unsigned long long>, std::shared_ptr<const Pla
 
 gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vector<int> &H,
                        const std::vector<int> &W, const std::vector<double> &al, const Opts &o, int smooth_S,
-                       bool need_gs)
+                       bool need_gs, bool periodic = false)
 {
     std::vector<unsigned long long> key;
-    for (int v : {n, smooth_S, need_gs ? 1 : 0, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype, o.use_graph, o.tile_rows,
-                  o.inner, o.launch, o.fsw})
+    for (int v : {n, smooth_S, need_gs ? 1 : 0, periodic ? 1 : 0, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype,
+                  o.use_graph, o.tile_rows, o.inner, o.launch, o.fsw})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
         key_push(key, H[i]);
@@ -580,6 +623,7 @@ gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vecto
     }
     auto p = std::make_shared<Plan>();
     p->need_gs_copy = need_gs;
+    p->periodic = periodic;
     const gdf_status r = make_plan(*p, n, H, W, al, o, smooth_S);
     if (r) return r;
     std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -700,6 +744,8 @@ struct Run {
     double **u64tab;
     float2 *partf;
     double *partd, *partd2, *partd3;
+    PItem *pitems;
+    int *r_p0;
     std::vector<char> active_host;
     double tol;
     int max_cycles;
@@ -726,7 +772,81 @@ struct Run {
         partd = reinterpret_cast<double *>(ws + P.off_partd);
         partd2 = reinterpret_cast<double *>(ws + P.off_partd2);
         partd3 = reinterpret_cast<double *>(ws + P.off_partd3);
+        pitems = reinterpret_cast<PItem *>(ws + P.off_pitems);
+        r_p0 = reinterpret_cast<int *>(ws + P.off_r_p0);
         active_host.assign(P.n, 1);
+    }
+
+    // ---- periodic boundaries
+    // launch arguments over level l's tiles (mid: only the slices that have a
+    // level below l)
+    PLaunch plaunch(int l, bool mid = false) const
+    {
+        PLaunch a{};
+        a.levs = desc;
+        a.items = pitems + P.poff[l];
+        a.n_items = mid ? P.pmid[l] : P.pcnt[l];
+        a.active = active;
+        // the per-cycle norms go to their own arrays: the output pass keeps the
+        // partial sums of slices it skips in a resume round in partd
+        a.part_rr = partd2;
+        a.part_r = partd3;
+        return a;
+    }
+    gdf_status psmooth(int l, int half_sweeps, int &cur, bool zero_first, bool fp64)
+    {
+        for (int h = 0; h < half_sweeps; ++h) {
+            PLaunch a = plaunch(l);
+            a.colour = h & 1;
+            a.in_sel = cur;
+            a.out_sel = cur ^ 1;
+            a.zero_in = h == 0 && zero_first;
+            ProfScope ps(PC_COARSE, 0.0, s, capturing);
+            HIP_TRY(launch_psmooth_level(fp64, l == 0, a, s));
+            cur ^= 1;
+        }
+        return GDF_OK;
+    }
+    // One V-cycle with periodic boundaries: down the levels (pre-smoothing,
+    // residual restricted into the next level's right-hand side; coarse levels
+    // start from zero), then up (prolongation of the coarser iterate, post-
+    // smoothing).  Each slice's coarsest level is smoothed on the way down and
+    // on the way up.  Level 0 takes nu sweeps each way, the coarse levels
+    // coarse_sweeps; an even number of half-sweeps per cycle leaves the
+    // level-0 iterate in buffer 0.
+    gdf_status pcycle(bool fp64, bool zero)
+    {
+        gdf_status r;
+        int cur[kMaxLevels] = {0};
+        for (int l = 0; l <= P.max_level; ++l) {
+            if ((r = psmooth(l, 2 * (l == 0 ? P.o.nu : P.o.csw), cur[l], l > 0 || zero, fp64))) return r;
+            if (l < P.max_level) {
+                PLaunch a = plaunch(l + 1);
+                a.in_sel = cur[l];
+                ProfScope ps(PC_COARSE, 0.0, s, capturing);
+                HIP_TRY(launch_prestrict_level(fp64, l == 0, a, s));
+            }
+        }
+        for (int l = P.max_level; l >= 0; --l) {
+            if (l < P.max_level) {
+                PLaunch a = plaunch(l, true);
+                a.in_sel = cur[l];
+                a.coarse_sel = cur[l + 1];
+                ProfScope ps(PC_COARSE, 0.0, s, capturing);
+                HIP_TRY(launch_pprolong_level(fp64, l == 0, a, s));
+            }
+            if ((r = psmooth(l, 2 * (l == 0 ? P.o.nu : P.o.csw), cur[l], false, fp64))) return r;
+        }
+        return GDF_OK;
+    }
+    // the in-loop convergence check after a cycle
+    gdf_status check_cycle(bool fp64)
+    {
+        if (!P.periodic) return finish(r_cycle, partf, nullptr, FIN_CHECK, 1);
+        PLaunch a = plaunch(0);
+        a.in_sel = 0;
+        HIP_TRY(launch_pnorm(fp64, a, s));
+        return finish(r_p0, nullptr, partd2, FIN_CHECK, 1, partd3);
     }
 
     // algorithmic bytes of a list's pass over the slices still iterating
@@ -766,11 +886,14 @@ struct Run {
 
     // The in-loop test uses 0.99 tol: the working-precision residual can sit a
     // hair below the exact FP64 residual of the output, which is checked after.
-    gdf_status finish(const int *range, const float2 *pf, const double *pd, int mode, int count)
+    // (in-loop checks -- strip partials, or FP64 partials with the sums of r --
+    // use the working-precision residual)
+    gdf_status finish(const int *range, const float2 *pf, const double *pd, int mode, int count,
+                      const double *pd2 = nullptr)
     {
-        const bool in_loop = mode == FIN_CHECK && pf;
+        const bool in_loop = mode == FIN_CHECK && (pf || pd2);
         const double t = in_loop ? 0.99 * tol : tol;
-        HIP_TRY(launch_finish(P.n, range, pf, pd, mode, t, max_cycles, count, in_loop ? stall_ratio : 0.0, st,
+        HIP_TRY(launch_finish(P.n, range, pf, pd, pd2, mode, t, max_cycles, count, in_loop ? stall_ratio : 0.0, st,
                               active, s));
         return GDF_OK;
     }
@@ -796,6 +919,7 @@ struct Run {
 
     gdf_status first_pass(bool fp64)
     {
+        if (P.periodic) return GDF_OK;   // (the first periodic cycle starts from zero)
         const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
@@ -812,6 +936,7 @@ struct Run {
     // zero: the finest iterate is zero (first cycle after a restricting first pass)
     gdf_status cycle(int k, bool fp64, bool slice_par = true, bool zero = false)
     {
+        if (P.periodic) return pcycle(fp64, zero);
         const double e = fp64 ? 8.0 : 4.0, ce = fp64 ? 8.0 : 2.0;
         gdf_status r;
         if ((r = coarse(fp64))) return r;
@@ -855,7 +980,7 @@ struct Run {
             HIP_TRY(launch_done(P.n, active, done, s));
             for (int k = 1; k <= (captured ? captured : max_cycles); ++k) {
                 if ((r = cycle(k, fp64, true, z && k == 1))) return r;
-                if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
+                if ((r = check_cycle(fp64))) return r;
                 HIP_TRY(launch_done(P.n, active, done, s));
             }
             return GDF_OK;
@@ -870,7 +995,7 @@ struct Run {
                 if (!any) break;
             }
             if ((r = cycle(k, fp64, true, z && k == 1))) return r;
-            if ((r = finish(r_cycle, partf, nullptr, FIN_CHECK, 1))) return r;
+            if ((r = check_cycle(fp64))) return r;
         }
         return GDF_OK;
     }
@@ -1016,11 +1141,15 @@ gdf_status mixed_iterate(Run &R, int gs_dtype, const void *gs, int go_dtype, con
     ra.in_sel = 1;
     ra.e_sel = 0;
     ra.first = 1;
-    {
+    // (periodic boundaries: tiles of the periodic lists, the inner solve's
+    // correction in level-0 buffer 0)
+    auto refine = [&]() -> hipError_t {
         ProfScope ps(PC_REFINE, 0.0, R.s, R.capturing);
-        HIP_TRY(launch_refine(ra, R.s));
-    }
-    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_CHECK, 0))) return r;
+        return P.periodic ? launch_prefine(ra, R.plaunch(0), R.s) : launch_refine(ra, R.s);
+    };
+    const int *rr_range = P.periodic ? R.r_p0 : R.r_tiles;
+    HIP_TRY(refine());
+    if ((r = R.finish(rr_range, nullptr, R.partd, FIN_CHECK, 0))) return r;
     const int steps = std::max(1, P.o.max_vc / P.o.inner);
     const int saved_max = R.max_cycles;
     R.max_cycles = steps;
@@ -1035,12 +1164,9 @@ gdf_status mixed_iterate(Run &R, int gs_dtype, const void *gs, int go_dtype, con
             if ((r = R.cycle(c, false, false, c == 1))) return r;
         ra.first = 0;
         ra.in_sel = (k - 1) & 1;
-        ra.e_sel = P.o.inner & 1;
-        {
-            ProfScope ps(PC_REFINE, 0.0, R.s, R.capturing);
-            HIP_TRY(launch_refine(ra, R.s));
-        }
-        if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_CHECK, 1))) return r;
+        ra.e_sel = P.periodic ? 0 : P.o.inner & 1;
+        HIP_TRY(refine());
+        if ((r = R.finish(rr_range, nullptr, R.partd, FIN_CHECK, 1))) return r;
     }
     R.max_cycles = saved_max;
     return GDF_OK;
@@ -1070,11 +1196,20 @@ gdf_status solve_body(Run &R, const SolveIO &x)
             {
                 // (later rounds touch only the resumed slices: not counted)
                 ProfScope ps(PC_FINALIZE, round ? 0.0 : all_px * (2.0 * P.esz + go_b + f_b), R.s, R.capturing);
-                HIP_TRY(launch_finalize(P.fp64, rows, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n,
-                                        rows ? P.n_ftiles : P.n_tiles, R.desc, R.st, round ? R.only : nullptr,
-                                        R.partd, R.s));
+                if (P.periodic) {
+                    PLaunch a = R.plaunch(0);
+                    a.in_sel = 0;
+                    a.part_rr = R.partd;
+                    HIP_TRY(launch_pfinalize(P.fp64, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, a, R.st,
+                                             round ? R.only : nullptr, R.s));
+                } else {
+                    HIP_TRY(launch_finalize(P.fp64, rows, x.go_dtype, x.go, P.o.out_dtype, x.f, R.io, P.n,
+                                            rows ? P.n_ftiles : P.n_tiles, R.desc, R.st, round ? R.only : nullptr,
+                                            R.partd, R.s));
+                }
             }
-            if ((r = R.finish(rows ? R.r_ftiles : R.r_tiles, nullptr, R.partd, FIN_FINAL, 0))) return r;
+            if ((r = R.finish(P.periodic ? R.r_p0 : (rows ? R.r_ftiles : R.r_tiles), nullptr, R.partd, FIN_FINAL, 0)))
+                return r;
             if (R.capturing) {
                 if (round == 2) break;
                 HIP_TRY(launch_resume_flags(P.n, R.st, R.tol, R.max_cycles, R.active, R.only, R.s));
@@ -1357,11 +1492,11 @@ static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long 
 }
 
 static gdf_status fuse_plan(std::shared_ptr<const Plan> &P, int S, int H, int W, double alpha, const Opts &o,
-                            bool need_gs)
+                            bool need_gs, bool periodic = false)
 {
     std::vector<int> Hs(S, H), Ws(S, W);
     std::vector<double> al(S, alpha);
-    return cached_plan(P, S, Hs, Ws, al, o, S, need_gs);
+    return cached_plan(P, S, Hs, Ws, al, o, S, need_gs, periodic);
 }
 
 static size_t fuse_workspace_plain(int S, int H, int W, const gdf_solve_opts *opts)
@@ -1514,7 +1649,8 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
     const bool mixed = o.prec == GDF_PREC_MIXED;
     std::shared_ptr<const Plan> PP;
-    if ((r = fuse_plan(PP, S, H, W, alpha, o, mixed && !g_smooth))) return r;
+    const bool periodic = bc == GDF_BC_PERIODIC;
+    if ((r = fuse_plan(PP, S, H, W, alpha, o, mixed && !g_smooth, periodic))) return r;
     const Plan &P = *PP;
     if (ws_bytes < P.total)
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
@@ -1552,7 +1688,7 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     a.b_pitch = P.g[0].pitch[0];
     // FP32 hierarchy: the smoothing pass also restricts b_u to level 1, so the
     // solve's first pass has nothing left to do
-    if (!P.fp64 && !mixed && P.g[0].nlev >= 2 && P.csz == 2) {
+    if (!P.fp64 && !mixed && !periodic && P.g[0].nlev >= 2 && P.csz == 2) {
         a.bc0 = ws + P.off_arena + P.g[0].off_b[1];
         a.bc_slice_stride = S > 1 ? (long long)((P.g[1].off_b[1] - P.g[0].off_b[1]) / P.csz) : 0;
         a.bc_pitch = P.g[0].pitch[1];
@@ -1568,7 +1704,15 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
         HIP_TRY(launch_smooth(P.fp64, a, s));
     }
     R.raw_rhs_l1 = a.bc0 != nullptr;
-    HIP_TRY(launch_finish_rhs(P.n, R.r_smooth, R.partd, R.partd2, R.partd3, R.st, s));
+    if (periodic) {
+        // the norms of Eq. (1)'s right-hand side with the periodic Laplacian,
+        // from the b_u the smoothing wrote and the stack
+        HIP_TRY(launch_pprep(P.fp64, P.fp64 ? GDF_F64 : GDF_F32, nullptr, GDF_U8, stack, R.io, R.plaunch(0), R.partd,
+                             R.partd2, R.partd3, s));
+        HIP_TRY(launch_finish_rhs(P.n, R.r_p0, R.partd, R.partd2, R.partd3, R.st, s));
+    } else {
+        HIP_TRY(launch_finish_rhs(P.n, R.r_smooth, R.partd, R.partd2, R.partd3, R.st, s));
+    }
 
     SolveIO x;
     x.gs_dtype = P.fp64 ? GDF_F64 : GDF_F32;
@@ -1865,7 +2009,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
     if (!gs || !go || !f) return set_err(GDF_EINVAL, "gs, go and f must be non-null");
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
     std::shared_ptr<const Plan> PP;
-    if ((r = cached_plan(PP, n, H, W, al, o, 0, false))) return r;
+    if ((r = cached_plan(PP, n, H, W, al, o, 0, false, bc == GDF_BC_PERIODIC))) return r;
     const Plan &P = *PP;
     if (ws_bytes < P.total)
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
@@ -1882,10 +2026,14 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
     auto body = [&]() -> gdf_status {
         {
             ProfScope ps(PC_PREP, 0.0, s, R.capturing);
-            HIP_TRY(launch_prep(P.fp64, gs_dtype, gs, go_dtype, go, R.io, n, P.n_tiles, R.desc, R.partd,
-                                R.partd2, R.partd3, s));
+            if (P.periodic)
+                HIP_TRY(launch_pprep(P.fp64, gs_dtype, gs, go_dtype, go, R.io, R.plaunch(0), R.partd, R.partd2,
+                                     R.partd3, s));
+            else
+                HIP_TRY(launch_prep(P.fp64, gs_dtype, gs, go_dtype, go, R.io, n, P.n_tiles, R.desc, R.partd,
+                                    R.partd2, R.partd3, s));
         }
-        HIP_TRY(launch_finish_rhs(n, R.r_tiles, R.partd, R.partd2, R.partd3, R.st, s));
+        HIP_TRY(launch_finish_rhs(n, P.periodic ? R.r_p0 : R.r_tiles, R.partd, R.partd2, R.partd3, R.st, s));
         return solve_body(R, x);
     };
 
@@ -2010,7 +2158,7 @@ static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, cons
     if (!grad_f || !f || !gs) return set_err(GDF_EINVAL, "grad_f, f and gs must be non-null");
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
     std::shared_ptr<const Plan> PP;
-    if ((r = cached_plan(PP, n, H, W, al, o, 0, false))) return r;
+    if ((r = cached_plan(PP, n, H, W, al, o, 0, false, bc == GDF_BC_PERIODIC))) return r;
     const Plan &P = *PP;
     if (ws_bytes < P.total)
         return set_err(GDF_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, P.total);
@@ -2032,10 +2180,17 @@ static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, cons
     }
     {
         ProfScope ps(PC_ADJOINT, 0.0, s, false);
-        HIP_TRY(launch_adjoint_assemble(P.fp64, gs, f, grad_gs, grad_go, R.io, n, P.n_tiles, R.desc, R.st,
-                                        P.mixed ? R.u64tab : nullptr, R.partd, s));
+        if (P.periodic) {
+            PLaunch a = R.plaunch(0);
+            a.in_sel = 0;
+            HIP_TRY(launch_padjoint(P.fp64, gs, f, grad_gs, grad_go, R.io, n, a, R.st, P.mixed ? R.u64tab : nullptr,
+                                    R.partd, s));
+        } else {
+            HIP_TRY(launch_adjoint_assemble(P.fp64, gs, f, grad_gs, grad_go, R.io, n, P.n_tiles, R.desc, R.st,
+                                            P.mixed ? R.u64tab : nullptr, R.partd, s));
+        }
     }
-    if ((r = R.finish(R.r_tiles, nullptr, R.partd, FIN_SUM, 0))) return r;
+    if ((r = R.finish(P.periodic ? R.r_p0 : R.r_tiles, nullptr, R.partd, FIN_SUM, 0))) return r;
     std::vector<SliceState> h(n);
     HIP_TRY(hipMemcpyAsync(h.data(), R.st, sizeof(SliceState) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -208,9 +208,11 @@ enum FinishMode {
 // FIN_CHECK with stall_ratio > 0: from the second counted cycle on, a slice
 // whose residual shrank by less than that factor in one cycle (while still
 // above tol) stops with state.stalled = 1 (the working precision's floor).
+// partials_d2 (with partials_d, FIN_CHECK): FP64 partial sums of r, giving
+// the constant-mode correction as the strip partials do.
 hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_f,
-                         const double *partials_d, int mode, double tol, int max_cycles,
-                         int count_cycle, double stall_ratio, SliceState *state, int *active,
+                         const double *partials_d, const double *partials_d2, int mode, double tol,
+                         int max_cycles, int count_cycle, double stall_ratio, SliceState *state, int *active,
                          hipStream_t s);
 
 // FIN_BB, FIN_INIT and FIN_MEAN of one right-hand side in one launch.
@@ -303,6 +305,68 @@ hipError_t launch_finalize64(int go_dtype, const void *go, int out_dtype, void *
                              const SliceIO *io_dev, int n_slices, long long n_tiles,
                              double *const *u64, const SliceState *state, const LevelDesc *levs,
                              hipStream_t s);
+
+// ---- periodic boundaries ---------------------------------------------------
+//
+// Slices with wrap-around (periodic) boundaries run a plain multigrid of their
+// own (periodic_kernels.hip): the same levels and finite-volume operators as
+// the Neumann hierarchy, with the neighbours of the first and last row and
+// column taken across the wrap, one launch per half-sweep (red-black, from one
+// buffer into the other, so cells of one colour that meet across the wrap of
+// an odd side read each other's previous values), a residual and restriction
+// pass, and a prolongation pass.  Every level is stored in the arithmetic
+// type.  Work is split into tiles of kPTileW x kPTileH cells of one level of
+// one slice (items); a list holds one level's items of every slice, slice by
+// slice, so per-slice partial sums occupy contiguous slots.
+constexpr int kPTileW = 64, kPTileH = 16;
+struct PItem {
+    int lev;     // LevelDesc index
+    int slice;   // slice index (SliceIO, flags)
+    int x0, y0;  // tile origin at that level
+};
+struct PLaunch {
+    const LevelDesc *levs;
+    const PItem *items;
+    int n_items;
+    const int *active;
+    int in_sel, out_sel;   // u buffers read and written (smoothing); the buffer used (others)
+    int colour;            // smoothing: cells with (x + y) % 2 == colour are updated
+    int zero_in;           // smoothing: the input iterate is zero (not read)
+    int coarse_sel;        // prolongation: the coarse level's buffer
+    double *part_rr, *part_r;   // level-0 residual: per-item sums of r^2 and r
+};
+// Buffer element types (gdf_dtype values of the public header).
+enum { GDF_DT_U8 = 0, GDF_DT_F32 = 1, GDF_DT_F64 = 2 };
+// One red-black half-sweep of a level (items of that level); level0: the
+// items are on level 0 (stored in the arithmetic type, coarse levels of an
+// FP32 hierarchy in bfloat16).
+hipError_t launch_psmooth_level(bool fp64, bool level0, const PLaunch &a, hipStream_t s);
+// residual of a level restricted into the next level's right-hand side
+// (items of the coarser level: each coarse cell sums its children's
+// residuals); from_level0: the finer level is level 0
+hipError_t launch_prestrict_level(bool fp64, bool from_level0, const PLaunch &a, hipStream_t s);
+// level-0 residual norms (r^2 and r per item; items of level 0)
+hipError_t launch_pnorm(bool fp64, const PLaunch &a, hipStream_t s);
+// u (buffer in_sel) += bilinear prolongation of the next level's iterate
+// (buffer coarse_sel); items of the finer level; into_level0: that is level 0
+hipError_t launch_pprolong_level(bool fp64, bool into_level0, const PLaunch &a, hipStream_t s);
+// b_u = alpha (g_s - g_o) into level-0 b, partials of ||alpha g_s + L g_o||^2,
+// ||b_u||^2, sum(b_u), with the periodic L; items of level 0
+hipError_t launch_pprep(bool fp64, int gs_dtype, const void *gs, int go_dtype, const void *go, const SliceIO *io,
+                        const PLaunch &a, double *part_bb, double *part_b0, double *part_bs, hipStream_t s);
+// f = g_o + u (+ uoff + shift) from the level-0 buffer a.in_sel, FP64 partials
+// of the residual ||b_u - A u||^2; slices with only[s] == 0 skipped (only non-null)
+hipError_t launch_pfinalize(bool fp64, int go_dtype, const void *go, int out_dtype, void *f, const SliceIO *io,
+                            const PLaunch &a, const SliceState *st, const int *only, hipStream_t s);
+// mixed refinement step with the periodic operator (as launch_refine; the
+// FP32 correction is in level-0 buffer e_sel)
+hipError_t launch_prefine(const RefineArgs &r, const PLaunch &a, hipStream_t s);
+// adjoint assembly with the periodic L (as launch_adjoint_assemble; lambda in
+// level-0 buffer a.in_sel, or the FP64 iterate u64[(cycles & 1) * n + s] when
+// u64 is non-null)
+hipError_t launch_padjoint(bool fp64, const void *gs, const void *f, void *grad_gs, void *grad_go,
+                           const SliceIO *io, int n_slices, const PLaunch &a, const SliceState *st,
+                           double *const *u64, double *part_da, hipStream_t s);
 
 // ---- smoothing ------------------------------------------------------------
 

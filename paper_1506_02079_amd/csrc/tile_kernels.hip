@@ -125,8 +125,8 @@ __device__ __forceinline__ bool quad_ctx(const SliceIO *io, int n, long long n_t
 // One block per slice; fixed-order strided sum then a fixed tree, so the
 // result does not depend on scheduling.
 __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *range,
-                                                     const float2 *pf, const double *pd, int mode,
-                                                     double tol, int max_cycles, int count_cycle,
+                                                     const float2 *pf, const double *pd, const double *pd2,
+                                                     int mode, double tol, int max_cycles, int count_cycle,
                                                      double stall_ratio, SliceState *st, int *active)
 {
     __shared__ double red[4];
@@ -140,10 +140,12 @@ __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *ra
             w += (double)pf[i].y;
         } else {
             v += pd[i];
+            if (pd2) w += pd2[i];
         }
     }
+    const bool has_r = pf || pd2;   // (uniform)
     const double sum = block_sum(v, red);
-    const double rsum = pf ? block_sum(w, red) : 0.0;
+    const double rsum = has_r ? block_sum(w, red) : 0.0;
     if (threadIdx.x != 0) return;
     SliceState &S = st[sidx];
     switch (mode) {
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(256) void finish_kernel(int n_slices, const int *ra
         }
         // Neumann: 1^T A = alpha 1^T, so the constant-mode error of the iterate is
         // exactly -mean(r) / alpha; adding it back removes mean(r) from the residual
-        S.shift = pf ? rsum / (S.npx * S.alpha) : 0.0;
+        S.shift = has_r ? rsum / (S.npx * S.alpha) : 0.0;
         if (!isfinite(sum)) S.status = 6;
         if (!isfinite(sum) || S.rel <= tol || S.cycles >= max_cycles) active[sidx] = 0;
         break;
@@ -213,13 +215,13 @@ hipError_t launch_finish_rhs(int n_slices, const int *range, const double *pbb, 
 }
 
 hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_f,
-                         const double *partials_d, int mode, double tol, int max_cycles,
-                         int count_cycle, double stall_ratio, SliceState *state, int *active,
+                         const double *partials_d, const double *partials_d2, int mode, double tol,
+                         int max_cycles, int count_cycle, double stall_ratio, SliceState *state, int *active,
                          hipStream_t s)
 {
     if (n_slices <= 0) return hipSuccess;
     hipLaunchKernelGGL(finish_kernel, dim3(n_slices), dim3(256), 0, s, n_slices, range, partials_f,
-                       partials_d, mode, tol, max_cycles, count_cycle, stall_ratio, state, active);
+                       partials_d, partials_d2, mode, tol, max_cycles, count_cycle, stall_ratio, state, active);
     return hipGetLastError();
 }
 

@@ -55,7 +55,7 @@ def _robust(v, **kw):
     (dict(alpha=float("inf")), gdf.GDF_EINVAL),
     (dict(tol=0.0), gdf.GDF_EINVAL),
     (dict(tol=1.5), gdf.GDF_EINVAL),
-    (dict(bc=1), gdf.GDF_EUNSUPPORTED),
+    (dict(bc=1, wsb=16), gdf.GDF_ENOMEM),   # periodic: valid, fails on the workspace
     (dict(bc=2), gdf.GDF_EUNSUPPORTED),
     (dict(bc=7), gdf.GDF_EINVAL),
     (dict(sxy=-1.0), gdf.GDF_EINVAL),
@@ -112,7 +112,9 @@ def test_solve_slices_rejects_on_host():
                                       1 << 23, 16, None, None)
     assert call(gsd=0) == gdf.GDF_EINVAL
     assert call(god=5) == gdf.GDF_EINVAL
-    assert call(bc=1) == gdf.GDF_EUNSUPPORTED
+    assert call(bc=1) == gdf.GDF_ENOMEM   # periodic boundaries are valid
+    assert call(bc=2) == gdf.GDF_EUNSUPPORTED
+    assert call(bc=3) == gdf.GDF_EINVAL
     assert call() == gdf.GDF_ENOMEM
     d[0].pitch_f = 4
     assert call() == gdf.GDF_EINVAL
