@@ -206,14 +206,17 @@ gdf_status solve_slices(int n, const gdf_slice_desc *desc_host, int gs_dtype, co
  * refinement: grad_f is usually rough (e.g. a data-misfit gradient) and lambda
  * then has large smooth components that an FP32 iterate cannot resolve to tol.  grad_f, f, grad_gs and grad_go use (off_f, pitch_f) of each
  * descriptor; g_s uses (off_gs, pitch_gs).  grad_gs_dev, grad_go_dev and
- * grad_alpha_host may each be NULL.                                          */
+ * grad_alpha_host may each be NULL.
+ * grad_alpha_sum_dev (device, one double, nullable): the sum over the slices
+ * of dLoss/dalpha_j, formed on the device in slice order -- the gradient of a
+ * scalar alpha shared by every slice.                                        */
 size_t gdf_backward_workspace_size(int n, const gdf_slice_desc *desc_host,
                                    const gdf_solve_opts *opts);
 
 gdf_status solve_slices_backward(int n, const gdf_slice_desc *desc_host, int dtype,
                                  const void *grad_f_dev, const void *f_dev, const void *gs_dev,
                                  int bc, double tol, void *grad_gs_dev, void *grad_go_dev,
-                                 double *grad_alpha_host, const gdf_solve_opts *opts,
+                                 double *grad_alpha_host, double *grad_alpha_sum_dev, const gdf_solve_opts *opts,
                                  void *workspace_dev, size_t workspace_bytes,
                                  gdf_slice_report *report_host, void *stream);
 
@@ -244,10 +247,14 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
  * applies the transpose: out(q) = sum_p K(q - p) grad(p) / D(p), the gradient
  * of a loss with respect to the stack given grad = dLoss/dI1.  Together with
  * solve_slices_backward (dLoss/dg_s, dLoss/dg_o) it differentiates
- * fuse_stack: dLoss/dstack = smooth_transpose(dLoss/dg_s) + dLoss/dg_o.
+ * fuse_stack: dLoss/dstack = smooth_transpose(dLoss/dg_s) + dLoss/dg_o (add_dev
+ * = dLoss/dg_o, or out_dev holding it with add_dev = out_dev).
  *
  * grad_dev, out_dev  [S][H][W] FP32 device buffers, contiguous; out_dev must
- *                    not alias grad_dev.  With W a multiple of 4 and 16-byte
+ *                    not alias grad_dev.
+ * add_dev            NULL, or [S][H][W] FP32 added to the result:
+ *                    out = K (grad / D) + add.  It may be out_dev itself
+ *                    (accumulate in place), not grad_dev.  With W a multiple of 4 and 16-byte
  *                    aligned buffers and workspace the passes move four
  *                    voxels per thread; any other shape or alignment is
  *                    accepted and takes one-voxel passes (equal up to FP32
@@ -262,7 +269,7 @@ int gdf_autotune_last(gdf_solve_opts *opts_host);
  * computed on the device, in the workspace.                                  */
 size_t gdf_smooth_transpose_workspace_size(int S, int H, int W);
 gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
-                            float *out_dev, void *workspace, size_t ws_bytes, void *stream);
+                            float *out_dev, const float *add_dev, void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* solve_slices_noalloc: solve_slices for callers that cannot allocate device

@@ -76,12 +76,12 @@ SIGNATURES = {
                       ctypes.POINTER(SolveOpts), _P, _S, ctypes.POINTER(SliceReport), _P], _I),
     "gdf_backward_workspace_size": ([_I, ctypes.POINTER(SliceDesc), ctypes.POINTER(SolveOpts)], _S),
     "solve_slices_backward": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _P, _P, _I, _D, _P, _P,
-                               ctypes.POINTER(_D), ctypes.POINTER(SolveOpts), _P, _S,
+                               ctypes.POINTER(_D), _P, ctypes.POINTER(SolveOpts), _P, _S,
                                ctypes.POINTER(SliceReport), _P], _I),
     "solve_slices_noalloc": ([_I, ctypes.POINTER(SliceDesc), _I, _P, _I, _P, _I, _D, _P,
                               ctypes.POINTER(SolveOpts), ctypes.POINTER(SliceReport), _P], _I),
     "gdf_smooth_transpose_workspace_size": ([_I, _I, _I], _S),
-    "smooth_transpose": ([_P, _I, _I, _I, _D, _D, _P, _P, _S, _P], _I),
+    "smooth_transpose": ([_P, _I, _I, _I, _D, _D, _P, _P, _P, _S, _P], _I),
 }
 
 
@@ -318,9 +318,13 @@ def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_
 
 def solve_slices_backward(grad_f, f, g_s, alpha, bc="neumann", tol=1e-6, precision=None, nu=0,
                           max_vcycles=0, need=(True, True, True), tile_rows=0, launch_mode=0,
-                          autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False):
-    """Adjoint of Eq. (1): returns (dL/dg_s, dL/dg_o, dL/dalpha per slice, report)
-    for grad_f = dL/df.  Tensors are [S, H, W] of one float dtype."""
+                          autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False,
+                          alpha_sum=False):
+    """Adjoint of Eq. (1): returns (dL/dg_s, dL/dg_o, dL/dalpha, report) for
+    grad_f = dL/df.  Tensors are [S, H, W] of one float dtype.  dL/dalpha is a
+    float64 CPU tensor of the per-slice terms, or with alpha_sum=True a float64
+    device tensor holding their sum (formed by the library on the device: the
+    gradient of one alpha shared by every slice)."""
     torch = _torch()
     _require_cuda(grad_f, f, g_s)
     if not (grad_f.shape == f.shape == g_s.shape) or grad_f.dim() != 3:
@@ -347,21 +351,28 @@ def solve_slices_backward(grad_f, f, g_s, alpha, bc="neumann", tol=1e-6, precisi
     ggs = torch.empty_like(grad_f) if need[0] else None
     ggo = torch.empty_like(grad_f) if need[1] else None
     ga = (ctypes.c_double * S)()
+    gsum = torch.empty((), dtype=torch.float64, device=grad_f.device) if (need[2] and alpha_sum) else None
     rep = (SliceReport * S)()
     st = L.solve_slices_backward(S, d, _dtype_code(grad_f), grad_f.data_ptr(), f.data_ptr(),
                                  g_s.data_ptr(), BC[bc], float(tol),
                                  ggs.data_ptr() if ggs is not None else None,
                                  ggo.data_ptr() if ggo is not None else None,
-                                 ga if need[2] else None, ctypes.byref(o), work.data_ptr(), ws, rep,
-                                 _stream(grad_f.device))
+                                 ga if (need[2] and not alpha_sum) else None,
+                                 gsum.data_ptr() if gsum is not None else None, ctypes.byref(o),
+                                 work.data_ptr(), ws, rep, _stream(grad_f.device))
     _check(st, allow_noconv)
-    galpha = torch.tensor([ga[i] for i in range(S)], dtype=torch.float64) if need[2] else None
+    if gsum is not None:
+        galpha = gsum
+    else:
+        galpha = torch.tensor([ga[i] for i in range(S)], dtype=torch.float64) if need[2] else None
     return ggs, ggo, galpha, _report_list(rep, S)
 
 
-def smooth_transpose(grad, sigma_xy=1.0, sigma_z=3.0):
+def smooth_transpose(grad, sigma_xy=1.0, sigma_z=3.0, add=None):
     """Transpose of the smoothing: dLoss/dstack for grad = dLoss/d(smoothed
-    stack), FP32 [S, H, W] (see smooth_transpose in include/gdf.h)."""
+    stack), FP32 [S, H, W] (see smooth_transpose in include/gdf.h).  add: an
+    FP32 [S, H, W] tensor the library adds to the result in place (it is
+    returned)."""
     torch = _torch()
     _require_cuda(grad)
     if grad.dim() != 3:
@@ -373,9 +384,14 @@ def smooth_transpose(grad, sigma_xy=1.0, sigma_z=3.0):
     if ws == 0:
         raise GdfError(GDF_EINVAL, "S, H, W must be >= 1")
     work = torch.empty(ws, dtype=torch.uint8, device=g.device)
-    out = torch.empty_like(g)
+    if add is not None:
+        if add.dtype != torch.float32 or tuple(add.shape) != (S, H, W) or not add.is_contiguous():
+            raise ValueError("add must be a contiguous float32 [S, H, W] tensor")
+        out = add
+    else:
+        out = torch.empty_like(g)
     st = L.smooth_transpose(g.data_ptr(), S, H, W, float(sigma_xy), float(sigma_z), out.data_ptr(),
-                            work.data_ptr(), ws, _stream(g.device))
+                            out.data_ptr() if add is not None else None, work.data_ptr(), ws, _stream(g.device))
     _check(st)
     return out
 
@@ -388,9 +404,10 @@ def fuse_stack_backward(grad_f, f, stack, alpha, sigma_xy=1.0, sigma_z=3.0, tol=
     torch = _torch()
     g32 = grad_f.to(torch.float32).contiguous()
     f32 = f.to(torch.float32).contiguous()
-    # (g_s only enters dLoss/dalpha, which is not asked for)
+    # (g_s only enters dLoss/dalpha, which is not asked for); the library adds
+    # the transposed smoothing of dLoss/dg_s into dLoss/dg_o in place
     ggs, ggo, _, rep = solve_slices_backward(g32, f32, f32, alpha, tol=tol, need=(True, True, False), **kw)
-    return smooth_transpose(ggs, sigma_xy, sigma_z) + ggo, rep
+    return smooth_transpose(ggs, sigma_xy, sigma_z, add=ggo), rep
 
 
 def fuse_color(color, grey, alpha, tol=1e-6, **kw):
@@ -498,13 +515,14 @@ def _make_autograd():
         def backward(ctx, grad_f):
             g_s, f, alpha = ctx.saved_tensors
             need = ctx.needs_input_grad
+            # a scalar alpha's gradient is the library's device sum over the slices
             ggs, ggo, ga, _ = solve_slices_backward(grad_f.contiguous().to(f.dtype), f, g_s.detach(),
                                                     ctx.al, tol=ctx.tol,
-                                                    need=(need[0], need[1], need[2]))
+                                                    need=(need[0], need[1], need[2]),
+                                                    alpha_sum=alpha.dim() == 0)
             galpha = None
             if need[2]:
-                galpha = ga.sum() if alpha.dim() == 0 else ga
-                galpha = galpha.to(dtype=alpha.dtype, device=alpha.device)
+                galpha = ga.to(dtype=alpha.dtype, device=alpha.device)
             return ggs, ggo, galpha, None
 
     return ScreenedPoissonSolve

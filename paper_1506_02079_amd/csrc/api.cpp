@@ -1032,13 +1032,53 @@ struct Run {
     }
 };
 
+// Page-locked staging of the tables image, per thread: two buffers used in
+// turn, each with an event recorded after its upload, so an upload never
+// waits for the device unless the buffer's previous upload is still in
+// flight.  (Without page-locked memory -- solve_slices_noalloc -- the image is
+// copied from pageable memory and the stream synchronised, so the image can
+// be released.)
+struct TableStaging {
+    int dev = -1;
+    char *buf[2] = {nullptr, nullptr};
+    size_t cap[2] = {0, 0};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    int next = 0;
+};
+thread_local TableStaging t_stage;
+
 gdf_status upload_tables(const Plan &P, char *ws, const std::vector<SliceIO> &io, hipStream_t s)
 {
     std::vector<char> img = bind_tables(P, ws, io);
-    HIP_TRY(hipMemcpyAsync(ws + P.off_tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
-    // pageable source: the copy is staged before the call returns; synchronise
-    // so the host image can be released safely
-    HIP_TRY(hipStreamSynchronize(s));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    TableStaging &T = t_stage;
+    if (t_no_pinned || (T.dev >= 0 && T.dev != dev)) {
+        HIP_TRY(hipMemcpyAsync(ws + P.off_tables, img.data(), img.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return GDF_OK;
+    }
+    T.dev = dev;
+    const int i = T.next;
+    if (T.pending[i]) {
+        HIP_TRY(hipEventSynchronize(T.ev[i]));
+        T.pending[i] = false;
+    }
+    if (!T.ev[i]) HIP_TRY(hipEventCreateWithFlags(&T.ev[i], hipEventDisableTiming));
+    if (T.cap[i] < img.size()) {
+        if (T.buf[i]) HIP_TRY(hipHostFree(T.buf[i]));
+        T.buf[i] = nullptr;
+        T.cap[i] = 0;
+        const size_t want = std::max<size_t>(img.size(), 1 << 16);
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&T.buf[i]), want, hipHostMallocDefault));
+        T.cap[i] = want;
+    }
+    std::memcpy(T.buf[i], img.data(), img.size());
+    HIP_TRY(hipMemcpyAsync(ws + P.off_tables, T.buf[i], img.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(T.ev[i], s));
+    T.pending[i] = true;
+    T.next = i ^ 1;
     return GDF_OK;
 }
 
@@ -1525,15 +1565,15 @@ static size_t transpose_tmp_bytes(int S, int H, int W)
 size_t gdf_smooth_transpose_workspace_size(int S, int H, int W)
 {
     if (S < 1 || H < 1 || W < 1) return 0;
-    return transpose_tmp_bytes(S, H, W) + sizeof(float) * ((size_t)S + H + W);
+    return 2 * transpose_tmp_bytes(S, H, W) + sizeof(float) * ((size_t)S + H + W);
 }
 
 gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double sigma_xy, double sigma_z,
-                            float *out_dev, void *workspace, size_t ws_bytes, void *stream)
+                            float *out_dev, const float *add_dev, void *workspace, size_t ws_bytes, void *stream)
 {
     if (S < 1 || H < 1 || W < 1) return set_err(GDF_EINVAL, "S, H, W must be >= 1 (got %d, %d, %d)", S, H, W);
     if (!grad_dev || !out_dev || !workspace) return set_err(GDF_EINVAL, "grad, out and workspace must be non-null");
-    if (grad_dev == out_dev) return set_err(GDF_EINVAL, "out must not alias grad");
+    if (grad_dev == out_dev || grad_dev == add_dev) return set_err(GDF_EINVAL, "out and add must not alias grad");
     if (!(sigma_xy >= 0.0) || !(sigma_z >= 0.0) || !std::isfinite(sigma_xy) || !std::isfinite(sigma_z))
         return set_err(GDF_EINVAL, "sigma_xy and sigma_z must be finite and >= 0");
     const int rxy = sigma_xy > 0 ? (int)std::floor(3.0 * sigma_xy) : 0;
@@ -1551,10 +1591,11 @@ gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double s
     for (int d = 0; d < 16; ++d) wzf[d] = (float)wz[d];
     char *ws = static_cast<char *>(workspace);
     float *tmp = reinterpret_cast<float *>(ws);
-    float *inv_d = reinterpret_cast<float *>(ws + transpose_tmp_bytes(S, H, W));
+    float *tmp2 = reinterpret_cast<float *>(ws + transpose_tmp_bytes(S, H, W));
+    float *inv_d = reinterpret_cast<float *>(ws + 2 * transpose_tmp_bytes(S, H, W));
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(launch_transpose_tables(inv_d, S, H, W, rxy, rz, wxy, wz, s));
-    HIP_TRY(launch_smooth_transpose(grad_dev, out_dev, tmp, inv_d, S, H, W, rxy, rz, wxyf, wzf, s));
+    HIP_TRY(launch_smooth_transpose(grad_dev, out_dev, add_dev, tmp, tmp2, inv_d, S, H, W, rxy, rz, wxyf, wzf, s));
     return GDF_OK;
 }
 
@@ -2102,20 +2143,20 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
 
 static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
                                  const void *f, const void *gs, int bc, double tol, void *grad_gs,
-                                 void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
+                                 void *grad_go, double *grad_alpha, double *grad_alpha_sum, const gdf_solve_opts *opts,
                                  void *workspace, size_t ws_bytes, gdf_slice_report *report,
                                  void *stream);
 
 gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
                                  const void *f, const void *gs, int bc, double tol, void *grad_gs,
-                                 void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
-                                 void *workspace, size_t ws_bytes, gdf_slice_report *report,
-                                 void *stream)
+                                 void *grad_go, double *grad_alpha, double *grad_alpha_sum,
+                                 const gdf_solve_opts *opts, void *workspace, size_t ws_bytes,
+                                 gdf_slice_report *report, void *stream)
 {
     const gdf_solve_opts b = opts_or_zero(opts);
     if (b.autotune != 1)
-        return backward_plain(n, d, dtype, grad_f, f, gs, bc, tol, grad_gs, grad_go, grad_alpha, opts, workspace,
-                              ws_bytes, report, stream);
+        return backward_plain(n, d, dtype, grad_f, f, gs, bc, tol, grad_gs, grad_go, grad_alpha, grad_alpha_sum, opts,
+                              workspace, ws_bytes, report, stream);
     Opts o;
     std::vector<int> H, W;
     std::vector<double> al;
@@ -2132,14 +2173,14 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
         key_push(key, d[i].alpha);
     }
     return autotuned(key, b, [&](const gdf_solve_opts *c) {
-        return backward_plain(n, d, dtype, grad_f, f, gs, bc, tol, grad_gs, grad_go, grad_alpha, c, workspace,
-                              ws_bytes, report, stream);
+        return backward_plain(n, d, dtype, grad_f, f, gs, bc, tol, grad_gs, grad_go, grad_alpha, grad_alpha_sum, c,
+                              workspace, ws_bytes, report, stream);
     });
 }
 
 static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, const void *grad_f,
                                  const void *f, const void *gs, int bc, double tol, void *grad_gs,
-                                 void *grad_go, double *grad_alpha, const gdf_solve_opts *opts,
+                                 void *grad_go, double *grad_alpha, double *grad_alpha_sum, const gdf_solve_opts *opts,
                                  void *workspace, size_t ws_bytes, gdf_slice_report *report,
                                  void *stream)
 {
@@ -2191,6 +2232,7 @@ static gdf_status backward_plain(int n, const gdf_slice_desc *d, int dtype, cons
         }
     }
     if ((r = R.finish(P.periodic ? R.r_p0 : R.r_tiles, nullptr, R.partd, FIN_SUM, 0))) return r;
+    if (grad_alpha_sum) HIP_TRY(launch_sum_aux(n, R.st, grad_alpha_sum, s));
     std::vector<SliceState> h(n);
     HIP_TRY(hipMemcpyAsync(h.data(), R.st, sizeof(SliceState) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -421,7 +421,12 @@ hipError_t launch_smooth(bool fp64, const SmoothArgs &a, hipStream_t s);
 // the in-plane (radius rxy <= 7) and cross-slice (rz <= 15) taps in FP64.
 hipError_t launch_transpose_tables(float *inv_d, int S, int H, int W, int rxy, int rz, const double *wxy,
                                    const double *wz, hipStream_t s);
-hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const float *inv_d, int S, int H, int W,
-                                   int rxy, int rz, const float *wxy, const float *wz, hipStream_t s);
+// add (nullable, may be out itself): out = K (g / D) + add.  tmp2: a second
+// S H W buffer for the one-voxel passes.
+hipError_t launch_smooth_transpose(const float *g, float *out, const float *add, float *tmp, float *tmp2,
+                                   const float *inv_d, int S, int H, int W, int rxy, int rz, const float *wxy,
+                                   const float *wz, hipStream_t s);
+// dst[0] = sum of state[i].aux over the slices, in slice order (one thread)
+hipError_t launch_sum_aux(int n_slices, const SliceState *state, double *dst, hipStream_t s);
 
 }  // namespace gdf

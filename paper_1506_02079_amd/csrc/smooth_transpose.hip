@@ -51,6 +51,8 @@ __device__ inline float vzero(float) { return 0.f; }
 __device__ inline vec4f vzero(vec4f) { return vec4f{0.f, 0.f, 0.f, 0.f}; }
 __device__ inline float vmul(float w, float a) { return w * a; }
 __device__ inline vec4f vmul(float w, vec4f a) { return vec4f{w * a.x, w * a.y, w * a.z, w * a.w}; }
+__device__ inline float vadd(float a, float b) { return a + b; }
+__device__ inline vec4f vadd(vec4f a, vec4f b) { return vec4f{a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w}; }
 __device__ inline float vfma(float w, float a, float b, float c) { return fmaf(w, a + b, c); }
 __device__ inline vec4f vfma(float w, vec4f a, vec4f b, vec4f c)
 {
@@ -66,8 +68,11 @@ struct Taps {
     float w[16];
 };
 
+// add (may alias out, or be null): out = (z pass) + add, element by element,
+// each element read before the same thread writes it
 template <int R, typename V>
-__global__ __launch_bounds__(256) void transpose_z_ring(const V *in, V *out, int S, long long plane, Taps t)
+__global__ __launch_bounds__(256) void transpose_z_ring(const V *in, V *out, const V *add, int S, long long plane,
+                                                        Taps t)
 {
     // plane: elements of V per slice
     constexpr int N = 2 * R + 1;
@@ -90,6 +95,7 @@ __global__ __launch_bounds__(256) void transpose_z_ring(const V *in, V *out, int
                 V acc = vmul(t.w[0], ring[(k + R) % N]);
 #pragma unroll
                 for (int d = 1; d <= R; ++d) acc = vfma(t.w[d], ring[(k + R - d) % N], ring[(k + R + d) % N], acc);
+                if (add) acc = vadd(acc, add[(long long)z * plane + col]);
                 out[(long long)z * plane + col] = acc;
             }
         }
@@ -252,21 +258,23 @@ hipError_t launch_y_ring(const float *in, float *out, int S, int H, int W, int r
     return hipGetLastError();
 }
 
-hipError_t launch_z_ring(const float *in, float *out, int S, int H, int W, int rz, const float *wz, hipStream_t s)
+hipError_t launch_z_ring(const float *in, float *out, const float *add, int S, int H, int W, int rz,
+                         const float *wz, hipStream_t s)
 {
     Taps t{};
     for (int d = 0; d < 16; ++d) t.w[d] = wz[d];
     const long long plane = (long long)H * W;
-    const bool vec = aligned16(in, out) && plane % 4 == 0;
+    const bool vec = aligned16(in, out) && (!add || aligned16(add, add)) && plane % 4 == 0;
     const long long pv = vec ? plane / 4 : plane;
     const dim3 grid((unsigned)((pv + 255) / 256));
     const vec4f *in4 = reinterpret_cast<const vec4f *>(in);
     vec4f *out4 = reinterpret_cast<vec4f *>(out);
+    const vec4f *add4 = reinterpret_cast<const vec4f *>(add);
     switch (rz) {
 #define GDF_ZR(R) \
     case R: \
-        if (vec) hipLaunchKernelGGL((transpose_z_ring<R, vec4f>), grid, dim3(256), 0, s, in4, out4, S, pv, t); \
-        else hipLaunchKernelGGL((transpose_z_ring<R, float>), grid, dim3(256), 0, s, in, out, S, plane, t); \
+        if (vec) hipLaunchKernelGGL((transpose_z_ring<R, vec4f>), grid, dim3(256), 0, s, in4, out4, add4, S, pv, t); \
+        else hipLaunchKernelGGL((transpose_z_ring<R, float>), grid, dim3(256), 0, s, in, out, add, S, plane, t); \
         break;
         GDF_ZR(0) GDF_ZR(1) GDF_ZR(2) GDF_ZR(3) GDF_ZR(4) GDF_ZR(5) GDF_ZR(6) GDF_ZR(7) GDF_ZR(8) GDF_ZR(9)
         GDF_ZR(10) GDF_ZR(11) GDF_ZR(12)
@@ -318,8 +326,9 @@ hipError_t launch_transpose_tables(float *inv_d, int S, int H, int W, int rxy, i
     return hipGetLastError();
 }
 
-hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const float *inv_d, int S, int H, int W,
-                                   int rxy, int rz, const float *wxy, const float *wz, hipStream_t s)
+hipError_t launch_smooth_transpose(const float *g, float *out, const float *add, float *tmp, float *tmp2,
+                                   const float *inv_d, int S, int H, int W, int rxy, int rz, const float *wxy,
+                                   const float *wz, hipStream_t s)
 {
     const long long n = (long long)S * H * W;
     if (n == 0) return hipSuccess;
@@ -348,18 +357,19 @@ hipError_t launch_smooth_transpose(const float *g, float *out, float *tmp, const
         }
         const hipError_t exy = hipGetLastError();
         if (exy != hipSuccess) return exy;
-        return launch_z_ring(tmp, out, S, H, W, rz, wz, s);
+        return launch_z_ring(tmp, out, add, S, H, W, rz, wz, s);
     }
-    // one-voxel x pass: g -> out; y: out -> tmp; z: tmp -> out
+    // one-voxel x pass: g -> tmp2; y: tmp2 -> tmp; z: tmp -> out
+    a.out = tmp2;
     {
         const dim3 grid((unsigned)((W + 255) / 256), (unsigned)std::min(H, 65535), (unsigned)std::min(S, 65535));
         hipLaunchKernelGGL(transpose_x_kernel, grid, dim3(256), 0, s, a);
     }
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
-    const hipError_t e = launch_y_ring(out, tmp, S, H, W, rxy, wxy, s);
+    const hipError_t e = launch_y_ring(tmp2, tmp, S, H, W, rxy, wxy, s);
     if (e != hipSuccess) return e;
-    return launch_z_ring(tmp, out, S, H, W, rz, wz, s);
+    return launch_z_ring(tmp, out, add, S, H, W, rz, wz, s);
 }
 
 }  // namespace gdf

@@ -225,6 +225,20 @@ hipError_t launch_finish(int n_slices, const int *range, const float2 *partials_
     return hipGetLastError();
 }
 
+__global__ __launch_bounds__(64) void sum_aux_kernel(int n_slices, const SliceState *st, double *dst)
+{
+    if (threadIdx.x != 0) return;
+    double v = 0.0;
+    for (int i = 0; i < n_slices; ++i) v += st[i].aux;   // fixed order
+    *dst = v;
+}
+
+hipError_t launch_sum_aux(int n_slices, const SliceState *state, double *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_aux_kernel, dim3(1), dim3(64), 0, s, n_slices, state, dst);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void done_kernel(int n_slices, const int *active, int *done)
 {
     __shared__ int any;

@@ -125,9 +125,9 @@ def test_solve_slices_rejects_on_host():
     # FP64 data needs the FP64 solver; every call here fails validation before
     # any device work (the pointers are placeholders)
     om = gdf.make_opts(precision="mixed")
-    assert L.solve_slices_backward(1, d, 2, 1 << 20, 1 << 21, 1 << 22, 0, 1e-6, None, None, None,
+    assert L.solve_slices_backward(1, d, 2, 1 << 20, 1 << 21, 1 << 22, 0, 1e-6, None, None, None, None,
                                    ctypes.byref(om), 1 << 23, 1 << 30, None, None) == gdf.GDF_EINVAL
-    assert L.solve_slices_backward(1, d, 1, 1 << 20, 1 << 21, 1 << 22, 0, 1e-6, None, None, None,
+    assert L.solve_slices_backward(1, d, 1, 1 << 20, 1 << 21, 1 << 22, 0, 1e-6, None, None, None, None,
                                    ctypes.byref(om), 1 << 23, 16, None, None) == gdf.GDF_ENOMEM
 
 

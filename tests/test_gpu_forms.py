@@ -437,7 +437,7 @@ def test_smooth_transpose_unaligned_buffers():
     ws = L.gdf_smooth_transpose_workspace_size(S, H, W)
     work = torch.empty(ws + 16, dtype=torch.uint8, device=DEV)
     print("unaligned transpose", (S, H, W), flush=True)
-    st = L.smooth_transpose(buf_g.data_ptr() + 4, S, H, W, 1.0, 3.0, buf_o.data_ptr() + 4,
+    st = L.smooth_transpose(buf_g.data_ptr() + 4, S, H, W, 1.0, 3.0, buf_o.data_ptr() + 4, None,
                             work.data_ptr() + 4, ws, gdf._stream(DEV))
     assert st == 0, gdf.last_error()
     torch.cuda.synchronize()
@@ -520,3 +520,35 @@ def test_streamed_stack_matches_whole():
     for j in (0, 15, 16, 31, 32, 36):
         fr = oracle.solve(gs[j], stack[j].astype(np.float64), 0.01, tol=1e-12)
         assert np.abs(f_s[j].numpy() - fr).max() <= 1e-3, j
+
+
+@pytest.mark.parametrize("shape", [(7, 33, 64), (5, 21, 37)])
+def test_smooth_transpose_adds_in_place(shape):
+    """out = K (G / D) + add with add = out (accumulate in place), on the
+    four-column passes (W = 64) and the one-voxel passes (W = 37)."""
+    rng = np.random.default_rng(sum(shape) + 1)
+    g = rng.standard_normal(shape)
+    base = rng.standard_normal(shape)
+    acc = torch.from_numpy(base).to(DEV, torch.float32)
+    out = gdf.smooth_transpose(torch.from_numpy(g).to(DEV, torch.float32), 1.0, 3.0, add=acc)
+    torch.cuda.synchronize()
+    assert out.data_ptr() == acc.data_ptr()
+    ref = oracle.smooth_transpose(g, 1.0, 3.0) + base
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max() + 1e-6
+
+
+def test_backward_alpha_sum_on_device():
+    """The device total of dLoss/dalpha equals the sum of the per-slice terms
+    (and the oracle's)."""
+    gs, go, t = _adj_data(4, 64, 90, 15)
+    alpha = 0.01
+    f = oracle.solve_stack(gs, go, alpha, tol=1e-13)
+    gbar = 2 * (f - t)
+    T = lambda a: torch.from_numpy(a).to(DEV, torch.float64)
+    _, _, per, _ = gdf.solve_slices_backward(T(gbar), T(f), T(gs), alpha, tol=1e-11, need=(False, False, True))
+    _, _, tot, _ = gdf.solve_slices_backward(T(gbar), T(f), T(gs), alpha, tol=1e-11, need=(False, False, True),
+                                             alpha_sum=True)
+    assert tot.is_cuda and tot.dim() == 0
+    ref = sum(oracle.adjoint(gbar[j], gs[j], f[j], alpha, tol=1e-13)[2] for j in range(4))
+    assert abs(float(tot) - float(per.sum())) <= 1e-12 * abs(ref)
+    assert abs(float(tot) - ref) <= 1e-7 * abs(ref)
