@@ -106,11 +106,16 @@ def summarize_pmc(fetch_dir, write_dir, out_json, command):
 
 
 def _timed(torch, fn, steps, warmup):
+    # (the previous call's outputs are dropped before the next call, so that
+    # large forms do not hold two sets of outputs and workspaces at once)
+    out = None
     for _ in range(warmup):
+        out = None
         out = fn()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
+        out = None
         out = fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps, out

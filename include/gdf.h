@@ -111,7 +111,13 @@ typedef struct {
                           weighted standard deviations from the window's weighted mean
                           are left out of the average (one pass).  FP32 and MIXED only
                           (GDF_EUNSUPPORTED with GDF_PREC_FP64); 0 = plain averaging. */
-    int reserved[4];
+    int z_begin, z_end; /* fuse_stack: solve only the slices [z_begin, z_end) of the stack
+                          (0, 0 = all).  The other slices only enter the cross-slice window
+                          of these (Section III-A), so a chunk of a larger stack, given with
+                          floor(3 sigma_z) slices on either side, gives the whole-stack
+                          result for its own slices ("Distributed Processing").  f_dev,
+                          g_smooth_dev and report_host then hold z_end - z_begin slices. */
+    int reserved[2];
 } gdf_solve_opts;
 
 typedef enum {

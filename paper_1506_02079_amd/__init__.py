@@ -41,7 +41,8 @@ class SolveOpts(ctypes.Structure):
                 ("tile_rows", ctypes.c_int), ("inner_cycles", ctypes.c_int),
                 ("launch_mode", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("fine_sweeps", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
-                ("robust", ctypes.c_int), ("reserved", ctypes.c_int * 4)]
+                ("robust", ctypes.c_int), ("z_begin", ctypes.c_int), ("z_end", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class SliceReport(ctypes.Structure):
@@ -184,10 +185,13 @@ def _require_cuda(*ts):
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
                tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
-               allow_noconv=False, robust=False):
+               allow_noconv=False, robust=False, z_range=None):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
     robust=True: robust cross-slice averaging (values more than two weighted
     standard deviations from the window's weighted mean are left out).
+    z_range=(z0, z1): solve only slices z0 .. z1 - 1 (the others only enter
+    their cross-slice windows); f, g_smooth and the report then hold z1 - z0
+    slices.
 
     Returns (f, report) or (f, report, g_smooth) with return_smooth=True.
     f has dtype float32 (fp32) or float64 (fp64 / mixed) unless out_dtype is given.
@@ -202,25 +206,29 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
     o = make_opts(precision, max_vcycles, nu, out_dtype, False, tile_rows, inner_cycles,
                   launch_mode, autotune, fine_sweeps, coarse_sweeps)
     o.robust = int(bool(robust))
+    n = S
+    if z_range is not None:
+        o.z_begin, o.z_end = int(z_range[0]), int(z_range[1])
+        n = o.z_end - o.z_begin
     L = lib()
     ws = L.gdf_fuse_workspace_size(S, H, W, ctypes.byref(o))
     if ws == 0:
         raise GdfError(GDF_EINVAL, last_error())
     od = o.out_dtype or (DTYPE_F32 if o.precision == 0 else DTYPE_F64)
-    f = torch.empty((S, H, W), dtype=torch.float64 if od == DTYPE_F64 else torch.float32,
+    f = torch.empty((n, H, W), dtype=torch.float64 if od == DTYPE_F64 else torch.float32,
                     device=stack.device)
     gsm = None
     if return_smooth:
-        gsm = torch.empty((S, H, W), dtype=torch.float64 if o.precision == 1 else torch.float32,
+        gsm = torch.empty((n, H, W), dtype=torch.float64 if o.precision == 1 else torch.float32,
                           device=stack.device)
     work = torch.empty(ws, dtype=torch.uint8, device=stack.device)
-    rep = (SliceReport * S)()
+    rep = (SliceReport * n)()
     st = L.fuse_stack(stack.data_ptr(), S, H, W, stack.stride(1), stack.stride(0), float(alpha),
                       BC[bc], float(tol), float(sigma_xy), float(sigma_z), f.data_ptr(),
                       gsm.data_ptr() if gsm is not None else None, ctypes.byref(o),
                       work.data_ptr(), ws, rep, _stream(stack.device))
     _check(st, allow_noconv)
-    out = (f, _report_list(rep, S))
+    out = (f, _report_list(rep, n))
     return out + (gsm,) if return_smooth else out
 
 
@@ -432,8 +440,8 @@ def fuse_stack_streamed(stack, alpha, chunk=32, out=None, sigma_xy=1.0, sigma_z=
     stack: uint8 [S, H, W] CPU tensor (pinned, for overlapped uploads).  Slices
     are processed `chunk` at a time; each chunk is uploaded with the
     floor(3 sigma_z) slices on either side that its smoothing reads, so every
-    slice's result equals the whole-stack one (the solve is per slice; the halo
-    slices are solved too and dropped).  The next chunk's upload runs on a side
+    slice's result equals the whole-stack one (the solve is per slice; the
+    slices on either side only enter the windows: z_range).  The next chunk's upload runs on a side
     stream while the current chunk computes, and each chunk's result goes back
     on a third stream while the next one computes.  Returns (f float32 [S, H, W] in
     pinned host memory, or `out`; the per-slice reports)."""
@@ -477,13 +485,14 @@ def fuse_stack_streamed(stack, alpha, chunk=32, out=None, sigma_xy=1.0, sigma_z=
         z1 = min(z0 + chunk, S)
         lo, hi = max(z0 - rz, 0), min(z0 + chunk + rz, S)
         main.wait_event(ready[b])
-        f, rep = fuse_stack(bufs[b][:hi - lo], alpha, tol=tol, sigma_xy=sigma_xy, sigma_z=sigma_z, **kw)
+        f, rep = fuse_stack(bufs[b][:hi - lo], alpha, tol=tol, sigma_xy=sigma_xy, sigma_z=sigma_z,
+                            z_range=(z0 - lo, z1 - lo), **kw)
         freed[b].record(main)
         down.wait_stream(main)
         with torch.cuda.stream(down):
-            out[z0:z1].copy_(f[z0 - lo:z1 - lo], non_blocking=True)
+            out[z0:z1].copy_(f, non_blocking=True)
         f.record_stream(down)      # the allocator keeps f until the download ends
-        reports += rep[z0 - lo:z1 - lo]
+        reports += rep
     torch.cuda.synchronize(dev)
     return out, reports
 

@@ -1511,6 +1511,18 @@ static gdf_status escalate_slices(const std::vector<int> &todo, const gdf_slice_
                                   gdf_slice_report *report, void *stream);
 
 
+// The slices fuse_stack solves: [z_begin, z_end) of the S (0, 0: all of them).
+static gdf_status out_range(const gdf_solve_opts *opts, int S, int &z0, int &z1)
+{
+    z0 = opts ? opts->z_begin : 0;
+    z1 = opts ? opts->z_end : 0;
+    if (z0 == 0 && z1 == 0) z1 = S;
+    if (z0 < 0 || z1 > S || z0 >= z1)
+        return set_err(GDF_EINVAL, "z_begin, z_end must satisfy 0 <= z_begin < z_end <= S (got %d, %d, S = %d)", z0,
+                       z1, S);
+    return GDF_OK;
+}
+
 static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long long pr, long long ps,
                                 double alpha, int bc, double tol, double sxy, double sz,
                                 const void *f, const gdf_solve_opts *opts, Opts &o)
@@ -1539,11 +1551,14 @@ static gdf_status fuse_plan(std::shared_ptr<const Plan> &P, int S, int H, int W,
     return cached_plan(P, S, Hs, Ws, al, o, S, need_gs, periodic);
 }
 
-static size_t fuse_workspace_plain(int S, int H, int W, const gdf_solve_opts *opts)
+static size_t fuse_workspace_plain(int S_all, int H, int W, const gdf_solve_opts *opts)
 {
     Opts o;
     if (parse_opts(opts, o)) return 0;
-    if (S < 1 || H < 1 || W < 1) return 0;
+    if (S_all < 1 || H < 1 || W < 1) return 0;
+    int z0, z1;
+    if (out_range(opts, S_all, z0, z1)) return 0;
+    const int S = z1 - z0;   // the slices solved
     std::shared_ptr<const Plan> P, Q;
     if (fuse_plan(P, S, H, W, 1.0, o, o.prec == GDF_PREC_MIXED)) return 0;
     // the hierarchy depth depends on alpha; size for the deepest (smallest alpha)
@@ -1606,7 +1621,7 @@ size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
-                  b.launch_mode, b.robust})
+                  b.launch_mode, b.robust, b.z_begin, b.z_end})
         key_push(key, v);
     return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
 }
@@ -1632,7 +1647,7 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps,
-                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust})
+                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust, b.z_begin, b.z_end})
         key_push(key, v);
     for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
     return autotuned(key, b, [&](const gdf_solve_opts *c) {
@@ -1675,19 +1690,30 @@ static SmoothArgs smooth_args(const uint8_t *stack, int S, int H, int W, long lo
         }
     a.tiles_x = (W + kSmoothTileW - 1) / kSmoothTileW;
     a.tiles_y = (H + kSmoothTileH - 1) / kSmoothTileH;
+    a.z_lo = 0;
+    a.z_hi = S;
     return a;
 }
 
-static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, long long pitch_row,
+static gdf_status fuse_stack_plain(const uint8_t *stack_all, int S_all, int H, int W, long long pitch_row,
                                    long long pitch_slice, double alpha, int bc, double tol, double sigma_xy,
                                    double sigma_z, void *f, void *g_smooth, const gdf_solve_opts *opts,
                                    void *workspace, size_t ws_bytes, gdf_slice_report *report, void *stream)
 {
     Opts o;
     gdf_status r;
-    if ((r = fuse_validate(stack, S, H, W, pitch_row, pitch_slice, alpha, bc, tol, sigma_xy, sigma_z, f, opts, o)))
+    if ((r = fuse_validate(stack_all, S_all, H, W, pitch_row, pitch_slice, alpha, bc, tol, sigma_xy, sigma_z, f, opts,
+                           o)))
         return r;
     if (!workspace) return set_err(GDF_EINVAL, "workspace must be non-null");
+    // The slices solved, [z0, z1): S of them at stack (the first).  The
+    // smoothing reads the stack from zv0, the first slice in their windows.
+    int z0, z1;
+    if ((r = out_range(opts, S_all, z0, z1))) return r;
+    const int S = z1 - z0;
+    const int rz = sigma_z > 0 ? (int)std::floor(3.0 * sigma_z) : 0;
+    const int zv0 = std::max(0, z0 - rz), zv1 = std::min(S_all, z1 + rz);
+    const uint8_t *stack = stack_all + (long long)z0 * pitch_slice;
     const bool mixed = o.prec == GDF_PREC_MIXED;
     std::shared_ptr<const Plan> PP;
     const bool periodic = bc == GDF_BC_PERIODIC;
@@ -1714,11 +1740,14 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     R.stall_ratio = o.prec == GDF_PREC_FP32 ? kStallRatio : 0.0;
 
     // smoothing writes the level-0 right-hand side of every slice
-    SmoothArgs a = smooth_args(stack, S, H, W, pitch_row, pitch_slice, sigma_xy, sigma_z, alpha, o.robust);
+    SmoothArgs a = smooth_args(stack_all + (long long)zv0 * pitch_slice, zv1 - zv0, H, W, pitch_row, pitch_slice,
+                               sigma_xy, sigma_z, alpha, o.robust);
+    a.z_lo = z0 - zv0;
+    a.z_hi = z1 - zv0;
     void *gs_used = g_smooth ? g_smooth : (mixed ? (void *)(ws + P.off_gscopy) : nullptr);
     a.gs_out = gs_used;
-    a.gs_zlo = 0;
-    a.gs_zhi = S;
+    a.gs_zlo = a.z_lo;
+    a.gs_zhi = a.z_hi;
     // a uniform stack: every slice has the same arena block, so the level-0
     // right-hand sides are equally spaced
     a.b0 = ws + P.off_arena + P.g[0].off_b[0];
@@ -1740,7 +1769,8 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     a.part_b0 = R.partd2;
     a.part_bs = R.partd3;
     {
-        ProfScope ps(PC_SMOOTH, (double)S * H * W * (1.0 + P.esz + (gs_used ? P.esz : 0) + (a.bc0 ? 0.25 * P.csz : 0.0)),
+        ProfScope ps(PC_SMOOTH,
+                     (double)H * W * ((zv1 - zv0) + S * (P.esz + (gs_used ? P.esz : 0) + (a.bc0 ? 0.25 * P.csz : 0.0))),
                      s, false);
         HIP_TRY(launch_smooth(P.fp64, a, s));
     }
@@ -1794,8 +1824,8 @@ static gdf_status fuse_stack_plain(const uint8_t *stack, int S, int H, int W, lo
     a1.part_bb = a1.part_b0 = a1.part_bs = nullptr;
     a1.gs_out = ws;
     for (int z : escalation_list(S, h, tol, o.max_vc)) {
-        a1.gs_zlo = z;
-        a1.gs_zhi = z + 1;
+        a1.z_lo = a1.gs_zlo = z + z0 - zv0;
+        a1.z_hi = a1.gs_zhi = z + z0 - zv0 + 1;
         HIP_TRY(launch_smooth(false, a1, s));
         if ((r = escalate_slices({z}, d.data(), GDF_F32, ws, GDF_U8, stack, bc, tol, f, o, ws + gs1, ws_bytes - gs1,
                                  status, report, stream)))

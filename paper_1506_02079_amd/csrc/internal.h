@@ -389,6 +389,9 @@ struct SmoothArgs {
     float wxy_f[8];       // the same taps rounded to FP32 (FP32 kernel: kept in scalar registers)
     float wz_f[16];
     float alpha_f;
+    int z_lo, z_hi;       // the output slices: [z_lo, z_hi) of the S (the others only feed
+                          // their cross-slice windows); b_u, the level-1 right-hand side and
+                          // the partial sums of slice z go to index z - z_lo
     void *gs_out;         // optional smoothed slices (contiguous [gs_zhi - gs_zlo][H][W])
     int gs_zlo, gs_zhi;   // output slices [gs_zlo, gs_zhi) are stored into gs_out (slice z at z - gs_zlo)
     void *b0;                 // level-0 right-hand side of slice 0 (b_u is written there);
@@ -399,9 +402,9 @@ struct SmoothArgs {
     // taps below it and hi above it inside the stack: inv_wz[lo][hi], lo, hi <= rz
     double inv_wz[13][13];
     float inv_wz_f[13][13];
-    double *part_bb;      // [S][tiles] partial ||alpha g_s + L g_o||^2
-    double *part_b0;      // [S][tiles] partial ||b_u||^2
-    double *part_bs;      // [S][tiles] partial sum(b_u)
+    double *part_bb;      // [z_hi - z_lo][tiles] partial ||alpha g_s + L g_o||^2
+    double *part_b0;      // [z_hi - z_lo][tiles] partial ||b_u||^2
+    double *part_bs;      // [z_hi - z_lo][tiles] partial sum(b_u)
     int tiles_x, tiles_y;
     // optional (FP32): level-1 right-hand side (bfloat16) of slice 0, written as
     // the sum of each coarse cell's children's b_u (no mean removed); slices are

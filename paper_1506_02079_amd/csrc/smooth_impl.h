@@ -237,18 +237,21 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     constexpr int kPB = 21;
     double pbuf = 0.0;
     const int pq = tid % 3, ps = tid / 3;
+    // (groups count from the first output slice; partial sums are indexed by
+    // output slice, z - z_lo)
     auto partial = [&](int z) {
-        const int zs = z % kPB;   // uniform
+        const int zl = z - a.z_lo;
+        const int zs = zl % kPB;   // uniform
         if (tid < 3 * kPB && ps == zs) {
             double v = 0.0;
 #pragma unroll
             for (int w = 0; w < kSmoothWaves; ++w) v += red_s[z & 1][w][pq];
             pbuf = v;
         }
-        if ((zs == kPB - 1 || z == S - 1) && a.b0) {
+        if ((zs == kPB - 1 || z == a.z_hi - 1) && a.b0) {
             if (tid < 3 * (zs + 1)) {
                 double *dst = pq == 0 ? a.part_bb : (pq == 1 ? a.part_b0 : a.part_bs);
-                dst[(long long)(z - zs + ps) * nparts + tile] = pbuf;
+                dst[(long long)(zl - zs + ps) * nparts + tile] = pbuf;
             }
         }
     };
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     float hx = 0.f;   // odd waves: column sum of their first row (the pair's second row)
     auto cstore = [&](int z, int ty, float v) {   // ty: tile row of the cell's first child (even)
         if (Y0 + ty >= H) return;
-        const Rsrc rc = make_rsrc(static_cast<unsigned short *>(a.bc0) + (long long)z * a.bc_slice_stride +
+        const Rsrc rc = make_rsrc(static_cast<unsigned short *>(a.bc0) + (long long)(z - a.z_lo) * a.bc_slice_stride +
                                       (long long)((Y0 + ty) >> 1) * a.bc_pitch,
                                   (unsigned)a.bc_pitch * 2u);
         Buf<unsigned short>::st(__builtin_bit_cast(unsigned short, (__bf16)v), rc, vcol, 0);   // nearest even
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     // zi into hb[zi & 1]; y blur of slice zi - 1 (x-blurred in the previous
     // step) into register ring slot (zi - 1) mod NZ; z blur and output of slice
     // zo = zi - 1 - RZ; the raw tile of slice zi + 1 enters the LDS ring.
-    // (called only for zi < S + RZ + 1; k = zi mod NZ, a constant once unrolled)
+    // (called only for zi < z_hi + RZ + 1; k = zi mod NZ, a constant once unrolled)
     auto step = [&](const int zi, const int k) __attribute__((always_inline)) {
         const int islot = zi % NRAW;
         issue(zi + 1);       // next raw tile: its latency is hidden by this step
@@ -332,9 +335,10 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
 #pragma unroll
             for (int i = 0; i < kSRows; ++i) ring[ks][i] = T(0);
         }
-        // ------------- output slice zo = zi - 1 - RZ
+        // ------------- output slice zo = zi - 1 - RZ (the first test is static in
+        // the peeled steps)
         const int zo = zi - 1 - RZ;
-        if (zo >= 0) {
+        if (zo >= 0 && zo >= a.z_lo && zo < a.z_hi) {
             const int zlo = min(RZ, zo), zhi = min(RZ, S - 1 - zo);   // in-stack taps
             T iz;
             if constexpr (sizeof(T) == 4) iz = a.inv_wz_f[zlo][zhi];
@@ -343,7 +347,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             // this slice's tile rows of b (and of g_s): windows of kSTY rows
             // (a resource of size zero drops the stores: no b_u without a.b0, and
             // g_s only for the output slices asked for)
-            const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)zo * a.b_slice_stride +
+            const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)(zo - a.z_lo) * a.b_slice_stride +
                                            (long long)Y0 * a.b_pitch,
                                        a.b0 ? (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)) : 0u);
             const bool gsz = a.gs_out && zo >= a.gs_zlo && zo < a.gs_zhi;   // uniform
@@ -417,10 +421,10 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             commit(zi + 1);
 #pragma unroll
             for (int i = 0; i < kSRows; ++i) asm volatile("" ::"v"(hold[i]));
-            if (zo >= 1) partial(zo - 1);
+            if (zo - 1 >= a.z_lo) partial(zo - 1);
             if (rst) {
                 if constexpr (kSRows % 2 == 1)
-                    if ((wv & 1) && zo >= 1) cstore(zo - 1, yb - 1, xs[(zo - 1) & 1][wv >> 1][tx] + hx);
+                    if ((wv & 1) && zo - 1 >= a.z_lo) cstore(zo - 1, yb - 1, xs[(zo - 1) & 1][wv >> 1][tx] + hx);
                 float cs[kSRows];
 #pragma unroll
                 for (int i = 0; i < kSRows; ++i) cs[i] = bms[i] + dpp_row<0xB1>(bms[i]);   // lane pairs
@@ -459,18 +463,20 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     // The first block of NZ steps is peeled: there every slice index is a
     // constant, so the steps before the first output carry no output code.
     // In the others every step has an output slice (zo >= NZ - 1 - RZ = RZ).
+    // (the march ends with the last output slice)
+    const int zend = a.z_hi + RZ + 1;
 #pragma unroll
     for (int k = 0; k < NZ; ++k)
-        if (k < S + RZ + 1) step(k, k);
-    for (int zb = NZ; zb < S + RZ + 1; zb += NZ) {
+        if (k < zend) step(k, k);
+    for (int zb = NZ; zb < zend; zb += NZ) {
         __builtin_assume(zb >= NZ);
 #pragma unroll
         for (int k = 0; k < NZ; ++k)
-            if (zb + k < S + RZ + 1) step(zb + k, k);   // uniform across the block
+            if (zb + k < zend) step(zb + k, k);   // uniform across the block
     }
-    partial(S - 1);   // the last slice's sums are complete after the last barrier
+    partial(a.z_hi - 1);   // the last slice's sums are complete after the last barrier
     if constexpr (kSRows % 2 == 1)
-        if (rst && (wv & 1)) cstore(S - 1, yb - 1, xs[(S - 1) & 1][wv >> 1][tx] + hx);
+        if (rst && (wv & 1)) cstore(a.z_hi - 1, yb - 1, xs[(a.z_hi - 1) & 1][wv >> 1][tx] + hx);
 }
 
 // Launch one (precision, radius) instance; defined per cross-slice radius in

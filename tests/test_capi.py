@@ -44,6 +44,12 @@ def _robust(v, **kw):
     return o
 
 
+def _zr(z0, z1):
+    o = gdf.make_opts()
+    o.z_begin, o.z_end = z0, z1
+    return o
+
+
 @pytest.mark.parametrize("kw,status", [
     (dict(S=0), gdf.GDF_EINVAL),
     (dict(H=-1), gdf.GDF_EINVAL),
@@ -77,6 +83,12 @@ def _robust(v, **kw):
     (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),
     (dict(wsb=16), gdf.GDF_ENOMEM),
+    # the slices to solve: [z_begin, z_end) of the S = 4
+    (dict(opts=_zr(1, 1)), gdf.GDF_EINVAL),
+    (dict(opts=_zr(2, 1)), gdf.GDF_EINVAL),
+    (dict(opts=_zr(-1, 2)), gdf.GDF_EINVAL),
+    (dict(opts=_zr(0, 5)), gdf.GDF_EINVAL),
+    (dict(opts=_zr(1, 3), wsb=16), gdf.GDF_ENOMEM),   # valid, fails on the workspace
     # the autotuner validates first; every candidate then fails the workspace check
     (dict(wsb=16, opts=gdf.make_opts(autotune=True)), gdf.GDF_ENOMEM),
     (dict(alpha=0.0, opts=gdf.make_opts(autotune=True)), gdf.GDF_EINVAL),
@@ -92,6 +104,13 @@ def test_workspace_sizes():
     a = L.gdf_fuse_workspace_size(64, 2048, 2048, ctypes.byref(o))
     assert a > 64 * 2048 * 2048 * 12  # u (2 buffers) + b in FP32, plus coarse levels
     assert L.gdf_fuse_workspace_size(0, 2048, 2048, ctypes.byref(o)) == 0
+    # solving 32 of the 64 slices takes about half the workspace; a bad range none
+    o.z_begin, o.z_end = 16, 48
+    h = L.gdf_fuse_workspace_size(64, 2048, 2048, ctypes.byref(o))
+    assert 0.45 * a < h < 0.55 * a
+    o.z_begin, o.z_end = 48, 16
+    assert L.gdf_fuse_workspace_size(64, 2048, 2048, ctypes.byref(o)) == 0
+    o.z_begin = o.z_end = 0
     d = (gdf.SliceDesc * 2)()
     for i, (H, W) in enumerate(((17, 33), (1, 1))):
         d[i].H, d[i].W, d[i].alpha = H, W, 0.01

@@ -522,6 +522,36 @@ def test_streamed_stack_matches_whole():
         assert np.abs(f_s[j].numpy() - fr).max() <= 1e-3, j
 
 
+@pytest.mark.parametrize("precision,z0,z1", [("fp32", 10, 20), ("fp32", 0, 5), ("fp32", 27, 32),
+                                              ("fp32", 31, 32), ("fp32", 0, 32), ("fp64", 3, 29),
+                                              ("mixed", 12, 13)])
+def test_fuse_stack_slice_range(precision, z0, z1):
+    """z_range solves slices z0 .. z1 - 1 only, the others entering their
+    cross-slice windows: g_s is the whole-stack one bit for bit, f matches
+    the whole-stack call and the oracle, the report has one entry per slice."""
+    S, H, W = 32, 70, 150
+    stack = synth.make_stack(S, H, W, seed=91, ramp=True)
+    st = torch.from_numpy(stack).to(DEV)
+    tol = {"fp32": 1e-6, "fp64": 1e-10, "mixed": 1e-8}[precision]
+    print("slice range", precision, (z0, z1), flush=True)
+    f_r, rep_r, gs_r = gdf.fuse_stack(st, 0.01, tol=tol, precision=precision, return_smooth=True, z_range=(z0, z1))
+    f_w, rep_w, gs_w = gdf.fuse_stack(st, 0.01, tol=tol, precision=precision, return_smooth=True)
+    f_n, rep_n = gdf.fuse_stack(st, 0.01, tol=tol, precision=precision, z_range=(z0, z1))   # no g_s output
+    torch.cuda.synchronize()
+    assert f_r.shape == (z1 - z0, H, W) and gs_r.shape == (z1 - z0, H, W) and len(rep_r) == z1 - z0
+    assert torch.equal(gs_r, gs_w[z0:z1])
+    bound = {"fp32": 1e-3, "fp64": 1e-6, "mixed": 1e-4}[precision]
+    assert (f_r - f_w[z0:z1]).abs().max().item() <= bound
+    assert (f_n - f_w[z0:z1]).abs().max().item() <= bound
+    assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= tol for r in rep_r + rep_n)
+    gs = oracle.smooth(stack)
+    for j in sorted({z0, z1 - 1}):
+        fr = oracle.solve(gs[j], stack[j].astype(np.float64), 0.01, tol=1e-12)
+        err = np.abs(f_r[j - z0].cpu().numpy().astype(np.float64) - fr).max()
+        print("slice", j, "err %.2e" % err, flush=True)
+        assert err <= bound
+
+
 @pytest.mark.parametrize("shape", [(7, 33, 64), (5, 21, 37)])
 def test_smooth_transpose_adds_in_place(shape):
     """out = K (G / D) + add with add = out (accumulate in place), on the
