@@ -173,6 +173,11 @@ void gdf_release(void);
  * g_smooth_dev   optional output [S][H][W] contiguous (NULL to skip): I1 in
  *                FP32 (FP64 when precision is GDF_PREC_FP64).
  * report_host    optional [S] per-slice report.
+ * With opts.use_graph the smoothing and the whole solve are captured as one
+ * graph per (sizes, pointers, stream, options) and replayed, convergence
+ * decided on the device: the call then waits for the device only to read the
+ * report (cap opts.max_vcycles: the graph holds that many cycles, which
+ * converged slices skip).
  * Returns GDF_OK when every slice reached tol.                              */
 size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts);
 

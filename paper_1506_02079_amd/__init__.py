@@ -169,6 +169,22 @@ def _side_stream(dev):
     return _SIDE[key]
 
 
+def _on_side_stream(dev, call, tensors):
+    """Runs call() (a library call on _stream(dev)) on a side stream ordered
+    after the caller's current stream and joined back after it: stream
+    capture needs a stream other than the default one."""
+    torch = _torch()
+    cur = torch.cuda.current_stream(dev)
+    side = _side_stream(dev)
+    side.wait_stream(cur)
+    with torch.cuda.stream(side):
+        st = call()
+    cur.wait_stream(side)
+    for t in tensors:
+        t.record_stream(side)
+    return st
+
+
 def _dtype_code(t):
     torch = _torch()
     return {torch.uint8: DTYPE_U8, torch.float32: DTYPE_F32, torch.float64: DTYPE_F64}[t.dtype]
@@ -185,13 +201,15 @@ def _require_cuda(*ts):
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
                tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
-               allow_noconv=False, robust=False, z_range=None):
+               allow_noconv=False, robust=False, z_range=None, use_graph=False):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
     robust=True: robust cross-slice averaging (values more than two weighted
     standard deviations from the window's weighted mean are left out).
     z_range=(z0, z1): solve only slices z0 .. z1 - 1 (the others only enter
     their cross-slice windows); f, g_smooth and the report then hold z1 - z0
-    slices.
+    slices.  use_graph=True: the whole schedule (smoothing and every V-cycle,
+    with the convergence test on the device) is captured once per shape,
+    pointers and options, then replayed; the host waits only for the report.
 
     Returns (f, report) or (f, report, g_smooth) with return_smooth=True.
     f has dtype float32 (fp32) or float64 (fp64 / mixed) unless out_dtype is given.
@@ -203,7 +221,7 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
     if stack.stride(2) != 1:
         stack = stack.contiguous()
     S, H, W = stack.shape
-    o = make_opts(precision, max_vcycles, nu, out_dtype, False, tile_rows, inner_cycles,
+    o = make_opts(precision, max_vcycles, nu, out_dtype, use_graph, tile_rows, inner_cycles,
                   launch_mode, autotune, fine_sweeps, coarse_sweeps)
     o.robust = int(bool(robust))
     n = S
@@ -223,10 +241,14 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                           device=stack.device)
     work = torch.empty(ws, dtype=torch.uint8, device=stack.device)
     rep = (SliceReport * n)()
-    st = L.fuse_stack(stack.data_ptr(), S, H, W, stack.stride(1), stack.stride(0), float(alpha),
-                      BC[bc], float(tol), float(sigma_xy), float(sigma_z), f.data_ptr(),
-                      gsm.data_ptr() if gsm is not None else None, ctypes.byref(o),
-                      work.data_ptr(), ws, rep, _stream(stack.device))
+    call = lambda: L.fuse_stack(stack.data_ptr(), S, H, W, stack.stride(1), stack.stride(0), float(alpha),
+                                BC[bc], float(tol), float(sigma_xy), float(sigma_z), f.data_ptr(),
+                                gsm.data_ptr() if gsm is not None else None, ctypes.byref(o),
+                                work.data_ptr(), ws, rep, _stream(stack.device))
+    if use_graph:
+        st = _on_side_stream(stack.device, call, [t for t in (work, stack, f, gsm) if t is not None])
+    else:
+        st = call()
     _check(st, allow_noconv)
     out = (f, _report_list(rep, n))
     return out + (gsm,) if return_smooth else out
@@ -303,18 +325,11 @@ def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_
     work = torch.empty(ws, dtype=torch.uint8, device=dev)
     rep = (SliceReport * n)()
     if use_graph:
-        # stream capture needs a non-default stream: run on a side stream that
-        # is ordered after the caller's current stream and joined back after
-        cur = torch.cuda.current_stream(dev)
-        side = _side_stream(dev)
-        side.wait_stream(cur)
-        with torch.cuda.stream(side):
-            st = L.solve_slices(n, d, _dtype_code(gs_list[0]), bases[0], _dtype_code(go_list[0]),
-                                bases[1], BC[bc], float(tol), bases[2], ctypes.byref(o),
-                                work.data_ptr(), ws, rep, _stream(dev))
-        cur.wait_stream(side)
-        for t in (work, *gs_list, *go_list, *f_list):
-            t.record_stream(side)
+        st = _on_side_stream(dev, lambda: L.solve_slices(n, d, _dtype_code(gs_list[0]), bases[0],
+                                                         _dtype_code(go_list[0]), bases[1], BC[bc], float(tol),
+                                                         bases[2], ctypes.byref(o), work.data_ptr(), ws, rep,
+                                                         _stream(dev)),
+                             [work, *gs_list, *go_list, *f_list])
     else:
         st = L.solve_slices(n, d, _dtype_code(gs_list[0]), bases[0], _dtype_code(go_list[0]),
                             bases[1], BC[bc], float(tol), bases[2], ctypes.byref(o),

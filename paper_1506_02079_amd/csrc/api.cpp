@@ -27,6 +27,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1614,6 +1615,37 @@ gdf_status smooth_transpose(const float *grad_dev, int S, int H, int W, double s
     return GDF_OK;
 }
 
+// Runs body (the whole device schedule of a call) as a graph: captured on
+// the stream the first time for this key (sizes, pointers, stream and
+// options), then replayed.  Convergence is decided on the device inside the
+// graph (per-slice flags); the host reads the states once, afterwards.
+static gdf_status run_captured(const std::vector<unsigned long long> &key, Run &R, const Opts &o,
+                               const std::function<gdf_status()> &body)
+{
+    hipStream_t s = R.s;
+    hipGraphExec_t ex = graph_lookup(key);
+    if (!ex) {
+        if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.csw, o.fsw, R.P.fp64);
+        R.capturing = true;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        gdf_status q = body();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        R.capturing = false;
+        if (q) {
+            if (g) hipGraphDestroy(g);
+            return q;
+        }
+        if (ec != hipSuccess) return set_err(GDF_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ei != hipSuccess) return set_err(GDF_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ei));
+        graph_store(key, ex);
+    }
+    HIP_TRY(hipGraphLaunch(ex, s));
+    return GDF_OK;
+}
+
 size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
 {
     const gdf_solve_opts b = opts_or_zero(opts);
@@ -1768,23 +1800,6 @@ static gdf_status fuse_stack_plain(const uint8_t *stack_all, int S_all, int H, i
     a.part_bb = R.partd;
     a.part_b0 = R.partd2;
     a.part_bs = R.partd3;
-    {
-        ProfScope ps(PC_SMOOTH,
-                     (double)H * W * ((zv1 - zv0) + S * (P.esz + (gs_used ? P.esz : 0) + (a.bc0 ? 0.25 * P.csz : 0.0))),
-                     s, false);
-        HIP_TRY(launch_smooth(P.fp64, a, s));
-    }
-    R.raw_rhs_l1 = a.bc0 != nullptr;
-    if (periodic) {
-        // the norms of Eq. (1)'s right-hand side with the periodic Laplacian,
-        // from the b_u the smoothing wrote and the stack
-        HIP_TRY(launch_pprep(P.fp64, P.fp64 ? GDF_F64 : GDF_F32, nullptr, GDF_U8, stack, R.io, R.plaunch(0), R.partd,
-                             R.partd2, R.partd3, s));
-        HIP_TRY(launch_finish_rhs(P.n, R.r_p0, R.partd, R.partd2, R.partd3, R.st, s));
-    } else {
-        HIP_TRY(launch_finish_rhs(P.n, R.r_smooth, R.partd, R.partd2, R.partd3, R.st, s));
-    }
-
     SolveIO x;
     x.gs_dtype = P.fp64 ? GDF_F64 : GDF_F32;
     x.gs = gs_used;
@@ -1792,7 +1807,42 @@ static gdf_status fuse_stack_plain(const uint8_t *stack_all, int S_all, int H, i
     x.go = stack;
     x.f = f;
     x.rows_ok = fin_rows_ok(io);
-    if ((r = solve_body(R, x))) return r;
+
+    auto body = [&]() -> gdf_status {
+        {
+            ProfScope ps(PC_SMOOTH,
+                         (double)H * W * ((zv1 - zv0) + S * (P.esz + (gs_used ? P.esz : 0) + (a.bc0 ? 0.25 * P.csz : 0.0))),
+                         s, R.capturing);
+            HIP_TRY(launch_smooth(P.fp64, a, s));
+        }
+        R.raw_rhs_l1 = a.bc0 != nullptr;
+        if (periodic) {
+            // the norms of Eq. (1)'s right-hand side with the periodic Laplacian,
+            // from the b_u the smoothing wrote and the stack
+            HIP_TRY(launch_pprep(P.fp64, P.fp64 ? GDF_F64 : GDF_F32, nullptr, GDF_U8, stack, R.io, R.plaunch(0),
+                                 R.partd, R.partd2, R.partd3, s));
+            HIP_TRY(launch_finish_rhs(P.n, R.r_p0, R.partd, R.partd2, R.partd3, R.st, s));
+        } else {
+            HIP_TRY(launch_finish_rhs(P.n, R.r_smooth, R.partd, R.partd2, R.partd3, R.st, s));
+        }
+        return solve_body(R, x);
+    };
+    if (!o.use_graph) {
+        if ((r = body())) return r;
+    } else {
+        std::vector<unsigned long long> key;
+        key_push(key, 3);
+        for (int v : {S_all, H, W, z0, z1, bc, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype, o.tile_rows, o.inner, o.launch,
+                      o.fsw, o.robust})
+            key_push(key, v);
+        for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
+        key_push(key, pitch_row);
+        key_push(key, pitch_slice);
+        for (const void *p : {(const void *)stack_all, (const void *)f, (const void *)g_smooth, (const void *)ws,
+                              (const void *)s})
+            key_push(key, p);
+        if ((r = run_captured(key, R, o, body))) return r;
+    }
     std::vector<SliceState> h;
     const gdf_status st = collect(P, ws, s, report, tol, mixed ? o.inner : 1, &h);
     if (st != GDF_ENOCONV || o.prec != GDF_PREC_FP32) return st;
@@ -2141,26 +2191,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
             key_push(key, d[i].pitch_go);
             key_push(key, d[i].pitch_f);
         }
-        hipGraphExec_t ex = graph_lookup(key);
-        if (!ex) {
-            if (o.launch == GDF_LAUNCH_PERSISTENT) strip_prepare(o.csw, o.fsw, P.fp64);
-            R.capturing = true;
-            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            gdf_status q = body();
-            hipGraph_t g = nullptr;
-            const hipError_t ec = hipStreamEndCapture(s, &g);
-            if (q) {
-                if (g) hipGraphDestroy(g);
-                return q;
-            }
-            if (ec != hipSuccess) return set_err(GDF_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
-            const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
-            if (ei != hipSuccess) return set_err(GDF_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ei));
-            graph_store(key, ex);
-            R.capturing = false;
-        }
-        HIP_TRY(hipGraphLaunch(ex, s));
+        if ((r = run_captured(key, R, o, body))) return r;
     }
     std::vector<SliceState> h;
     const gdf_status st = collect(P, ws, s, report, tol, o.prec == GDF_PREC_MIXED ? o.inner : 1, &h);

@@ -552,6 +552,29 @@ def test_fuse_stack_slice_range(precision, z0, z1):
         assert err <= bound
 
 
+@pytest.mark.parametrize("precision,z_range", [("fp32", None), ("fp32", (4, 9)), ("mixed", None),
+                                              ("fp64", (0, 3))])
+def test_fuse_stack_graph_replays(precision, z_range):
+    """use_graph: the captured schedule (smoothing, cycles, device-side
+    convergence) replayed three times, with eager calls in between, gives the
+    eager result each time."""
+    S, H, W = 12, 90, 140
+    stack = synth.make_stack(S, H, W, seed=93, ramp=True)
+    st = torch.from_numpy(stack).to(DEV)
+    tol = {"fp32": 1e-6, "fp64": 1e-10, "mixed": 1e-8}[precision]
+    kw = dict(tol=tol, precision=precision, z_range=z_range, max_vcycles=12)
+    f_e, rep_e = gdf.fuse_stack(st, 0.01, **kw)
+    out = torch.empty_like(f_e)
+    for i in range(3):
+        print("graph replay", precision, z_range, i, flush=True)
+        f_g, rep_g = gdf.fuse_stack(st, 0.01, use_graph=True, **kw)
+        torch.cuda.synchronize()
+        assert (f_g - f_e).abs().max().item() <= (1e-3 if precision == "fp32" else 1e-6)
+        assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= tol for r in rep_g)
+        assert [r["vcycles"] for r in rep_g] == [r["vcycles"] for r in rep_e]
+        out.copy_(gdf.fuse_stack(st, 0.02, tol=tol, precision=precision, z_range=z_range)[0])   # eager work between
+
+
 @pytest.mark.parametrize("shape", [(7, 33, 64), (5, 21, 37)])
 def test_smooth_transpose_adds_in_place(shape):
     """out = K (G / D) + add with add = out (accumulate in place), on the
