@@ -20,8 +20,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgdf.so")
 INCLUDE = os.path.join(ROOT, "include")
 
-SOURCES = ["smooth_rz_c.hip", "mg_kernels.hip", "smooth_rz_a.hip", "smooth_rz_b.hip",
-           "smooth_rz_d.hip", "tile_kernels.hip", "periodic_kernels.hip", "smooth_kernel.hip", "smooth_transpose.hip", "api.cpp"]
+SOURCES = ["smooth_rz_b.hip", "mg_kernels.hip", "smooth_rz_d.hip", "smooth_rz_e.hip", "smooth_rz_f.hip",
+           "smooth_rz_a.hip", "smooth_rz_c.hip", "tile_kernels.hip", "periodic_kernels.hip", "smooth_kernel.hip",
+           "smooth_transpose.hip", "api.cpp"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("GDF_OFFLOAD_ARCH", "gfx950")

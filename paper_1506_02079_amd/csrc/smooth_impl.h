@@ -89,8 +89,10 @@ inline bool smooth_fast_loads(const SmoothArgs &a)
 // cross-slice average of "Extensions and Applications" (values more than two
 // weighted standard deviations from the window's weighted mean left out).
 // Plain FP32 instances keep four waves per SIMD (two workgroups per CU); FP64
-// and robust ones need more registers than that allows.
-template <typename T, int RZ, int RT, bool FAST, bool ROBUST>
+// and robust ones need more registers than that allows.  RANGE: only the
+// output slices [a.z_lo, a.z_hi) are computed and stored (a uniform test per
+// step; without it the march has none).
+template <typename T, int RZ, int RT, bool FAST, bool ROBUST, bool RANGE>
 __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) void smooth_kernel(SmoothArgs a)
 {
     constexpr int NZ = 2 * RZ + 1;     // register ring of blurred planes
@@ -107,6 +109,8 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     const int tile_x = tile % a.tiles_x, tile_y = tile / a.tiles_x;
     const int X0 = tile_x * kSTX, Y0 = tile_y * kSTY;
     const int S = a.S, H = a.H, W = a.W, R = a.rxy;
+    // output slices (RANGE: [a.z_lo, a.z_hi); otherwise all, with no test in the march)
+    const int z_lo = RANGE ? a.z_lo : 0, z_hi = RANGE ? a.z_hi : S;
     constexpr int rawH = kSTY + 2 * RH;
     const int n_dw = rawH * kRawDw;
     const bool aligned = ((a.pitch_row & 3) == 0) && ((a.pitch_slice & 3) == 0) &&
@@ -240,7 +244,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     // (groups count from the first output slice; partial sums are indexed by
     // output slice, z - z_lo)
     auto partial = [&](int z) {
-        const int zl = z - a.z_lo;
+        const int zl = z - z_lo;
         const int zs = zl % kPB;   // uniform
         if (tid < 3 * kPB && ps == zs) {
             double v = 0.0;
@@ -248,7 +252,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             for (int w = 0; w < kSmoothWaves; ++w) v += red_s[z & 1][w][pq];
             pbuf = v;
         }
-        if ((zs == kPB - 1 || z == a.z_hi - 1) && a.b0) {
+        if ((zs == kPB - 1 || z == z_hi - 1) && a.b0) {
             if (tid < 3 * (zs + 1)) {
                 double *dst = pq == 0 ? a.part_bb : (pq == 1 ? a.part_b0 : a.part_bs);
                 dst[(long long)(zl - zs + ps) * nparts + tile] = pbuf;
@@ -265,7 +269,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     float hx = 0.f;   // odd waves: column sum of their first row (the pair's second row)
     auto cstore = [&](int z, int ty, float v) {   // ty: tile row of the cell's first child (even)
         if (Y0 + ty >= H) return;
-        const Rsrc rc = make_rsrc(static_cast<unsigned short *>(a.bc0) + (long long)(z - a.z_lo) * a.bc_slice_stride +
+        const Rsrc rc = make_rsrc(static_cast<unsigned short *>(a.bc0) + (long long)(z - z_lo) * a.bc_slice_stride +
                                       (long long)((Y0 + ty) >> 1) * a.bc_pitch,
                                   (unsigned)a.bc_pitch * 2u);
         Buf<unsigned short>::st(__builtin_bit_cast(unsigned short, (__bf16)v), rc, vcol, 0);   // nearest even
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
         // ------------- output slice zo = zi - 1 - RZ (the first test is static in
         // the peeled steps)
         const int zo = zi - 1 - RZ;
-        if (zo >= 0 && zo >= a.z_lo && zo < a.z_hi) {
+        if (zo >= 0 && (!RANGE || (zo >= z_lo && zo < z_hi))) {
             const int zlo = min(RZ, zo), zhi = min(RZ, S - 1 - zo);   // in-stack taps
             T iz;
             if constexpr (sizeof(T) == 4) iz = a.inv_wz_f[zlo][zhi];
@@ -347,7 +351,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             // this slice's tile rows of b (and of g_s): windows of kSTY rows
             // (a resource of size zero drops the stores: no b_u without a.b0, and
             // g_s only for the output slices asked for)
-            const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)(zo - a.z_lo) * a.b_slice_stride +
+            const Rsrc rbw = make_rsrc(static_cast<T *>(a.b0) + (long long)(zo - z_lo) * a.b_slice_stride +
                                            (long long)Y0 * a.b_pitch,
                                        a.b0 ? (unsigned)(kSTY * a.b_pitch * (int)sizeof(T)) : 0u);
             const bool gsz = a.gs_out && zo >= a.gs_zlo && zo < a.gs_zhi;   // uniform
@@ -421,10 +425,10 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
             commit(zi + 1);
 #pragma unroll
             for (int i = 0; i < kSRows; ++i) asm volatile("" ::"v"(hold[i]));
-            if (zo - 1 >= a.z_lo) partial(zo - 1);
+            if (zo - 1 >= z_lo) partial(zo - 1);
             if (rst) {
                 if constexpr (kSRows % 2 == 1)
-                    if ((wv & 1) && zo - 1 >= a.z_lo) cstore(zo - 1, yb - 1, xs[(zo - 1) & 1][wv >> 1][tx] + hx);
+                    if ((wv & 1) && zo - 1 >= z_lo) cstore(zo - 1, yb - 1, xs[(zo - 1) & 1][wv >> 1][tx] + hx);
                 float cs[kSRows];
 #pragma unroll
                 for (int i = 0; i < kSRows; ++i) cs[i] = bms[i] + dpp_row<0xB1>(bms[i]);   // lane pairs
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
     // constant, so the steps before the first output carry no output code.
     // In the others every step has an output slice (zo >= NZ - 1 - RZ = RZ).
     // (the march ends with the last output slice)
-    const int zend = a.z_hi + RZ + 1;
+    const int zend = z_hi + RZ + 1;
 #pragma unroll
     for (int k = 0; k < NZ; ++k)
         if (k < zend) step(k, k);
@@ -474,23 +478,29 @@ __global__ __launch_bounds__(kSThreads, ((sizeof(T) == 4 && !ROBUST) ? 4 : 1)) v
         for (int k = 0; k < NZ; ++k)
             if (zb + k < zend) step(zb + k, k);   // uniform across the block
     }
-    partial(a.z_hi - 1);   // the last slice's sums are complete after the last barrier
+    partial(z_hi - 1);   // the last slice's sums are complete after the last barrier
     if constexpr (kSRows % 2 == 1)
-        if (rst && (wv & 1)) cstore(a.z_hi - 1, yb - 1, xs[(a.z_hi - 1) & 1][wv >> 1][tx] + hx);
+        if (rst && (wv & 1)) cstore(z_hi - 1, yb - 1, xs[(z_hi - 1) & 1][wv >> 1][tx] + hx);
 }
 
 // Launch one (precision, radius) instance; defined per cross-slice radius in
 // the smooth_rz*.hip translation units so they compile in parallel.
+template <typename T, int RZ, int RT, bool ROBUST, bool RANGE>
+hipError_t smooth_launch_r(const SmoothArgs &a, hipStream_t s)
+{
+    if (smooth_fast_loads(a))
+        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, true, ROBUST, RANGE>), dim3(a.tiles_x * a.tiles_y),
+                           dim3(kSThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, false, ROBUST, RANGE>), dim3(a.tiles_x * a.tiles_y),
+                           dim3(kSThreads), 0, s, a);
+    return hipGetLastError();
+}
 template <typename T, int RZ, int RT, bool ROBUST>
 hipError_t smooth_launch(const SmoothArgs &a, hipStream_t s)
 {
-    if (smooth_fast_loads(a))
-        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, true, ROBUST>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0, s,
-                           a);
-    else
-        hipLaunchKernelGGL((smooth_kernel<T, RZ, RT, false, ROBUST>), dim3(a.tiles_x * a.tiles_y), dim3(kSThreads), 0,
-                           s, a);
-    return hipGetLastError();
+    if (a.z_lo == 0 && a.z_hi == a.S) return smooth_launch_r<T, RZ, RT, ROBUST, false>(a, s);
+    return smooth_launch_r<T, RZ, RT, ROBUST, true>(a, s);
 }
 
 // All instances for one cross-slice radius RZ.
