@@ -177,7 +177,12 @@ void gdf_release(void);
  * graph per (sizes, pointers, stream, options) and replayed, convergence
  * decided on the device: the call then waits for the device only to read the
  * report (cap opts.max_vcycles: the graph holds that many cycles, which
- * converged slices skip).
+ * converged slices skip).  With use_graph and report_host NULL the call is
+ * asynchronous: it returns GDF_OK once the work is enqueued on the stream,
+ * without waiting; slices are not checked against tol on the host and
+ * slices left at the FP32 floor are not re-solved (reading the report is
+ * what decides both).  The workspace and buffers must stay valid until the
+ * stream has run the work.
  * Returns GDF_OK when every slice reached tol.                              */
 size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts);
 
@@ -196,7 +201,8 @@ gdf_status fuse_stack(const uint8_t *stack_dev, int S, int H, int W, long long p
  * go_dtype/go    g_o buffer: GDF_U8, GDF_F32 or GDF_F64.
  * f_dev          output buffer, dtype opts.out_dtype.
  * Uneven batches run as one work list per multigrid level; with
- * opts.use_graph the schedule is captured once and replayed.               */
+ * opts.use_graph the schedule is captured once and replayed, and with
+ * use_graph and report_host NULL the call is asynchronous (as fuse_stack).  */
 size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *desc_host, const gdf_solve_opts *opts);
 
 gdf_status solve_slices(int n, const gdf_slice_desc *desc_host, int gs_dtype, const void *gs_dev,

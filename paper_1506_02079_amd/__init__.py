@@ -201,7 +201,7 @@ def _require_cuda(*ts):
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
                tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
-               allow_noconv=False, robust=False, z_range=None, use_graph=False):
+               allow_noconv=False, robust=False, z_range=None, use_graph=False, wait=True):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
     robust=True: robust cross-slice averaging (values more than two weighted
     standard deviations from the window's weighted mean are left out).
@@ -210,6 +210,8 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
     slices.  use_graph=True: the whole schedule (smoothing and every V-cycle,
     with the convergence test on the device) is captured once per shape,
     pointers and options, then replayed; the host waits only for the report.
+    use_graph=True, wait=False: asynchronous; the call returns (f, None) once
+    the work is enqueued on the current stream (no report, no per-slice check).
 
     Returns (f, report) or (f, report, g_smooth) with return_smooth=True.
     f has dtype float32 (fp32) or float64 (fp64 / mixed) unless out_dtype is given.
@@ -239,8 +241,10 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
     if return_smooth:
         gsm = torch.empty((n, H, W), dtype=torch.float64 if o.precision == 1 else torch.float32,
                           device=stack.device)
+    if not wait and not use_graph:
+        raise ValueError("wait=False needs use_graph=True (the eager schedule reads flags every cycle)")
     work = torch.empty(ws, dtype=torch.uint8, device=stack.device)
-    rep = (SliceReport * n)()
+    rep = (SliceReport * n)() if wait else None
     call = lambda: L.fuse_stack(stack.data_ptr(), S, H, W, stack.stride(1), stack.stride(0), float(alpha),
                                 BC[bc], float(tol), float(sigma_xy), float(sigma_z), f.data_ptr(),
                                 gsm.data_ptr() if gsm is not None else None, ctypes.byref(o),
@@ -250,7 +254,7 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
     else:
         st = call()
     _check(st, allow_noconv)
-    out = (f, _report_list(rep, n))
+    out = (f, _report_list(rep, n) if wait else None)
     return out + (gsm,) if return_smooth else out
 
 

@@ -1842,6 +1842,7 @@ static gdf_status fuse_stack_plain(const uint8_t *stack_all, int S_all, int H, i
                               (const void *)s})
             key_push(key, p);
         if ((r = run_captured(key, R, o, body))) return r;
+        if (!report) return GDF_OK;   // asynchronous: nothing waits for the device
     }
     std::vector<SliceState> h;
     const gdf_status st = collect(P, ws, s, report, tol, mixed ? o.inner : 1, &h);
@@ -2192,6 +2193,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
             key_push(key, d[i].pitch_f);
         }
         if ((r = run_captured(key, R, o, body))) return r;
+        if (!report) return GDF_OK;   // asynchronous: nothing waits for the device
     }
     std::vector<SliceState> h;
     const gdf_status st = collect(P, ws, s, report, tol, o.prec == GDF_PREC_MIXED ? o.inner : 1, &h);

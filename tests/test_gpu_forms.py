@@ -573,6 +573,12 @@ def test_fuse_stack_graph_replays(precision, z_range):
         assert all(r["status"] == gdf.GDF_OK and r["rel_residual"] <= tol for r in rep_g)
         assert [r["vcycles"] for r in rep_g] == [r["vcycles"] for r in rep_e]
         out.copy_(gdf.fuse_stack(st, 0.02, tol=tol, precision=precision, z_range=z_range)[0])   # eager work between
+    # asynchronous: no report, nothing waits; the caller's stream orders the result
+    f_a, rep_a = gdf.fuse_stack(st, 0.01, use_graph=True, wait=False, **kw)
+    assert rep_a is None
+    assert (f_a - f_e).abs().max().item() <= (1e-3 if precision == "fp32" else 1e-6)
+    with pytest.raises(ValueError):
+        gdf.fuse_stack(st, 0.01, wait=False, **kw)
 
 
 @pytest.mark.parametrize("shape", [(7, 33, 64), (5, 21, 37)])
