@@ -117,7 +117,13 @@ typedef struct {
                           floor(3 sigma_z) slices on either side, gives the whole-stack
                           result for its own slices ("Distributed Processing").  f_dev,
                           g_smooth_dev and report_host then hold z_end - z_begin slices. */
-    int reserved[2];
+    int sor;           /* 1: over-relaxed red-black sweeps in the fused finest passes: every
+                          half-sweep after the first of a pass moves its pixels by 1.2 times
+                          the Gauss-Seidel step (a solver choice, not the paper's).  FP32 and
+                          MIXED hierarchies with fine_sweeps 4 or 5, Neumann boundary
+                          (GDF_EUNSUPPORTED otherwise); 0 = Gauss-Seidel.  The autotuner
+                          tries it when left at 0. */
+    int reserved[1];
 } gdf_solve_opts;
 
 typedef enum {

@@ -42,7 +42,7 @@ class SolveOpts(ctypes.Structure):
                 ("launch_mode", ctypes.c_int), ("autotune", ctypes.c_int),
                 ("fine_sweeps", ctypes.c_int), ("coarse_sweeps", ctypes.c_int),
                 ("robust", ctypes.c_int), ("z_begin", ctypes.c_int), ("z_end", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("sor", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 class SliceReport(ctypes.Structure):
@@ -111,7 +111,7 @@ def version() -> str:
 
 def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=False,
               tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0,
-              coarse_sweeps=0) -> SolveOpts:
+              coarse_sweeps=0, sor=False) -> SolveOpts:
     o = SolveOpts()
     o.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     o.max_vcycles = int(max_vcycles)
@@ -124,17 +124,18 @@ def make_opts(precision="fp32", max_vcycles=0, nu=0, out_dtype=None, use_graph=F
     o.autotune = int(bool(autotune))
     o.fine_sweeps = int(fine_sweeps)
     o.coarse_sweeps = int(coarse_sweeps)
+    o.sor = int(bool(sor))
     return o
 
 
 def autotune_last():
     """Settings chosen by the last autotuned call on this thread, or None:
-    dict(nu, fine_sweeps, coarse_sweeps, tile_rows, launch_mode)."""
+    dict(nu, fine_sweeps, coarse_sweeps, tile_rows, launch_mode, sor)."""
     o = SolveOpts()
     if not lib().gdf_autotune_last(ctypes.byref(o)):
         return None
     return dict(nu=o.nu, fine_sweeps=o.fine_sweeps, coarse_sweeps=o.coarse_sweeps, tile_rows=o.tile_rows,
-                launch_mode=o.launch_mode)
+                launch_mode=o.launch_mode, sor=bool(o.sor))
 
 
 def _check(status, allow_noconv=False):
@@ -201,8 +202,9 @@ def _require_cuda(*ts):
 def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
                precision="fp32", out_dtype=None, return_smooth=False, nu=0, max_vcycles=0,
                tile_rows=0, inner_cycles=0, launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0,
-               allow_noconv=False, robust=False, z_range=None, use_graph=False, wait=True):
+               allow_noconv=False, robust=False, z_range=None, use_graph=False, wait=True, sor=False):
     """Smooth a uint8 stack [S, H, W] across slices and blend each slice (Eq. (1)).
+    sor=True: over-relaxed sweeps in the fused finest passes (fine_sweeps 4 or 5).
     robust=True: robust cross-slice averaging (values more than two weighted
     standard deviations from the window's weighted mean are left out).
     z_range=(z0, z1): solve only slices z0 .. z1 - 1 (the others only enter
@@ -224,7 +226,7 @@ def fuse_stack(stack, alpha, bc="neumann", tol=1e-6, sigma_xy=1.0, sigma_z=3.0,
         stack = stack.contiguous()
     S, H, W = stack.shape
     o = make_opts(precision, max_vcycles, nu, out_dtype, use_graph, tile_rows, inner_cycles,
-                  launch_mode, autotune, fine_sweeps, coarse_sweeps)
+                  launch_mode, autotune, fine_sweeps, coarse_sweeps, sor)
     o.robust = int(bool(robust))
     n = S
     if z_range is not None:
@@ -285,7 +287,7 @@ def _descs(gs_list, go_list, f_list, alphas):
 
 def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_dtype=None,
                  nu=0, max_vcycles=0, use_graph=False, tile_rows=0, inner_cycles=0,
-                 launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False):
+                 launch_mode=0, autotune=False, fine_sweeps=0, coarse_sweeps=0, allow_noconv=False, sor=False):
     """Eq. (1) per slice.  g_s, g_o: [S, H, W] tensors or lists of 2D tensors
     (uneven batch).  alpha: scalar or per-slice sequence.  Returns (f, report)
     with f shaped like the input (a list for list input)."""
@@ -307,7 +309,7 @@ def solve_slices(g_s, g_o, alpha, bc="neumann", tol=1e-6, precision="fp32", out_
         raise ValueError("all g_s slices (and all g_o slices) must share a dtype")
     alphas = [float(alpha)] * n if not hasattr(alpha, "__len__") else [float(a) for a in alpha]
     o = make_opts(precision, max_vcycles, nu, out_dtype, use_graph, tile_rows, inner_cycles,
-                  launch_mode, autotune, fine_sweeps, coarse_sweeps)
+                  launch_mode, autotune, fine_sweeps, coarse_sweeps, sor)
     od = o.out_dtype or (DTYPE_F32 if o.precision == 0 else DTYPE_F64)
     fdt = torch.float64 if od == DTYPE_F64 else torch.float32
     dev = gs_list[0].device

@@ -81,6 +81,7 @@ struct Opts {
     int fsw;   // sweeps of the fused finest pass
     int csw;   // sweeps per smoothing step on the coarse levels
     int robust;   // robust cross-slice averaging in fuse_stack
+    int sor;      // over-relaxed fused finest passes
 };
 
 gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
@@ -126,6 +127,11 @@ gdf_status parse_opts(const gdf_solve_opts *o, Opts &r)
     if (r.robust != 0 && r.robust != 1) return set_err(GDF_EINVAL, "opts.robust must be 0 or 1 (got %d)", r.robust);
     if (r.robust && r.prec == GDF_PREC_FP64)
         return set_err(GDF_EUNSUPPORTED, "opts.robust: robust averaging runs in the FP32 smoothing (FP32 or MIXED)");
+    r.sor = o->sor;
+    if (r.sor != 0 && r.sor != 1) return set_err(GDF_EINVAL, "opts.sor must be 0 or 1 (got %d)", r.sor);
+    if (r.sor && (r.prec == GDF_PREC_FP64 || (r.fsw != 4 && r.fsw != 5)))
+        return set_err(GDF_EUNSUPPORTED, "opts.sor: over-relaxed sweeps are built for FP32 hierarchies (FP32 or "
+                                         "MIXED) with 4 or 5 fused finest sweeps (got fine_sweeps %d)", r.fsw);
     return GDF_OK;
 }
 
@@ -606,7 +612,7 @@ gdf_status cached_plan(std::shared_ptr<const Plan> &out, int n, const std::vecto
 {
     std::vector<unsigned long long> key;
     for (int v : {n, smooth_S, need_gs ? 1 : 0, periodic ? 1 : 0, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype,
-                  o.use_graph, o.tile_rows, o.inner, o.launch, o.fsw})
+                  o.use_graph, o.tile_rows, o.inner, o.launch, o.fsw, o.sor})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
         key_push(key, H[i]);
@@ -881,7 +887,8 @@ struct Run {
         a.n_items = L.count;
         a.n_fast = L.n_fast;
         a.n_rows_in = L.n_rows_in;
-        HIP_TRY(launch_strip(kind, P.o.csw, P.o.fsw, fp64, P.o.launch == GDF_LAUNCH_PERSISTENT, a, s));
+        const bool sor = P.o.sor && (kind == SK_FINE || kind == SK_FINE_ZERO);
+        HIP_TRY(launch_strip(kind, P.o.csw, P.o.fsw, fp64, P.o.launch == GDF_LAUNCH_PERSISTENT, a, s, sor));
         return GDF_OK;
     }
 
@@ -1283,7 +1290,7 @@ gdf_status solve_body(Run &R, const SolveIO &x)
 // cached per batch signature (sizes, screening weights, tolerances, precision
 // and dtypes; not the data or the pointers) until gdf_release.
 
-struct Tuned { int nu, fine_sweeps, coarse_sweeps, tile_rows, launch; };
+struct Tuned { int nu, fine_sweeps, coarse_sweeps, tile_rows, launch, sor; };
 std::mutex g_tune_mu;
 std::vector<std::pair<std::vector<unsigned long long>, Tuned>> g_tuned;
 thread_local gdf_solve_opts g_last_tuned;
@@ -1357,7 +1364,7 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
 {
     gdf_solve_opts best = base;
     best.autotune = 0;
-    Tuned t{0, 0, 0, 0, 0};
+    Tuned t{0, 0, 0, 0, 0, 0};
     bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1394,11 +1401,22 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
         };
         try_field(&gdf_solve_opts::nu, nus);
         try_field(&gdf_solve_opts::fine_sweeps, tune_fine_sweeps(base, cur.nu));
+        // over-relaxed sweeps, with the sweep counts they are built for (fewer
+        // over-relaxed sweeps can match more plain ones, so both change together)
+        if (!base.sor && base.precision != GDF_PREC_FP64)
+            for (int fs : {4, 5}) {
+                if (fs < 2 * cur.nu || fs > 2 * cur.nu + 2 || (base.fine_sweeps && base.fine_sweeps != fs)) continue;
+                gdf_solve_opts c = cur;
+                c.sor = 1;
+                c.fine_sweeps = fs;
+                const double tc = timeit(c);
+                if (tc < tcur) { cur = c; tcur = tc; }
+            }
         try_field(&gdf_solve_opts::coarse_sweeps, tune_coarse_sweeps(base, cur.nu));
         try_field(&gdf_solve_opts::tile_rows, tiles);
         try_field(&gdf_solve_opts::launch_mode, ls);
         if (!(tcur < inf)) return call(&best);   // no candidate ran cleanly: report the plain call
-        t = Tuned{cur.nu, cur.fine_sweeps, cur.coarse_sweeps, cur.tile_rows, cur.launch_mode};
+        t = Tuned{cur.nu, cur.fine_sweeps, cur.coarse_sweeps, cur.tile_rows, cur.launch_mode, cur.sor};
         std::lock_guard<std::mutex> lk(g_tune_mu);
         if (g_tuned.size() >= 64) g_tuned.erase(g_tuned.begin());
         g_tuned.emplace_back(key, t);
@@ -1408,6 +1426,7 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
     best.coarse_sweeps = t.coarse_sweeps;
     best.tile_rows = t.tile_rows;
     best.launch_mode = t.launch;
+    best.sor = t.sor;
     g_last_tuned = best;
     g_last_tuned_ok = true;
     return call(&best);
@@ -1537,6 +1556,8 @@ static gdf_status fuse_validate(const uint8_t *stack, int S, int H, int W, long 
         return set_err(GDF_EINVAL, "pitch_row must be >= W and pitch_slice >= H * pitch_row");
     if (!(alpha > 0.0) || !std::isfinite(alpha)) return set_err(GDF_EINVAL, "alpha must be finite and > 0 (got %g)", alpha);
     if ((r = check_common(bc, tol))) return r;
+    if (o.sor && bc == GDF_BC_PERIODIC)
+        return set_err(GDF_EUNSUPPORTED, "opts.sor: the periodic multigrid has no over-relaxed sweeps");
     if (!(sxy >= 0.0) || !(sz >= 0.0) || !std::isfinite(sxy) || !std::isfinite(sz))
         return set_err(GDF_EINVAL, "sigma_xy and sigma_z must be finite and >= 0");
     if (std::floor(3.0 * sxy) > 7 || std::floor(3.0 * sz) > 12)
@@ -1653,7 +1674,7 @@ size_t gdf_fuse_workspace_size(int S, int H, int W, const gdf_solve_opts *opts)
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
-                  b.launch_mode, b.robust, b.z_begin, b.z_end})
+                  b.launch_mode, b.robust, b.z_begin, b.z_end, b.sor})
         key_push(key, v);
     return tuned_workspace(key, b, [&](const gdf_solve_opts *c) { return fuse_workspace_plain(S, H, W, c); });
 }
@@ -1679,7 +1700,7 @@ gdf_status fuse_stack(const uint8_t *stack, int S, int H, int W, long long pitch
     std::vector<unsigned long long> key;
     key_push(key, 0);
     for (int v : {S, H, W, bc, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps,
-                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust, b.z_begin, b.z_end})
+                  b.tile_rows, b.launch_mode, g_smooth ? 1 : 0, b.robust, b.z_begin, b.z_end, b.sor})
         key_push(key, v);
     for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
     return autotuned(key, b, [&](const gdf_solve_opts *c) {
@@ -1833,7 +1854,7 @@ static gdf_status fuse_stack_plain(const uint8_t *stack_all, int S_all, int H, i
         std::vector<unsigned long long> key;
         key_push(key, 3);
         for (int v : {S_all, H, W, z0, z1, bc, o.prec, o.max_vc, o.nu, o.csw, o.out_dtype, o.tile_rows, o.inner, o.launch,
-                      o.fsw, o.robust})
+                      o.fsw, o.robust, o.sor})
             key_push(key, v);
         for (double v : {alpha, tol, sigma_xy, sigma_z}) key_push(key, v);
         key_push(key, pitch_row);
@@ -1895,6 +1916,8 @@ static gdf_status slices_validate(int n, const gdf_slice_desc *d, double tol, in
     if ((r = parse_opts(opts, o))) return r;
     if (n < 1 || !d) return set_err(GDF_EINVAL, "n must be >= 1 and desc non-null");
     if ((r = check_common(bc, tol))) return r;
+    if (o.sor && bc == GDF_BC_PERIODIC)
+        return set_err(GDF_EUNSUPPORTED, "opts.sor: the periodic multigrid has no over-relaxed sweeps");
     H.resize(n);
     W.resize(n);
     al.resize(n);
@@ -1951,7 +1974,7 @@ size_t gdf_solve_workspace_size(int n, const gdf_slice_desc *d, const gdf_solve_
     std::vector<unsigned long long> key;
     key_push(key, 1);
     for (int v : {n, b.precision, b.max_vcycles, b.out_dtype, b.use_graph, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows,
-                  b.launch_mode})
+                  b.launch_mode, b.sor})
         key_push(key, v);
     for (int i = 0; i < n; ++i) {
         key_push(key, d[i].H);
@@ -2101,7 +2124,7 @@ gdf_status solve_slices(int n, const gdf_slice_desc *d, int gs_dtype, const void
     std::vector<unsigned long long> key;
     key_push(key, 1);
     for (int v : {n, bc, gs_dtype, go_dtype, b.precision, b.max_vcycles, b.out_dtype, b.use_graph,
-                  b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode})
+                  b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode, b.sor})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {
@@ -2181,6 +2204,7 @@ static gdf_status solve_slices_plain(int n, const gdf_slice_desc *d, int gs_dtyp
         key_push(key, o.inner);
         key_push(key, o.launch);
         key_push(key, o.fsw);
+        key_push(key, o.sor);
         for (int i = 0; i < n; ++i) {
             key_push(key, d[i].H);
             key_push(key, d[i].W);
@@ -2227,7 +2251,7 @@ gdf_status solve_slices_backward(int n, const gdf_slice_desc *d, int dtype, cons
     if ((r = slices_validate(n, d, tol, bc, opts, o, H, W, al))) return r;
     std::vector<unsigned long long> key;
     key_push(key, 2);
-    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode})
+    for (int v : {n, bc, dtype, b.precision, b.max_vcycles, b.inner_cycles, b.nu, b.fine_sweeps, b.coarse_sweeps, b.tile_rows, b.launch_mode, b.sor})
         key_push(key, v);
     key_push(key, tol);
     for (int i = 0; i < n; ++i) {

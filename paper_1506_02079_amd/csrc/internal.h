@@ -161,9 +161,11 @@ int strip_halo(StripKind k, int csw, int fsw);
 // the coarse passes; fsw: sweeps of the fused finest pass
 // (SK_FINE).  fp64 selects double precision.  persistent: the grid is capped
 // at the workgroups resident on the device at once and each wave loops over
-// the list's items; otherwise one wave per item.
+// the list's items; otherwise one wave per item.  sor: the over-relaxed
+// instances of SK_FINE / SK_FINE_ZERO (FP32, fsw 4 or 5; any other pass or
+// setting is an error).
 hipError_t launch_strip(StripKind k, int csw, int fsw, bool fp64, bool persistent, const StripLaunch &a,
-                        hipStream_t s);
+                        hipStream_t s, bool sor = false);
 
 // Waves of a strip kernel variant that the device holds at once (occupancy x
 // SIMDs); 0 if the runtime cannot tell (no device).

@@ -166,6 +166,10 @@ __device__ __forceinline__ int xcd_logical_block()
 
 // ------------------------------------------------------------ strip pass ---
 
+// Over-relaxation factor of the SOR instances of the fused finest pass
+// (red-black order, level 0 only)
+constexpr double kOmega = 1.2;
+
 // length of the load queue for a register ring of rs rows (a divisor of rs, so
 // that queue slots are compile-time constants in the unrolled ring loop)
 #ifndef GDF_QUEUE_MAX
@@ -211,7 +215,8 @@ template <bool PROLONG, int NHS, int RMODE, int QM = GDF_QUEUE_MAX> struct Strip
 // on coarse levels, the narrower last column).
 // SO: storage of this level's arrays; SC: storage of the next coarser level's
 // (prolongation source, restriction target).  Arithmetic is in T.
-template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR>
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, int VAR,
+          bool SOR = false>
 __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 {
     constexpr bool RIN = VAR != 0;   // rows interior: no row guards
@@ -398,6 +403,14 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     };
 #pragma unroll
     for (int q = 0; q < Q - 1; ++q) issue_row(q, q & 1, qb[q], qu[q], qus[q], qe0[q], qe1[q]);
+    // SOR: every half-sweep after the first moves its pixels by kOmega times
+    // the Gauss-Seidel step (successive over-relaxation); the first keeps
+    // omega = 1, so the red values it overwrites are still never read (and
+    // never loaded)
+    auto relax = [](T v_gs, T v_old, int s) -> T {
+        if constexpr (SOR) return s > 1 ? fma(T(kOmega), v_gs - v_old, v_old) : v_gs;
+        else return v_gs;
+    };
     // Wait for the first rows here, once per item: with loads still in flight
     // on entry, the wait at the head of the ring loop (which merges the entry
     // with the loop's own back edge) would become a full drain on every trip.
@@ -486,10 +499,10 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                         if (!GEN || CIN) {   // unit couplings
                             if (j == 0) {
                                 const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
-                                u[sl][0] = fma(nb, g0, b[sl][0]);
+                                u[sl][0] = relax(fma(nb, g0, b[sl][0]), u[sl][0], s);
                             } else {
                                 const T nb = wave_shl1(u[sl][0]) + u[sl][0] + u[su][1] + u[sd][1];
-                                u[sl][1] = fma(nb, g1, b[sl][1]);
+                                u[sl][1] = relax(fma(nb, g1, b[sl][1]), u[sl][1], s);
                             }
                         } else {             // coarse level at a column edge: per-lane couplings
                             if (j == 0) {
@@ -510,11 +523,11 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                                 if (j == 0) {
                                     const T iv = dy == 2 ? inv0[2] : (dy == 1 ? inv0[1] : inv0[0]);
                                     const T nb = wave_shr1(u[sl][1]) + u[sl][1] + u[su][0] + u[sd][0];
-                                    u[sl][0] = (b[sl][0] + nb) * iv;
+                                    u[sl][0] = relax((b[sl][0] + nb) * iv, u[sl][0], s);
                                 } else {
                                     const T iv = dy == 2 ? inv1[2] : (dy == 1 ? inv1[1] : inv1[0]);
                                     const T nb = wave_shl1(u[sl][0]) + u[sl][0] + u[su][1] + u[sd][1];
-                                    u[sl][1] = (b[sl][1] + nb) * iv;
+                                    u[sl][1] = relax((b[sl][1] + nb) * iv, u[sl][1], s);
                                 }
                             } else {
                                 const RowC rc = row_coef(y);
@@ -632,7 +645,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
 // (capped at the waves the chip holds at once) loops over the list.  Items
 // [0, n_fast) run the interior variant, [n_fast, n_rows_in) the column-edge
 // one and the rest the guarded one.
-template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool SOR = false>
 __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
 {
     if (a.done && uniform(*a.done)) return;   // a captured pass after the last active slice
@@ -640,11 +653,11 @@ __global__ __launch_bounds__(256) void strip_kernel(StripLaunch a)
     for (int id = uniform(xcd_logical_block() * kWavesPerBlock + (threadIdx.x >> 6)); id < a.n_items;
          id += stride) {
         if (id < a.n_fast)
-            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 1>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 1, SOR>(a, id);
         else if (id < a.n_rows_in)
-            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 2>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 2, SOR>(a, id);
         else
-            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 0>(a, id);
+            strip_item<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, 0, SOR>(a, id);
     }
 }
 
@@ -691,14 +704,14 @@ static int resident_blocks(const void *kernel)
 
 // Persistent grid size of one kernel instantiation, queried once (a query that
 // fails is retried on the next call).  One device type per process.
-template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN>
+template <typename T, typename SO, typename SC, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN, bool SOR>
 static int persistent_cap()
 {
     static std::atomic<int> cap{0};
     int c = cap.load(std::memory_order_relaxed);
     if (c == 0) {
         c = resident_blocks(
-            reinterpret_cast<const void *>(&strip_kernel<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>));
+            reinterpret_cast<const void *>(&strip_kernel<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, SOR>));
         if (c > 0) cap.store(c, std::memory_order_relaxed);
     }
     return c;
@@ -708,34 +721,47 @@ static int persistent_cap()
 // in LevelStor<T>::Coarse; coarse-level passes (GEN true) keep everything in
 // LevelStor<T>::Coarse.  waves non-null: only store the waves resident at once
 // (0 if unknown); n_items < 0: only resolve the persistent grid size.
-template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false>
+template <typename T, bool PROLONG, bool ZERO, int NHS, int RMODE, bool GEN = false, bool SOR = false>
 static hipError_t go(const StripLaunch &a, bool persistent, hipStream_t s, int *waves)
 {
     typedef typename LevelStor<T>::Coarse SC;
     typedef typename std::conditional<GEN, SC, T>::type SO;
     if (waves) {
-        *waves = persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>() * kWavesPerBlock;
+        *waves = persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, SOR>() * kWavesPerBlock;
         return hipSuccess;
     }
     if (a.n_items < 0) {
-        persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>();
+        persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, SOR>();
         return hipSuccess;
     }
     if (a.n_items == 0) return hipSuccess;
     const int nblocks = (a.n_items + kWavesPerBlock - 1) / kWavesPerBlock;
     int grid = ((nblocks + 7) / 8) * 8;   // multiple of 8 for the XCD remap
     if (persistent) {
-        const int cap = persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>();
+        const int cap = persistent_cap<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, SOR>();
         if (cap >= 8 && grid > cap) grid = cap;
     }
-    hipLaunchKernelGGL((strip_kernel<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((strip_kernel<T, SO, SC, PROLONG, ZERO, NHS, RMODE, GEN, SOR>), dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t launch_strip_t(StripKind k, int csw, int fsw, bool p, const StripLaunch &a, hipStream_t s,
-                                 int *w = nullptr)
+                                 int *w = nullptr, bool sor = false)
 {
+    if (sor) {
+        // over-relaxed fused finest passes: FP32 hierarchies, 4 or 5 sweeps
+        if (!std::is_same<T, float>::value) return hipErrorInvalidValue;
+        const bool zero = k == SK_FINE_ZERO;
+        if (k != SK_FINE && !zero) return hipErrorInvalidValue;
+        switch (fsw) {
+        case 4: return zero ? go<T, true, true, 8, RES_BOTH, false, true>(a, p, s, w)
+                            : go<T, true, false, 8, RES_BOTH, false, true>(a, p, s, w);
+        case 5: return zero ? go<T, true, true, 10, RES_BOTH, false, true>(a, p, s, w)
+                            : go<T, true, false, 10, RES_BOTH, false, true>(a, p, s, w);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (k) {
     case SK_FINE:
         switch (fsw) {
@@ -798,10 +824,10 @@ void strip_prepare(int csw, int fsw, bool fp64)
 }
 
 hipError_t launch_strip(StripKind k, int csw, int fsw, bool fp64, bool persistent, const StripLaunch &a,
-                        hipStream_t s)
+                        hipStream_t s, bool sor)
 {
-    return fp64 ? launch_strip_t<double>(k, csw, fsw, persistent, a, s)
-                : launch_strip_t<float>(k, csw, fsw, persistent, a, s);
+    return fp64 ? launch_strip_t<double>(k, csw, fsw, persistent, a, s, nullptr, sor)
+                : launch_strip_t<float>(k, csw, fsw, persistent, a, s, nullptr, sor);
 }
 
 }  // namespace gdf

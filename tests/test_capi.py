@@ -44,6 +44,12 @@ def _robust(v, **kw):
     return o
 
 
+def _sor(**kw):
+    o = gdf.make_opts(**kw)
+    o.sor = 1
+    return o
+
+
 def _zr(z0, z1):
     o = gdf.make_opts()
     o.z_begin, o.z_end = z0, z1
@@ -83,6 +89,13 @@ def _zr(z0, z1):
     (dict(opts=gdf.make_opts(launch_mode=-1)), gdf.GDF_EINVAL),
     (dict(ws=None), gdf.GDF_EINVAL),
     (dict(wsb=16), gdf.GDF_ENOMEM),
+    # over-relaxed sweeps: FP32 hierarchies, 4 or 5 fused sweeps, Neumann
+    (dict(opts=_sor(precision="fp64")), gdf.GDF_EUNSUPPORTED),
+    (dict(opts=_sor(nu=2, fine_sweeps=6)), gdf.GDF_EUNSUPPORTED),
+    (dict(opts=_sor(nu=1)), gdf.GDF_EUNSUPPORTED),            # (2 fused sweeps)
+    (dict(opts=_sor(), bc=1), gdf.GDF_EUNSUPPORTED),
+    (dict(opts=_sor(), wsb=16), gdf.GDF_ENOMEM),              # valid, fails on the workspace
+    (dict(opts=_sor(nu=1, fine_sweeps=4, precision="mixed"), wsb=16), gdf.GDF_ENOMEM),
     # the slices to solve: [z_begin, z_end) of the S = 4
     (dict(opts=_zr(1, 1)), gdf.GDF_EINVAL),
     (dict(opts=_zr(2, 1)), gdf.GDF_EINVAL),
