@@ -59,6 +59,9 @@ def _zr(z0, z1):
 @pytest.mark.parametrize("kw,status", [
     (dict(S=0), gdf.GDF_EINVAL),
     (dict(H=-1), gdf.GDF_EINVAL),
+    # the widest slice is 4194304 columns (32-bit byte offsets within a row band)
+    (dict(H=1, W=4194305, pr=4194305, ps=4194305), gdf.GDF_EINVAL),
+    (dict(H=1, W=4194304, pr=4194304, ps=4194304, wsb=16), gdf.GDF_ENOMEM),
     (dict(stack=None), gdf.GDF_EINVAL),
     (dict(f=None), gdf.GDF_EINVAL),
     (dict(alpha=0.0), gdf.GDF_EINVAL),
