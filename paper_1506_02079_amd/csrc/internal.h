@@ -87,7 +87,11 @@ template <> struct Buf<double> : BufBits<double, U2> {};
 
 // One multigrid level of one slice.  Arrays are row-major with row pitch
 // `pitch` (elements, even, >= W + 1 for odd W) so that a lane's two-column
-// vector access never leaves the allocation.
+// vector access never leaves the allocation.  Exception: the iterate of
+// level 0 (outside the periodic multigrid) stores each row by colour, pixel
+// (x, y) at element x / 2 of the half (x + y) & 1 of row y, each half pitch / 2
+// elements long: a red-black sweep pass then reads the one colour it needs as
+// contiguous runs.
 struct LevelDesc {
     void *u[2];      // iterate ping-pong buffers at this level
     void *b;         // right-hand side at this level (scaled units, see below)

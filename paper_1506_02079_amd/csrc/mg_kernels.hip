@@ -331,8 +331,29 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     const unsigned winB = (unsigned)(whi - wlo + 1) * rowB;
     const size_t wofs = (size_t)wlo * pitch;
     const Rsrc rb = make_rsrc((const SO *)L.b + wofs, winB);
-    const Rsrc ru = make_rsrc((const SO *)(in_sel ? L.u[1] : L.u[0]) + wofs, winB);
-    const Rsrc rw = make_rsrc((SO *)(out_sel ? L.u[1] : L.u[0]) + wofs, winB);
+    // The iterate: on level 0 each row stored by colour (see LevelDesc): pixel
+    // (x, y) at element x / 2 of the half (x + y) & 1 of row y, the halves
+    // pitch / 2 long.  A lane's two columns are element cx0 / 2 of both
+    // halves, and the black pixel it loads is in half 1.  Coarse levels keep
+    // rows of pixels.
+    constexpr bool RB = !GEN;
+    const SO *uin = (const SO *)(in_sel ? L.u[1] : L.u[0]);
+    SO *uout = (SO *)(out_sel ? L.u[1] : L.u[0]);
+    const Rsrc ru = make_rsrc(uin + wofs, winB), rw = make_rsrc(uout + wofs, winB);
+    const unsigned hB = RB ? (unsigned)(pitch >> 1) * ES : 0u;                   // half 1 of a row
+    const unsigned cxu = RB ? (unsigned)(cxl >> 1) * ES : cxb;                   // the lane's loads
+    // Level-0 stores go in lane pairs (cx0 / 2 even: the first of a pair, whose
+    // element is 8-byte aligned): the first stores its own and its right
+    // neighbour's column-0 values (row parity p: both of half p), the second
+    // its left neighbour's and its own column-1 values (both of half 1 - p), so
+    // each lane issues one 2-element store.  Owned columns start and end at pair
+    // boundaries (x0 and the owned width are multiples of 4); a pair is stored
+    // when its first column is owned (its second may lie in the row padding).
+    const bool pfirst = ((cx0 >> 1) & 1) == 0;
+    const int cxp = pfirst ? cx0 : cx0 - 2;   // the pair's first column
+    const bool own_pair = cxp >= 0 && cxp < W && cxp >= it.x0 && cxp < it.x0 + VW;
+    const unsigned vo_p0 = own_pair ? (pfirst ? 0u : hB) + (unsigned)(cxp >> 1) * ES : kNoLane;   // p = 0
+    const unsigned vo_p1 = own_pair ? (pfirst ? hB : 0u) + (unsigned)(cxp >> 1) * ES : kNoLane;   // p = 1
     const Rsrc rnone = make_rsrc(L.b, 0u);   // drops every store
     // (row offsets go through readfirstlane: a value the compiler happens to
     // compute in vector registers would otherwise get a per-lane loop around
@@ -342,6 +363,17 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
     };
     auto win_off = [=](int y) -> unsigned {   // y clamped into the window
         return (unsigned)uniform((min(max(y, wlo), whi) - wlo) * (int)rowB);
+    };
+    // store one row of the iterate (row parity p = y & 1, static): the lane's
+    // two columns, by colour and in lane pairs on level 0
+    auto store_u = [&](T v0, T v1, int p, bool keep, int y) {
+        if constexpr (RB) {
+            const T n0 = wave_shl1(v0), n1 = wave_shr1(v1);
+            Buf<PO>::st(pfirst ? SOt::pair(v0, n0) : SOt::pair(n1, v1), keep ? rw : rnone, p ? vo_p1 : vo_p0,
+                        win_off(y));
+        } else {
+            Buf<PO>::st(SOt::pair(v0, v1), keep ? rw : rnone, vo_own, win_off(y));
+        }
     };
     const int cwlo = max((wlo >> 1) - 1, 0), cwhi = min((whi >> 1) + 1, Hc - 1);
     const unsigned crowB = (unsigned)pitch_c * CS;
@@ -392,8 +424,15 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
         const unsigned so = row_off(yq);
         vb = Buf<PO>::ld(rb, cxb, so);
         if (!ZERO) {
-            if (RIN) vus = Buf<SO>::ld(ru, par ? cxb : cxb + ES, so);
-            else vu = Buf<PO>::ld(ru, cxb, so);
+            if constexpr (RB) {
+                // the black pixel (half 1); the guarded variant both halves, in
+                // colour order (the commit maps them to columns)
+                if (RIN) vus = Buf<SO>::ld(ru, cxu + hB, so);
+                else vu = SOt::pair((T)SOt::get(Buf<SO>::ld(ru, cxu, so)), (T)SOt::get(Buf<SO>::ld(ru, cxu + hB, so)));
+            } else {
+                if (RIN) vus = Buf<SO>::ld(ru, par ? cxb : cxb + ES, so);
+                else vu = Buf<PO>::ld(ru, cxb, so);
+            }
         }
         if (PROLONG) {
             const int m = yq >> 1;
@@ -478,8 +517,11 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                     const T wyr = y == H - 1 ? wyL : T(1);
                     b[k][0] = v0 ? (T)SOt::lo(qb[qs]) - fma(bsc * wx0, wyr, bsh) : T(0);
                     b[k][1] = v1 ? (T)SOt::hi(qb[qs]) - fma(bsc * wx1, wyr, bsh) : T(0);
-                    u[k][0] = v0 ? (ZERO ? T(0) : (T)SOt::lo(qu[qs])) + cor0 : T(0);
-                    u[k][1] = v1 ? (ZERO ? T(0) : (T)SOt::hi(qu[qs])) + cor1 : T(0);
+                    // (level 0: qu holds colours 0 and 1; column cx0 has colour k & 1)
+                    const T q0 = (T)(RB && (k & 1) ? SOt::hi(qu[qs]) : SOt::lo(qu[qs]));
+                    const T q1 = (T)(RB && (k & 1) ? SOt::lo(qu[qs]) : SOt::hi(qu[qs]));
+                    u[k][0] = v0 ? (ZERO ? T(0) : q0) + cor0 : T(0);
+                    u[k][1] = v1 ? (ZERO ? T(0) : q1) + cor1 : T(0);
                 }
             }
             // ------------------------------------------------ stages 1..NS
@@ -514,7 +556,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                             }
                         }
                         if (s == NHS)
-                            Buf<PO>::st(SOt::pair(u[sl][0], u[sl][1]), owned_row ? rw : rnone, vo_own, win_off(y));
+                            store_u(u[sl][0], u[sl][1], k & 1, owned_row, y);
                     } else {
                         const int lo = max(ybase + s, 0), hi = min(yend - s, H);
                         if (y >= lo && y < hi) {
@@ -541,8 +583,7 @@ __device__ __forceinline__ void strip_item(const StripLaunch &a, int item_id)
                                     u[sl][1] = (b[sl][1] + fma(rc.wy, h, wx1 * v)) * rc.i1;
                                 }
                             }
-                            if (s == NHS && owned_row)
-                                Buf<PO>::st(SOt::pair(u[sl][0], u[sl][1]), rw, vo_own, win_off(y));
+                            if (s == NHS && owned_row) store_u(u[sl][0], u[sl][1], k & 1, true, y);
                         }
                     }
                 } else if (RMODE != RES_NONE) {

@@ -64,6 +64,49 @@ __device__ __forceinline__ void load4(const TV *p, long long i, int nvalid, doub
     }
 }
 
+template <typename T> struct Vec2 { typedef T type __attribute__((ext_vector_type(2))); };
+
+// Level-0 iterates store each row by colour (see LevelDesc): pixel (x, y) at
+// element x / 2 of the half (x + y) & 1 of row y, the halves pitch / 2 long.
+template <typename S> struct RBView {
+    const S *u;
+    long long pitch, half;
+    __device__ RBView(const S *u_, long long pitch_) : u(u_), pitch(pitch_), half(pitch_ >> 1) {}
+    __device__ double at(int x, int y) const
+    {
+        return (double)u[(long long)y * pitch + ((x + y) & 1) * half + (x >> 1)];
+    }
+    // pixels x .. x + 3 of row y (x a multiple of 4); past nvalid: 0
+    __device__ void quad(int x, int y, int nvalid, double v[4]) const
+    {
+        using V2 = typename Vec2<S>::type;
+        if (nvalid <= 0) {
+            v[0] = v[1] = v[2] = v[3] = 0.0;
+            return;
+        }
+        const S *r0 = u + (long long)y * pitch + (x >> 1), *r1 = r0 + half;
+        const S *re = (y & 1) ? r1 : r0, *ro = (y & 1) ? r0 : r1;   // colours of pixels x and x + 1
+        if (nvalid >= 4) {
+            const V2 a = *reinterpret_cast<const V2 *>(re), b = *reinterpret_cast<const V2 *>(ro);
+            v[0] = (double)a.x;
+            v[1] = (double)b.x;
+            v[2] = (double)a.y;
+            v[3] = (double)b.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = k < nvalid ? (double)((k & 1) ? ro : re)[k >> 1] : 0.0;
+        }
+    }
+};
+// A row-major array (the FP64 iterates of the mixed scheme), same interface.
+template <typename S> struct RowView {
+    const S *u;
+    long long pitch;
+    __device__ RowView(const S *u_, long long pitch_) : u(u_), pitch(pitch_) {}
+    __device__ double at(int x, int y) const { return (double)u[(long long)y * pitch + x]; }
+    __device__ void quad(int x, int y, int nvalid, double v[4]) const { load4(u, (long long)y * pitch + x, nvalid, v); }
+};
+
 template <typename TV>
 __device__ __forceinline__ void store4(TV *p, long long i, int nvalid, const double v[4])
 {
@@ -381,23 +424,24 @@ __global__ __launch_bounds__(256) void finalize_quad_kernel(const TO *go, TF *f,
     const LevelDesc &L = levs[P.lev0];
     const int x = c.x, y = c.y, nv = c.row_in ? c.nvalid : 0;
     const double sg = P.alpha;
-    const T *u = static_cast<const T *>(L.u[st[c.si].cycles & 1]);
+    const RBView<T> u(static_cast<const T *>(L.u[st[c.si].cycles & 1]), L.pitch);
     const T *bu = static_cast<const T *>(L.b);
     // full correction = uoff (mean removed on load) + u + shift (constant-mode
     // correction); constants cancel in L, and b is used as stored
     const double shift = st[c.si].shift + st[c.si].uoff;
     const long long pu = L.pitch;
-    const long long p = (long long)min(y, P.H - 1) * pu + x;   // clamped row: loads stay in the slice
+    const int yc = min(y, P.H - 1);   // clamped row: loads stay in the slice
+    const long long p = (long long)yc * pu + x;
     double uc[4], un[4], us[4], bb[4];
-    load4(u, p, nv, uc);
+    u.quad(x, yc, nv, uc);
     load4(bu, p, nv, bb);
-    load4(u, p - pu, (y > 0) ? nv : 0, un);
-    load4(u, p + pu, (y < P.H - 1) ? nv : 0, us);
+    u.quad(x, yc - 1, (y > 0) ? nv : 0, un);
+    u.quad(x, yc + 1, (y < P.H - 1) ? nv : 0, us);
     // horizontal neighbours of the quad's first and last pixel
     double ul = row_prev(uc[3]), ur = row_next(uc[0]);
     const int g = threadIdx.x & 15;
-    if (nv > 0 && g == 0 && x > 0) ul = (double)u[p - 1];
-    if (nv > 0 && (g == 15 || nv < 4) && x + nv < P.W) ur = (double)u[p + nv];
+    if (nv > 0 && g == 0 && x > 0) ul = u.at(x - 1, yc);
+    if (nv > 0 && (g == 15 || nv < 4) && x + nv < P.W) ur = u.at(x + nv, yc);
     double srr = 0.0, o[4], fo[4];
     load4(go, P.off_go + (long long)y * P.pitch_go + x, nv, o);
 #pragma unroll
@@ -501,23 +545,50 @@ __global__ __launch_bounds__(64) void finalize_kernel(const TO *go_, TF *f_, con
     const int xe = min(max(lane == 0 ? X0 - 1 : X0 + kFinCols, 0), W - 1);
     // horizontal neighbour masks of the quad's first and last pixel
     const double ml = x > 0 ? 1.0 : 0.0, mr = x + 3 < W - 1 ? 1.0 : 0.0;
-    // arena rows are multiples of 64 elements: a lane's quad never leaves its row
-    auto urow = [&](int y) { return u + (long long)min(max(y, 0), H - 1) * pu; };
+    // The iterate stores each row by colour (LevelDesc): pixel (x, y) at
+    // element x / 2 of the half (x + y) & 1 of row y (halves pu / 2 long).  A
+    // lane's quad (xl a multiple of 4) is two pairs: pixels xl, xl + 2 of one
+    // colour and xl + 1, xl + 3 of the other.  Rows are clamped into the slice;
+    // arena rows are multiples of 64 elements, so a pair never leaves its half.
+    using VT2 = typename Vec2<T>::type;
+    const long long pu2 = pu >> 1;
+    auto uat = [&](int x, int y) -> T {
+        const int yc = min(max(y, 0), H - 1);
+        return u[(long long)yc * pu + ((x + yc) & 1) * pu2 + (x >> 1)];
+    };
+    auto uquad = [&](int y, VT2 &ev, VT2 &od) {   // the colours of pixels xl (ev) and xl + 1 (od)
+        const int yc = min(max(y, 0), H - 1);
+        const GDF_GLOBAL T *r0 = u + (long long)yc * pu + (xl >> 1);
+        ev = *reinterpret_cast<const GDF_GLOBAL VT2 *>((yc & 1) ? r0 + pu2 : r0);
+        od = *reinterpret_cast<const GDF_GLOBAL VT2 *>((yc & 1) ? r0 : r0 + pu2);
+    };
+    auto quad_d = [](const VT2 &ev, const VT2 &od, double v[4]) {
+        v[0] = (double)ev.x;
+        v[1] = (double)od.x;
+        v[2] = (double)ev.y;
+        v[3] = (double)od.y;
+    };
 
     double un[4], uc[4], us[4];
-    v4_to_d(*reinterpret_cast<const GDF_GLOBAL VT *>(urow(Y0 - 1) + xl), un);   // (row -1: masked below)
-    v4_to_d(*reinterpret_cast<const GDF_GLOBAL VT *>(urow(Y0) + xl), uc);
-    double ue = (double)urow(Y0)[xe];
+    {
+        VT2 ev, od;
+        uquad(Y0 - 1, ev, od);   // (row -1: masked below)
+        quad_d(ev, od, un);
+        uquad(Y0, ev, od);
+        quad_d(ev, od, uc);
+    }
+    double ue = (double)uat(xe, Y0);
 
     // queue: u of row y + 1 (and its outer element), b and g_o of row y; past
     // the block's last row the queue re-reads that row (cache hits, unused)
-    VT qu[Q], qb[Q];
+    VT2 qev[Q], qod[Q];
+    VT qb[Q];
     VO qo[Q];
     T qe[Q];
     auto issue = [&](int t, int slot) {
         const int y = min(Y0 + t, Y1 - 1);
-        qu[slot] = *reinterpret_cast<const GDF_GLOBAL VT *>(urow(y + 1) + xl);
-        qe[slot] = urow(y + 1)[xe];
+        uquad(y + 1, qev[slot], qod[slot]);
+        qe[slot] = uat(xe, y + 1);
         qb[slot] = *reinterpret_cast<const GDF_GLOBAL VT *>(bu + (long long)y * pu + xl);
         qo[slot] = *reinterpret_cast<const GDF_GLOBAL VO *>(go + off_go + (long long)y * pitch_go + xl);
     };
@@ -538,7 +609,7 @@ __global__ __launch_bounds__(64) void finalize_kernel(const TO *go_, TF *f_, con
             const double mu = y > 0 ? 1.0 : 0.0, md = y < H - 1 ? 1.0 : 0.0;   // uniform
             const double wrow = (t < n_rows && in) ? 1.0 : 0.0;
             double bb[4], o[4];
-            v4_to_d(qu[k], us);
+            quad_d(qev[k], qod[k], us);
             v4_to_d(qb[k], bb);
             v4_to_d(qo[k], o);
             const double ue_next = (double)qe[k];
@@ -658,20 +729,18 @@ hipError_t launch_prep_adjoint(bool fp64, const void *grad_f, const SliceIO *io_
 
 // The quad of level-0 values at row y and its four-neighbour sums: c (the
 // quad), and sum over in-slice neighbours q of (c_k - v_q).
-template <typename TL>
-__device__ __forceinline__ void quad_lap(const TL *v, long long pl, const QuadCtx &q, int nv, double c[4],
-                                         double lap[4])
+template <typename View>
+__device__ __forceinline__ void quad_lap(const View &v, const QuadCtx &q, int nv, double c[4], double lap[4])
 {
     const int x = q.x, y = min(q.y, q.P.H - 1), H = q.P.H, W = q.P.W;
-    const long long p = (long long)y * pl + x;
     double n[4], s[4];
-    load4(v, p, nv, c);
-    load4(v, p - pl, y > 0 ? nv : 0, n);
-    load4(v, p + pl, y < H - 1 ? nv : 0, s);
+    v.quad(x, y, nv, c);
+    v.quad(x, y - 1, y > 0 ? nv : 0, n);
+    v.quad(x, y + 1, y < H - 1 ? nv : 0, s);
     double l = row_prev(c[3]), r = row_next(c[0]);
     const int g = threadIdx.x & 15;
-    if (nv > 0 && g == 0 && x > 0) l = (double)v[p - 1];
-    if (nv > 0 && g == 15 && x + nv < W) r = (double)v[p + nv];
+    if (nv > 0 && g == 0 && x > 0) l = v.at(x - 1, y);
+    if (nv > 0 && g == 15 && x + nv < W) r = v.at(x + nv, y);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const double vl = k == 0 ? l : c[k - 1], vr = k == 3 ? r : c[k + 1];
@@ -686,15 +755,15 @@ __device__ __forceinline__ void quad_lap(const TL *v, long long pl, const QuadCt
 
 // lambda = A^{-1} grad_f (level-0 iterate): grad_gs = alpha lambda,
 // grad_go = L lambda, partials of lambda . (g_s - f).
-template <typename T, typename TL>
-__device__ __forceinline__ void adjoint_quad(const TL *lam, double shift, const T *gs, const T *f, T *ggs,
-                                             T *ggo, const QuadCtx &q, long long pl, double &sda)
+template <typename T, typename View>
+__device__ __forceinline__ void adjoint_quad(const View &lam, double shift, const T *gs, const T *f, T *ggs,
+                                             T *ggo, const QuadCtx &q, double &sda)
 {
     const SliceIO &P = q.P;
     const int nv = q.row_in ? q.nvalid : 0;
     const int y = min(q.y, P.H - 1);
     double lc[4], lap[4], g[4], fv[4], og[4], oo[4];
-    quad_lap(lam, pl, q, nv, lc, lap);   // L is blind to the constant shift
+    quad_lap(lam, q, nv, lc, lap);   // L is blind to the constant shift
     const long long fo = P.off_f + (long long)y * P.pitch_f + q.x;
     load4(gs, P.off_gs + (long long)y * P.pitch_gs + q.x, nv, g);
     load4(f, fo, nv, fv);
@@ -723,11 +792,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const T *gs, const T *f, T
     const int par = st[c.si].cycles & 1;
     double sda = 0.0;
     if (u64) {
-        adjoint_quad<T, double>(u64[par * n + c.si], 0.0, gs, f, ggs, ggo, c, L.pitch, sda);
+        adjoint_quad<T>(RowView<double>(u64[par * n + c.si], L.pitch), 0.0, gs, f, ggs, ggo, c, sda);
     } else {
-        const T *lam = static_cast<const T *>(L.u[par]);
+        const RBView<T> lam(static_cast<const T *>(L.u[par]), L.pitch);
         const double shift = st[c.si].shift + st[c.si].uoff;   // constant parts of lambda
-        adjoint_quad<T, T>(lam, shift, gs, f, ggs, ggo, c, L.pitch, sda);
+        adjoint_quad<T>(lam, shift, gs, f, ggs, ggo, c, sda);
     }
     const double t = block_sum(sda, red);
     if (threadIdx.x == 0) part_da[c.tile] = t;
@@ -766,7 +835,7 @@ __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a)
         const int nv = c.row_in ? c.nvalid : 0;
         const double *uin = a.u64[a.in_sel * a.n_slices + c.si];
         double *uout = a.u64[(a.in_sel ^ 1) * a.n_slices + c.si];
-        const float *e = static_cast<const float *>(L.u[a.e_sel]);
+        const RBView<float> e(static_cast<const float *>(L.u[a.e_sel]), pl);
         const long long p = (long long)y * pl + x;
         // new iterate on the quad and its four neighbour rows / columns
         double uc[4], un[4], us[4], t0[4], t1[4];
@@ -776,24 +845,24 @@ __global__ __launch_bounds__(256) void refine_kernel(RefineArgs a)
             for (int k = 0; k < 4; ++k) uc[k] = un[k] = us[k] = 0.0;
         } else {
             load4(uin, p, nv, uc);
-            load4(e, p, nv, t0);
+            e.quad(x, y, nv, t0);
             load4(uin, p - pl, y > 0 ? nv : 0, un);
-            load4(e, p - pl, y > 0 ? nv : 0, t1);
+            e.quad(x, y - 1, y > 0 ? nv : 0, t1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 uc[k] += t0[k];
                 un[k] += t1[k];
             }
             load4(uin, p + pl, y < H - 1 ? nv : 0, us);
-            load4(e, p + pl, y < H - 1 ? nv : 0, t1);
+            e.quad(x, y + 1, y < H - 1 ? nv : 0, t1);
 #pragma unroll
             for (int k = 0; k < 4; ++k) us[k] += t1[k];
         }
         ul = row_prev(uc[3]);
         ur = row_next(uc[0]);
         const int g = threadIdx.x & 15;
-        if (!a.first && nv > 0 && g == 0 && x > 0) ul = uin[p - 1] + (double)e[p - 1];
-        if (!a.first && nv > 0 && g == 15 && x + nv < W) ur = uin[p + nv] + (double)e[p + nv];
+        if (!a.first && nv > 0 && g == 0 && x > 0) ul = uin[p - 1] + e.at(x - 1, y);
+        if (!a.first && nv > 0 && g == 15 && x + nv < W) ur = uin[p + nv] + e.at(x + nv, y);
         double bv[4];
         if (a.rhs) {
             load4(static_cast<const TS *>(a.rhs), P.off_f + (long long)y * P.pitch_f + x, nv, bv);
