@@ -474,13 +474,13 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg (CPU baseline and error checks)")
     # defaults: the fastest settings measured for this workload on MI355X (a
     # sweep over nu, fine and coarse sweeps, band height and over-relaxation;
-    # --autotune runs the library's tuner instead)
-    # (--autotune runs the tuner instead, inside the untimed warm-up)
+    # --autotune runs the library's tuner instead, inside the untimed warm-up)
     ap.add_argument("--nu", type=int, default=2)
     ap.add_argument("--fine-sweeps", type=int, default=4)
     ap.add_argument("--sor", type=int, default=1, choices=[0, 1],
                     help="over-relaxed sweeps in the fused finest passes (opts.sor)")
-    ap.add_argument("--coarse-sweeps", type=int, default=3)
+    ap.add_argument("--coarse-sweeps", type=int, default=0,
+                    help="0: the library default (nu + 1, nu on strongly screened levels)")
     ap.add_argument("--tile-rows", type=int, default=128)
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, mixed-precision, adjoint and other forms")

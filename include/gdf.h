@@ -101,8 +101,11 @@ typedef struct {
                           0 = 2 nu.  Extra sweeps lower the residual at each check and can
                           save a whole V-cycle. */
     int coarse_sweeps; /* red-black sweeps before and after each coarse correction on the
-                          coarse levels: 1 .. 3; 0 = nu + 1 (nu for GDF_PREC_MIXED, whose
-                          inner solves run a fixed number of cycles).  The coarse levels are
+                          coarse levels: 1 .. 3, the same on every level; 0 = nu + 1, except
+                          nu on levels where every slice's screening coefficient
+                          (alpha 4^l on level l) is at least 0.05, where the extra sweep
+                          buys no cycles (nu everywhere for GDF_PREC_MIXED, whose inner
+                          solves run a fixed number of cycles).  The coarse levels are
                           small and latency-bound, so a third sweep there costs little and
                           lowers the residual of every cycle. */
     int robust;        /* fuse_stack: 1 = robust cross-slice averaging ("Extensions and
