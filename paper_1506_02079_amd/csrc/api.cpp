@@ -966,10 +966,12 @@ struct Run {
         gdf_status r;
         if ((r = coarse(fp64))) return r;
         const int nC = P.list_fine >= 0 ? P.lists[P.list_fine].count : 0;
-        // read u (unless zero) and b, write u; read the coarse correction and
-        // write the coarse right-hand side (a quarter per pixel each)
+        // read b and the black half of u (the red half is dead: the first
+        // half-sweep overwrites it unread; none of u when zero), write u; read
+        // the coarse correction and write the coarse right-hand side (a quarter
+        // per pixel each)
         if ((r = strip(P.list_fine, zero ? SK_FINE_ZERO : SK_FINE, (k - 1) & 1, k & 1, partf, fp64,
-                       zero ? PC_FINE0 : PC_FINE, (zero ? 2 : 3) * e + 0.5 * ce, slice_par)))
+                       zero ? PC_FINE0 : PC_FINE, (zero ? 2.0 : 2.5) * e + 0.5 * ce, slice_par)))
             return r;
         if ((r = strip(P.list_single, SK_SINGLE, (k - 1) & 1, k & 1, partf + nC, fp64, PC_COARSE, 3 * e, slice_par))) return r;
         return GDF_OK;
