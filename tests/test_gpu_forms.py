@@ -276,6 +276,28 @@ def test_coarse_sweep_counts(coarse_sweeps):
         assert np.abs(f1[j].cpu().numpy() - fr).max() <= 1e-3
 
 
+def test_default_coarse_sweeps_follow_screening():
+    # default coarse sweeps: nu + 1, and nu on levels whose alpha 4^l is at least
+    # 0.05.  At alpha 0.1 every coarse level qualifies, so the default run is the
+    # explicit two-sweep run bit for bit (and not the explicit three-sweep one:
+    # the plans are cached apart); at alpha 0.001 only the deep levels do.
+    stack = synth.make_stack(3, 300, 412, seed=67, ramp=True)
+    st = torch.from_numpy(stack).to(DEV)
+    fd, rd = gdf.fuse_stack(st, 0.1, tol=1e-6)
+    f2, r2 = gdf.fuse_stack(st, 0.1, tol=1e-6, coarse_sweeps=2)
+    f3, r3 = gdf.fuse_stack(st, 0.1, tol=1e-6, coarse_sweeps=3)
+    assert torch.equal(fd, f2)
+    assert [r["vcycles"] for r in rd] == [r["vcycles"] for r in r2]
+    assert not torch.equal(fd, f3)
+    for a in (0.1, 0.001):
+        f1, r1, gsm = gdf.fuse_stack(st, a, tol=1e-6, return_smooth=True)
+        assert all(r["rel_residual"] <= 1e-6 and r["status"] == gdf.GDF_OK for r in r1)
+        g = gsm.cpu().numpy().astype(np.float64)
+        for j in (0, 2):
+            fr = oracle.solve(g[j], stack[j].astype(np.float64), a, tol=1e-11)
+            assert np.abs(f1[j].cpu().numpy() - fr).max() <= 1e-3
+
+
 @pytest.mark.parametrize("nu,fine_sweeps", [(2, 5), (2, 6), (1, 3), (1, 4)])
 def test_fused_pass_sweep_counts(nu, fine_sweeps):
     # more sweeps in the fused finest pass: same solution, fewer or equal cycles
