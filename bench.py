@@ -481,7 +481,8 @@ def main():
                     help="over-relaxed sweeps in the fused finest passes (opts.sor)")
     ap.add_argument("--coarse-sweeps", type=int, default=0,
                     help="0: the library default (nu + 1, nu on strongly screened levels)")
-    ap.add_argument("--tile-rows", type=int, default=128)
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="rows per level-0 work item; 0: the library default (80, fewer for small batches)")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the batched, mixed-precision, adjoint and other forms")
     ap.add_argument("--forms", default="", help="comma-separated subset of the forms to run (default: all)")

@@ -91,7 +91,8 @@ typedef struct {
     int out_dtype;     /* GDF_F32 or GDF_F64 for f; 0 = F32 for FP32, F64 otherwise */
     int use_graph;     /* 1: record the whole V-cycle schedule once as a hipGraph and
                           replay it, with per-slice convergence flags on the device */
-    int tile_rows;     /* rows per strip work item (even, >= 16); 0 = tuned default */
+    int tile_rows;     /* rows per level-0 strip work item (even, >= 16); 0 = 80, halved
+                          (down to 16) for batches too small to fill the GPU twice over */
     int inner_cycles;  /* MIXED: FP32 V-cycles per refinement step (default 3) */
     int launch_mode;   /* gdf_launch_mode for the multigrid passes (default GDF_LAUNCH_GRID) */
     int autotune;      /* 1: pick nu, fine_sweeps, coarse_sweeps, tile_rows and launch_mode by timing

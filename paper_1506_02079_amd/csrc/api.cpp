@@ -253,11 +253,12 @@ struct Plan {
     size_t off_partf, off_partd, off_partd2, off_partd3, off_gscopy, off_arena, arena_bytes, total;
 };
 
-// Rows per work item of a list (TH): 128, halved (down to 16) while the list
-// would have fewer than two items per wave the device holds at once.  Taller
-// items waste less on halo rows; more items keep every SIMD busy to the end of
-// the pass.  (Measured on 64 x 2048^2 stacks and on batches of uneven slices:
-// 128 rows beat 256 and taller on level 0.)
+// Rows per work item of a list (TH): 80 on level 0, halved (down to 16) while
+// the list would have fewer than two items per wave the device holds at once.
+// Taller items waste less on halo rows; more items keep every SIMD busy to the
+// end of the pass.  (Measured on 64 x 2048^2 stacks at alpha 0.001, 0.01 and
+// 0.1: 80 rows beat 64, 72, 88, 96, 112, 128 and taller on level 0, by 1-4% of
+// the whole step against 128.)
 int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripKind kind, int G, int VW, int csw)
 {
     if (level == 0 && P.o.tile_rows) return P.o.tile_rows;
@@ -270,7 +271,7 @@ int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripK
     // items (each re-walking its halo rows) lose to fewer taller ones (on the
     // 64 x 2048^2 stack 16-row items on levels 2 and 3 make the coarse levels
     // 18% slower, and so do 128-row items everywhere)
-    int th = 128;
+    int th = 80;
     double want = 2.0 * slots;   // level 0: items that fill the GPU twice over
     if (level > 0) {
         int hmax = 0;
@@ -278,7 +279,7 @@ int choose_rows(const Plan &P, const std::vector<int> &slices, int level, StripK
         th = hmax <= 256 ? 32 : 64;
         want = slots / 16.0;
     }
-    for (; th > 16; th /= 2) {
+    for (; th / 2 >= 16; th /= 2) {
         double items = 0.0;
         for (int s : slices) {
             const int H = P.g[s].h[level], W = P.g[s].w[level];
@@ -1301,11 +1302,13 @@ gdf_status solve_body(Run &R, const SolveIO &x)
 // ------------------------------------------------------------- autotuning
 //
 // A call with opts.autotune = 1 times whole solves of its own batch under
-// candidate settings and keeps the fastest: first the sweep count nu per
-// smoothing step (fewer sweeps per pass against more V-cycles), then the rows
-// per strip work item (tile_rows: halo overhead against the number of items
-// in flight), then the launch mode (one wave per item against a persistent
-// grid).  Fields the caller set explicitly are not tuned.  The result is
+// candidate settings and keeps the fastest, one field at a time: first the
+// sweep count nu per smoothing step (fewer sweeps per pass against more
+// V-cycles), then, in two rounds, the fused and coarse sweep counts (plain or
+// over-relaxed), the rows per strip work item (tile_rows: halo overhead
+// against the number of items in flight) and the launch mode (one wave per
+// item against a persistent grid).  Fields the caller set explicitly are not
+// tuned.  The result is
 // cached per batch signature (sizes, screening weights, tolerances, precision
 // and dtypes; not the data or the pointers) until gdf_release.
 
@@ -1411,29 +1414,35 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
         cur.launch_mode = ls[0];
         double tcur = timeit(cur);
         auto try_field = [&](int gdf_solve_opts::*field, const std::vector<int> &vals) {
-            for (size_t i = 1; i < vals.size(); ++i) {
+            for (int v : vals) {
+                if (cur.*field == v) continue;
                 gdf_solve_opts c = cur;
-                c.*field = vals[i];
+                c.*field = v;
                 const double tc = timeit(c);
                 if (tc < tcur) { cur = c; tcur = tc; }
             }
         };
         try_field(&gdf_solve_opts::nu, nus);
-        try_field(&gdf_solve_opts::fine_sweeps, tune_fine_sweeps(base, cur.nu));
-        // over-relaxed sweeps, with the sweep counts they are built for (fewer
-        // over-relaxed sweeps can match more plain ones, so both change together)
-        if (!base.sor && base.precision != GDF_PREC_FP64)
-            for (int fs : {4, 5}) {
-                if (fs < 2 * cur.nu || fs > 2 * cur.nu + 2 || (base.fine_sweeps && base.fine_sweeps != fs)) continue;
-                gdf_solve_opts c = cur;
-                c.sor = 1;
-                c.fine_sweeps = fs;
-                const double tc = timeit(c);
-                if (tc < tcur) { cur = c; tcur = tc; }
-            }
-        try_field(&gdf_solve_opts::coarse_sweeps, tune_coarse_sweeps(base, cur.nu));
-        try_field(&gdf_solve_opts::tile_rows, tiles);
-        try_field(&gdf_solve_opts::launch_mode, ls);
+        // two rounds over the other fields: the best sweep counts depend on the
+        // item height and launch mode picked after them, and back
+        for (int round = 0; round < 2; ++round) {
+            try_field(&gdf_solve_opts::fine_sweeps, tune_fine_sweeps(base, cur.nu));
+            // over-relaxed sweeps, with the sweep counts they are built for (fewer
+            // over-relaxed sweeps can match more plain ones, so both change together)
+            if (!base.sor && base.precision != GDF_PREC_FP64)
+                for (int fs : {4, 5}) {
+                    if (fs < 2 * cur.nu || fs > 2 * cur.nu + 2 || (base.fine_sweeps && base.fine_sweeps != fs)) continue;
+                    if (cur.sor && cur.fine_sweeps == fs) continue;
+                    gdf_solve_opts c = cur;
+                    c.sor = 1;
+                    c.fine_sweeps = fs;
+                    const double tc = timeit(c);
+                    if (tc < tcur) { cur = c; tcur = tc; }
+                }
+            try_field(&gdf_solve_opts::coarse_sweeps, tune_coarse_sweeps(base, cur.nu));
+            try_field(&gdf_solve_opts::tile_rows, tiles);
+            try_field(&gdf_solve_opts::launch_mode, ls);
+        }
         if (!(tcur < inf)) return call(&best);   // no candidate ran cleanly: report the plain call
         t = Tuned{cur.nu, cur.fine_sweeps, cur.coarse_sweeps, cur.tile_rows, cur.launch_mode, cur.sor};
         std::lock_guard<std::mutex> lk(g_tune_mu);
