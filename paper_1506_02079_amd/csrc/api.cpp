@@ -1302,13 +1302,13 @@ gdf_status solve_body(Run &R, const SolveIO &x)
 // ------------------------------------------------------------- autotuning
 //
 // A call with opts.autotune = 1 times whole solves of its own batch under
-// candidate settings and keeps the fastest, one field at a time: first the
-// sweep count nu per smoothing step (fewer sweeps per pass against more
-// V-cycles), then, in two rounds, the fused and coarse sweep counts (plain or
-// over-relaxed), the rows per strip work item (tile_rows: halo overhead
-// against the number of items in flight) and the launch mode (one wave per
-// item against a persistent grid).  Fields the caller set explicitly are not
-// tuned.  The result is
+// candidate settings and keeps the fastest: first the sweep count nu per
+// smoothing step (fewer sweeps per pass against more V-cycles), then every
+// pairing of the fused-pass sweeps (plain or over-relaxed) with the rows per
+// strip work item (tile_rows: halo overhead against the number of items in
+// flight), then the coarse sweeps, the launch mode (one wave per item against
+// a persistent grid) and the rows once more.  Fields the caller set
+// explicitly are not tuned.  The result is
 // cached per batch signature (sizes, screening weights, tolerances, precision
 // and dtypes; not the data or the pointers) until gdf_release.
 
@@ -1423,26 +1423,30 @@ gdf_status autotuned(const std::vector<unsigned long long> &key, const gdf_solve
             }
         };
         try_field(&gdf_solve_opts::nu, nus);
-        // two rounds over the other fields: the best sweep counts depend on the
-        // item height and launch mode picked after them, and back
-        for (int round = 0; round < 2; ++round) {
-            try_field(&gdf_solve_opts::fine_sweeps, tune_fine_sweeps(base, cur.nu));
-            // over-relaxed sweeps, with the sweep counts they are built for (fewer
-            // over-relaxed sweeps can match more plain ones, so both change together)
-            if (!base.sor && base.precision != GDF_PREC_FP64)
-                for (int fs : {4, 5}) {
-                    if (fs < 2 * cur.nu || fs > 2 * cur.nu + 2 || (base.fine_sweeps && base.fine_sweeps != fs)) continue;
-                    if (cur.sor && cur.fine_sweeps == fs) continue;
-                    gdf_solve_opts c = cur;
-                    c.sor = 1;
-                    c.fine_sweeps = fs;
-                    const double tc = timeit(c);
-                    if (tc < tcur) { cur = c; tcur = tc; }
-                }
-            try_field(&gdf_solve_opts::coarse_sweeps, tune_coarse_sweeps(base, cur.nu));
-            try_field(&gdf_solve_opts::tile_rows, tiles);
-            try_field(&gdf_solve_opts::launch_mode, ls);
-        }
+        // the fused-pass sweeps (plain counts, then 4 or 5 over-relaxed ones:
+        // fewer over-relaxed sweeps can match more plain ones, so count and
+        // mode change together) jointly with the item height: the best of each
+        // depends on the other, and one field at a time stops short of it
+        struct Sweeps { int fs, sor; };
+        std::vector<Sweeps> sw;
+        for (int fs : tune_fine_sweeps(base, cur.nu)) sw.push_back({fs, base.sor});
+        if (!base.sor && base.precision != GDF_PREC_FP64)
+            for (int fs : {4, 5})
+                if (fs >= 2 * cur.nu && fs <= 2 * cur.nu + 2 && (!base.fine_sweeps || base.fine_sweeps == fs))
+                    sw.push_back({fs, 1});
+        for (const Sweeps &w : sw)
+            for (int tr : tiles) {
+                if (w.fs == cur.fine_sweeps && w.sor == cur.sor && tr == cur.tile_rows) continue;
+                gdf_solve_opts c = cur;
+                c.fine_sweeps = w.fs;
+                c.sor = w.sor;
+                c.tile_rows = tr;
+                const double tc = timeit(c);
+                if (tc < tcur) { cur = c; tcur = tc; }
+            }
+        try_field(&gdf_solve_opts::coarse_sweeps, tune_coarse_sweeps(base, cur.nu));
+        try_field(&gdf_solve_opts::launch_mode, ls);
+        try_field(&gdf_solve_opts::tile_rows, tiles);   // (under the launch mode picked)
         if (!(tcur < inf)) return call(&best);   // no candidate ran cleanly: report the plain call
         t = Tuned{cur.nu, cur.fine_sweeps, cur.coarse_sweeps, cur.tile_rows, cur.launch_mode, cur.sor};
         std::lock_guard<std::mutex> lk(g_tune_mu);
